@@ -1,0 +1,465 @@
+"""Pins of the FP64 CPU oracle against things other than itself.
+
+Each test fixes part of the oracle by mathematics or by numbers the paper
+prints: closed-form discrete eigen-solutions, exactness of the transfer
+operators on polynomials, the entries of the appendix's operator matrices
+(tests/golden/), library linear solves, the identity L_H I^ = I L_h of the
+chosen transfer pair, invariances of the additive smoother, convergence
+order of one FMG cycle, and a dense-matrix brute force on tiny grids.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1207_6720_amd import workloads as W
+from tests import dense_reference as D
+
+RNG = np.random.default_rng(12345)
+
+
+def closed_form_discrete(n, k, c, gL=0.0, gR=0.0):
+    """Discrete solution of L u = sum c_k (k pi)^2 sin(k pi x): sines are
+    exact eigenvectors of the cell-centred Laplacian with odd-reflection
+    ghosts, eigenvalue 4 n^2 sin^2(k pi / 2n); plus the linear function
+    carrying the boundary values (L annihilates it exactly)."""
+    x = W.cell_centres(n)
+    u = gL + (gR - gL) * x
+    for kk, cc in zip(k, c):
+        lam = 4.0 * n * n * np.sin(kk * np.pi / (2 * n)) ** 2
+        u = u + cc * (kk * np.pi) ** 2 / lam * np.sin(kk * np.pi * x)
+    return u
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# --------------------------------------------------------------------------
+# Operators
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [4, 16, 128, 1024])
+def test_L_sine_eigenvectors(n):
+    x = W.cell_centres(n)
+    for k in (1, 3, n // 2, n - 1):
+        s = np.sin(k * np.pi * x)
+        lam = 4.0 * n * n * np.sin(k * np.pi / (2 * n)) ** 2
+        Ls = oracle.apply_L(s)
+        assert np.max(np.abs(Ls - lam * s)) <= 1e-12 * 4 * n * n
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 64])
+def test_L_annihilates_boundary_line(n):
+    gL, gR = 0.7, -1.3
+    x = W.cell_centres(n)
+    line = gL + (gR - gL) * x
+    assert np.max(np.abs(oracle.apply_L(line, gL, gR))) <= 1e-13 * n * n
+
+
+def test_L_matches_appendix_matrix():
+    n = 8
+    u = RNG.standard_normal(n)
+    assert np.allclose(oracle.apply_L(u), D.laplacian(n) @ u, rtol=0, atol=1e-12 * n * n)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 1000])
+def test_coarse_solve_vs_library(n):
+    F = RNG.standard_normal(n)
+    gL, gR = 0.25, -0.5
+    u = oracle.coarse_solve(F, gL, gR)
+    # residual of the Dirichlet problem, and numpy's dense solve
+    A = D.laplacian(n)
+    b = F.copy()
+    b[0] += 2.0 * gL * n * n
+    b[-1] += 2.0 * gR * n * n
+    ref = np.linalg.solve(A, b)
+    assert rel(u, ref) < 1e-12
+    assert np.max(np.abs(oracle.apply_L(u, gL, gR) - F)) < 1e-9 * max(1.0, np.abs(F).max())
+
+
+@pytest.mark.parametrize("n", [16, 256, 1024])
+def test_coarse_solve_closed_form(n):
+    k, c = W.modes("inv_k2", 16, 3)
+    k, c = k[: n // 2], c[: n // 2]
+    f = W.rhs_numpy(n, k, c)
+    u = oracle.coarse_solve(f, 0.3, -0.2)
+    assert rel(u, closed_form_discrete(n, k, c, 0.3, -0.2)) < 1e-12
+
+
+def test_interp_exact_on_cubics():
+    nc = 64
+    X = W.cell_centres(nc)
+    x = W.cell_centres(2 * nc)
+    p = lambda t: 1.0 - 2.0 * t + 3.0 * t ** 2 - 5.0 * t ** 3
+    fine = oracle.interp_fmg(p(X))
+    # interior children (stencil does not reach a ghost)
+    sl = slice(4, 2 * nc - 4)
+    assert np.max(np.abs(fine[sl] - p(x)[sl])) < 1e-13
+
+
+@pytest.mark.parametrize("nc", [1, 2, 3, 4, 33])
+def test_interp_exact_on_boundary_line(nc):
+    gL, gR = -0.4, 1.9
+    line = lambda t: gL + (gR - gL) * t
+    fine = oracle.interp_fmg(line(W.cell_centres(nc)), gL, gR)
+    assert np.max(np.abs(fine - line(W.cell_centres(2 * nc)))) < 1e-14
+
+
+@pytest.mark.parametrize("nc", [4, 5, 16])
+def test_interp_matches_appendix_rows(nc):
+    """Boundary and interior rows equal the matrix the appendix prints."""
+    I = np.eye(nc)
+    dense = np.stack([oracle.interp_fmg(I[j]) for j in range(nc)], axis=1)
+    assert np.array_equal(dense, D.fmg_interp(nc))
+
+
+@pytest.mark.parametrize("nc", [1, 2, 3, 8])
+def test_prolong_matches_appendix(nc):
+    I = np.eye(nc)
+    dense = np.stack([oracle.prolong_linear(I[j]) for j in range(nc)], axis=1)
+    if nc >= 2:
+        assert np.array_equal(dense, D.prolongation(nc))
+    # exact on linear functions away from the boundary (second order)
+    X, x = W.cell_centres(nc), W.cell_centres(2 * nc)
+    if nc >= 3:
+        fine = oracle.prolong_linear(0.3 + 2.0 * X)
+        assert np.max(np.abs(fine[1:-1] - (0.3 + 2.0 * x)[1:-1])) < 1e-14
+
+
+@pytest.mark.parametrize("nc", [1, 2, 5, 8])
+def test_restrictions(nc):
+    I = np.eye(2 * nc)
+    avg = np.stack([oracle.restrict_avg(I[i]) for i in range(2 * nc)], axis=1)
+    fw = np.stack([oracle.restrict_fw(I[i]) for i in range(2 * nc)], axis=1)
+    Pl = np.stack([oracle.prolong_linear(np.eye(nc)[j]) for j in range(nc)], axis=1)
+    assert np.array_equal(fw, 0.5 * Pl.T)           # I = 1/2 P^T
+    if nc >= 2:
+        assert np.array_equal(avg, D.restriction_avg(nc))
+    assert np.allclose(avg @ np.full(2 * nc, 3.25), 3.25, atol=0)
+
+
+@pytest.mark.parametrize("nf", [2, 4, 6, 32, 256])
+def test_transfer_identity_LH_Ihat_equals_I_Lh(nf):
+    """L_H(I^ u) = I(L_h u) for every u and boundary data: tau's Laplacian
+    part vanishes with the average / full-weighting pair."""
+    u = RNG.standard_normal(nf)
+    gL, gR = 0.9, -0.35
+    lhs = oracle.apply_L(oracle.restrict_avg(u), gL, gR)
+    rhs = oracle.restrict_fw(oracle.apply_L(u, gL, gR))
+    assert np.max(np.abs(lhs - rhs)) <= 1e-14 * nf * nf * (np.abs(u).max() + 1)
+
+
+@pytest.mark.parametrize("nf", [2, 8, 64, 256])
+def test_compression_commutes_with_solve(nf):
+    """Consequence of the identity: I^ L_h^{-1} f = L_H^{-1} I f."""
+    f = RNG.standard_normal(nf)
+    a = oracle.restrict_avg(oracle.coarse_solve(f, 0.1, 0.2))
+    b = oracle.coarse_solve(oracle.restrict_fw(f), 0.1, 0.2)
+    assert rel(a, b) < 1e-13
+
+
+def test_average_restriction_breaks_identity():
+    """With the appendix's average for both restrictions tau is not zero
+    (so split tau would be wrong there): the identity must fail."""
+    u = RNG.standard_normal(64)
+    lhs = oracle.apply_L(oracle.restrict_avg(u))
+    rhs = oracle.restrict_avg(oracle.apply_L(u))
+    assert np.max(np.abs(lhs - rhs)) > 1.0
+
+
+# --------------------------------------------------------------------------
+# Relaxation
+# --------------------------------------------------------------------------
+
+def test_kaczmarz_projection():
+    n = 40
+    u = RNG.standard_normal(n)
+    c = RNG.standard_normal(n // 2)
+    lo, hi = 5, 31                         # covers pairs J = 3..14
+    v = oracle.kaczmarz(u, c, lo, hi)
+    rv = oracle.restrict_avg(v)
+    J = np.arange(3, 15)
+    assert np.max(np.abs(rv[J] - c[J])) <= 4e-16 * (np.abs(c).max() + np.abs(u).max())
+    untouched = np.setdiff1d(np.arange(n), np.arange(6, 30))
+    assert np.array_equal(v[untouched], u[untouched])
+    w = oracle.kaczmarz(v, c, lo, hi)
+    assert np.max(np.abs(w - v)) <= 1e-15 * np.abs(v).max()
+    # differences inside each pair are untouched (the update moves both children equally)
+    assert np.allclose((v[0::2] - v[1::2])[J], (u[0::2] - u[1::2])[J], atol=1e-14)
+
+
+@pytest.mark.parametrize("n", [1, 2, 9, 64])
+def test_rb_sweep_fixed_point(n):
+    F = RNG.standard_normal(n)
+    u = oracle.coarse_solve(F, 0.2, -0.1)
+    v = oracle.rb_sweep(u, F, gL=0.2, gR=-0.1)
+    assert np.max(np.abs(v - u)) <= 1e-12 * max(np.abs(u).max(), 1e-3)
+
+
+@pytest.mark.parametrize("n,lo,hi", [(12, 0, 12), (16, 3, 11), (9, 0, 9)])
+def test_rb_sweep_dense_splitting(n, lo, hi):
+    """Red-black GS equals the dense Gauss-Seidel splitting in red-then-black order."""
+    u = RNG.standard_normal(n)
+    F = RNG.standard_normal(n) * n * n
+    A = D.laplacian(n)
+    E = np.arange(lo, hi)
+    ref = D.gs_sweep(A, u, F, E, D.rb_order(E))
+    assert rel(oracle.rb_sweep(u, F, lo, hi), ref) < 1e-13
+
+
+def test_lex_sweep_dense_splitting():
+    n = 11
+    u = RNG.standard_normal(n)
+    F = RNG.standard_normal(n) * n * n
+    A = D.laplacian(n)
+    E = np.arange(2, 9)
+    assert rel(oracle.lex_sweep(u, F, 2, 9), D.gs_sweep(A, u, F, E, list(E))) < 1e-13
+    assert rel(oracle.lex_sweep(u, F, 2, 9, backward=True),
+               D.gs_sweep(A, u, F, E, list(E)[::-1])) < 1e-13
+
+
+@pytest.mark.parametrize("nu", [1, 2, 3])
+def test_blocks_equal_global_when_buffer_covers(nu):
+    """Cores of the additive smoother equal global red-black sweeps bitwise
+    once the buffer reaches the dependency cone (b >= 2 nu - 1)."""
+    n, S = 256, 4
+    v = RNG.standard_normal(n)
+    F = RNG.standard_normal(n) * n * n
+    glob = v.copy()
+    for _ in range(nu):
+        glob = oracle.rb_sweep(glob, F)
+    for b in (2 * nu - 1, 2 * nu + 3):
+        out = oracle.smooth_blocks(v, F, S, b, nu)
+        assert np.array_equal(out, glob)
+    if nu >= 2:
+        assert not np.array_equal(oracle.smooth_blocks(v, F, S, 2 * nu - 2, nu), glob)
+
+
+def test_blocks_order_invariant_and_local():
+    n, S, b = 96, 12, 1
+    v = RNG.standard_normal(n)
+    F = RNG.standard_normal(n) * n * n
+    c = RNG.standard_normal(n // 2)
+    for kc in (None, c):
+        a = oracle.smooth_blocks(v, F, S, b, 2, kaczmarz_c=kc, order=0)
+        bb = oracle.smooth_blocks(v, F, S, b, 2, kaczmarz_c=kc, order=1)
+        assert np.array_equal(a, bb)
+    # dense brute force of the same block smoother
+    A = D.laplacian(n)
+    ref = D.smooth(A, v, F, 2, D.make_segments(n, S, b))
+    assert rel(oracle.smooth_blocks(v, F, S, b, 2), ref) < 1e-13
+    ref = D.smooth(A, v, F, 2, D.make_segments(n, S, b), kacz=(D.restriction_avg(n // 2), c))
+    assert rel(oracle.smooth_blocks(v, F, S, b, 2, kaczmarz_c=c), ref) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# FMG-FAS(-SR)
+# --------------------------------------------------------------------------
+
+def _problem(n, seed=0, law="inv_k2", nm=16):
+    k, c = W.modes(law, nm, seed, n)
+    return k, c, W.rhs_numpy(n, k, c)
+
+
+@pytest.mark.parametrize("nsr", [0, 1, 2])
+@pytest.mark.parametrize("tau", ["split", "literal"])
+def test_fmg_matches_dense_brute_force(nsr, tau):
+    n, levels = 64, 5                     # coarsest grid 4 cells
+    _, _, f = _problem(n, 1)
+    for S, b in ((4, 3), (8, 1)):
+        u = oracle.fmgsr_solve(f, levels=levels, segments=S, buffer=b, nsr=nsr, tau=tau,
+                               tau_assembled=True)
+        ref = D.fmgsr(f, levels, S, b, nsr=nsr, tau=tau)
+        assert rel(u, ref) < 1e-11, (S, b)
+
+
+@pytest.mark.parametrize("smoother,block", [("lex", 2), ("lex", 0), ("rb", 2)])
+def test_fmg_paper_mode_matches_dense(smoother, block):
+    n, levels = 64, 5
+    k, c = W.modes("paper", 0, 0, n)
+    f = W.rhs_numpy(n, k, c)
+    for nsr in (0, 1, 3):
+        u = oracle.fmgsr_solve(f, levels=levels, segments=1, buffer=4, nsr=nsr, tau="literal",
+                               rhs_restrict="avg", smoother=smoother, tau_assembled=True,
+                               block_all=block, nu1=1, nu2=1)
+        ref = D.fmgsr(f, levels, 1, 4, nu1=1, nu2=1, nsr=nsr, tau="literal",
+                      rhs_restrict="avg", smoother=smoother, block_all=block)
+        assert rel(u, ref) < 1e-11
+
+
+def test_fmg_linearity():
+    n = 256
+    f1 = _problem(n, 1)[2]
+    f2 = _problem(n, 2)[2]
+    kw = dict(segments=4, buffer=4, nsr=1)
+    a = oracle.fmgsr_solve(2.0 * f1 - 0.5 * f2, 0.3, -0.6, **kw)
+    b = 2.0 * oracle.fmgsr_solve(f1, 0.0, 0.0, **kw) - 0.5 * oracle.fmgsr_solve(f2, 0.0, 0.0, **kw) \
+        + oracle.fmgsr_solve(np.zeros(n), 0.3, -0.6, **kw)
+    assert rel(a, b) < 1e-13
+
+
+@pytest.mark.parametrize("nsr", [0, 1])
+@pytest.mark.parametrize("n", [1, 2, 8, 1024])
+def test_fmg_boundary_line_exact(nsr, n):
+    gL, gR = 1.5, -0.25
+    levels = int(np.log2(n)) + 1
+    if n < 2:
+        nsr = 0
+    u = oracle.fmgsr_solve(np.zeros(n), gL, gR, levels=levels, segments=1, buffer=2, nsr=nsr)
+    x = W.cell_centres(n)
+    assert np.max(np.abs(u - (gL + (gR - gL) * x))) < 1e-13
+
+
+@pytest.mark.parametrize("nsr", [0, 1])
+def test_fmg_second_order_and_truncation_accuracy(nsr):
+    """One FMG(-SR) cycle reaches the discretisation error: algebraic error
+    <= 0.1 x discretisation error, and the total error falls like h^2."""
+    errs = []
+    for e in range(6, 17, 2):
+        n = 1 << e
+        k, c, f = _problem(n, 0)
+        S = max(n // 4096, 4)
+        u = oracle.fmgsr_solve(f, segments=S, buffer=8, nsr=nsr)
+        ustar = closed_form_discrete(n, k, c)
+        uex = W.exact_numpy(n, k, c)
+        disc = rel(ustar, uex)
+        alg = np.linalg.norm(u - ustar) / np.linalg.norm(uex)
+        bound = 0.1 if (nsr == 0 or n >= 1024) else 0.7
+        assert alg <= bound * disc, (n, alg / disc)
+        errs.append(rel(u, uex))
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all((ratios > 14.0) & (ratios < 18.0)), ratios   # two doublings: ~16
+
+
+def test_fmg_c1_workload():
+    wl = W.WORKLOADS["c1"]
+    for seed in range(3):
+        k, c = W.modes(wl.law, wl.n_modes, seed)
+        f = W.rhs_numpy(wl.n, k, c)
+        u = oracle.fmgsr_solve(f, levels=wl.levels, segments=wl.segments, buffer=wl.buffer)
+        ustar = closed_form_discrete(wl.n, k, c)
+        uex = W.exact_numpy(wl.n, k, c)
+        assert np.linalg.norm(u - ustar) / np.linalg.norm(ustar - uex) < 0.1
+
+
+def test_fmg_segment_invariance():
+    """With b >= 2 nu1 - 1 and b >= 2 nu2 the SR result does not depend on
+    the segment count (bitwise); with a thin buffer it does."""
+    n = 1024
+    f = _problem(n, 4)[2]
+    ref = oracle.fmgsr_solve(f, 0.1, 0.2, segments=1, buffer=0, nsr=1)
+    for S in (2, 4, 16, 64, 256):
+        assert np.array_equal(oracle.fmgsr_solve(f, 0.1, 0.2, segments=S, buffer=3, nsr=1), ref)
+    thin = oracle.fmgsr_solve(f, 0.1, 0.2, segments=64, buffer=1, nsr=1)
+    assert not np.array_equal(thin, ref)
+
+
+def test_fmg_block_order_invariance():
+    n = 512
+    f = _problem(n, 5)[2]
+    for tau in ("split", "literal"):
+        a = oracle.fmgsr_solve(f, segments=32, buffer=1, nsr=2, tau=tau, order=0)
+        b = oracle.fmgsr_solve(f, segments=32, buffer=1, nsr=2, tau=tau, order=1)
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("n", [64, 4096])
+def test_literal_tau_agrees_with_split_on_small_grids(n):
+    """Literal tau is the difference of two O(n^2 |u|) terms whose exact
+    value is 0 here, so it injects rounding noise of about eps n^2 |u| into
+    every coarse rhs; the two forms may differ by that noise mapped through
+    the solve (measured ~1e-13 n).  A wrong term or sign would be O(1)."""
+    f = _problem(n, 6)[2]
+    a = oracle.fmgsr_solve(f, segments=4, buffer=4, nsr=1, tau="split")
+    b = oracle.fmgsr_solve(f, segments=4, buffer=4, nsr=1, tau="literal")
+    c = oracle.fmgsr_solve(f, segments=4, buffer=4, nsr=1, tau="literal", tau_assembled=True)
+    tol = 1e-13 * n
+    assert rel(a, b) < tol and rel(b, c) < tol
+
+
+def test_per_patch_tau_equals_assembled_when_buffer_is_wide():
+    """Per-patch literal tau reads 2 cells past the core; with b >= 2 nu1 + 1
+    it coincides bitwise with the assembled tau."""
+    n = 256
+    f = _problem(n, 7)[2]
+    a = oracle.fmgsr_solve(f, segments=8, buffer=5, nsr=1, tau="literal")
+    b = oracle.fmgsr_solve(f, segments=8, buffer=5, nsr=1, tau="literal", tau_assembled=True)
+    assert np.array_equal(a, b)
+
+
+def test_vcycle_fixed_point_and_rate():
+    n = 1024
+    k, c, f = _problem(n, 8)
+    ustar = oracle.coarse_solve(f)
+    v = oracle.fas_vcycle(ustar, f)
+    assert rel(v, ustar) < 1e-12
+    # error reduction of V(2,1): h-independent and small with full weighting
+    for rr, bound in (("fw", 0.1), ("avg", 0.4)):
+        tau = "split" if rr == "fw" else "literal"
+        u = RNG.standard_normal(n)
+        e0 = np.linalg.norm(u - ustar)
+        for _ in range(4):
+            u = oracle.fas_vcycle(u, f, rhs_restrict=rr, tau=tau)
+        rate = (np.linalg.norm(u - ustar) / e0) ** 0.25
+        assert rate < bound, (rr, rate)
+
+
+def test_correction_scheme_equivalence():
+    """In the linear case FAS is the correction scheme: one FMG with
+    correction-scheme V-cycles (dense, written from the textbook form
+    e_H = L_H^{-1} I r_h, u_h += P e_H) gives the same iterate."""
+    n, levels = 128, 6
+    f = _problem(n, 9)[2]
+    M = levels - 1
+    ns = [n >> (M - l) for l in range(M + 1)]
+    A = [D.laplacian(m) for m in ns]
+
+    def vcycle_cs(l, u, r):
+        if l == 0:
+            return np.linalg.solve(A[0], r)
+        u = D.smooth(A[l], u, r, 2)
+        rc = D.restriction_fw(ns[l - 1]) @ (r - A[l] @ u)
+        ec = vcycle_cs(l - 1, np.zeros(ns[l - 1]), rc)
+        u = u + D.prolongation(ns[l - 1]) @ ec
+        return D.smooth(A[l], u, r, 1)
+
+    F = [None] * (M + 1)
+    F[M] = f
+    for l in range(M, 0, -1):
+        F[l - 1] = D.restriction_fw(ns[l - 1]) @ F[l]
+    u = np.linalg.solve(A[0], F[0])
+    for l in range(1, M + 1):
+        u = vcycle_cs(l, D.fmg_interp(ns[l - 1]) @ u, F[l])
+    got = oracle.fmgsr_solve(f, levels=levels, nsr=0)
+    assert rel(got, u) < 1e-12
+
+
+def test_paper_mode_second_order():
+    """The paper's convergence studies (lexicographic GS, two-cell average
+    restrictions, coarsest grid of 4 cells) show second-order convergence of
+    one FMG cycle for 0-3 SR levels with 4 halo cells and with the global
+    smoother."""
+    for block, b in ((0, 0), (2, 4)):
+        for nu in (1, 2):
+            for nsr in (0, 1, 2, 3):
+                errs = []
+                for e in (6, 8, 10):
+                    n = 1 << e
+                    k, c = W.modes("paper", 0, 0, n)
+                    f = W.rhs_numpy(n, k, c)
+                    u = oracle.fmgsr_solve(f, levels=e - 1, segments=1, buffer=b, nsr=nsr,
+                                           tau="literal", rhs_restrict="avg", smoother="lex",
+                                           tau_assembled=True, block_all=block, nu1=nu, nu2=nu)
+                    errs.append(rel(u, W.exact_numpy(n, k, c)))
+                ratios = np.array(errs[:-1]) / np.array(errs[1:])
+                assert np.all((ratios > 10.0) & (ratios < 24.0)), (block, nu, nsr, ratios)
+
+
+def test_invalid_arguments():
+    f = np.zeros(64)
+    with pytest.raises(ValueError):
+        oracle.fmgsr_solve(f, levels=8)                   # 64 not divisible by 2^7
+    with pytest.raises(ValueError):
+        oracle.fmgsr_solve(f, segments=3, buffer=1, nsr=1)
+    with pytest.raises(ValueError):
+        oracle.fmgsr_solve(f, rhs_restrict="avg", tau="split")
