@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark one FMG-FAS-SR iteration on the GPU (1D Poisson, FP64).
+
+A step is one full solve: forcing hierarchy, FMG cycles on every level, the
+SR down and up passes over the finest level, result streamed to u_out.  All
+inputs are resident in HBM before the timed region.  Prints ONE JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload c5|c2|c1] [--gpus 1]
+
+Default workload: N = 2^28 fine cells, 29 levels, 2^16 segments of 4096
+cells + 8 buffer cells, V(2,1) red-black Gauss-Seidel, 32-mode seeded
+manufactured solution.  Timing: HIP events on the solve's stream around K
+back-to-back solves (K = 10 by default).  The dominant kernel (largest share
+of a profiled solve) is additionally bracketed by events inside the timed
+region to report its achieved algorithmic bandwidth against the 8 TB/s HBM
+peak.  The CPU baseline times the FP64 oracle on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fine-grid unknowns/sec, one FMG-FAS-SR iter to discretization error; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def closed_form(n, k, c, dev):
+    """Discrete solution of the cell-centred problem (sines are exact
+    eigenvectors, eigenvalue 4 n^2 sin^2(k pi / 2n)) and the continuous one."""
+    import torch
+    x = (torch.arange(n, dtype=torch.float64, device=dev) + 0.5) / n
+    ustar = torch.zeros(n, dtype=torch.float64, device=dev)
+    uex = torch.zeros(n, dtype=torch.float64, device=dev)
+    for kk, cc in zip(k, c):
+        s = torch.sin(x * (float(kk) * np.pi))
+        lam = 4.0 * n * n * np.sin(kk * np.pi / (2 * n)) ** 2
+        ustar.add_(s, alpha=float(cc * (kk * np.pi) ** 2 / lam))
+        uex.add_(s, alpha=float(cc))
+        del s
+    del x
+    return ustar, uex
+
+
+def traffic_for(kernel, kernel_source_hash):
+    """Measured HBM bytes per launch of `kernel` from the committed counter
+    summary, if it was taken on the current kernel source (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = t.get("kernels", {}).get(kernel)
+    if not ent or t.get("source_sha256") != kernel_source_hash:
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for p in ("paper_1207_6720_amd/csrc/fmgsr_kernels.hpp", "paper_1207_6720_amd/csrc/fmgsr.hip"):
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def cpu_baseline(wl, log2n, runs, dev):
+    """Time the FP64 oracle (single thread, as written) on a bounded sample:
+    the same workload law and segment geometry at N = 2^log2n."""
+    import torch
+    import oracle
+    from paper_1207_6720_amd import workloads as W
+    n = 1 << log2n
+    k, c = W.modes(wl.law, wl.n_modes, 0)
+    f = W.rhs_torch(n, k, c, dev).cpu().numpy()
+    seg = max(n // (wl.n // wl.segments), 1)
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        oracle.fmgsr_solve(f, levels=log2n + 1, segments=seg, buffer=wl.buffer)
+        times.append(time.perf_counter() - t0)
+        log(f"oracle N=2^{log2n}: {times[-1]:.2f} s")
+    t = float(np.median(times))
+    return {"value": n / t, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one FMG-FAS-SR iteration of the {wl.name} law at N=2^{log2n} "
+                       f"({seg} segments x {wl.n // wl.segments} cells + {wl.buffer} buffer), "
+                       f"single-threaded C oracle, median of {runs} runs ({t:.2f} s each)")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c5"])
+    ap.add_argument("--tau", default="split", choices=["split", "literal"])
+    ap.add_argument("--sr-levels", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--cpu-log2n", type=int, default=24)
+    ap.add_argument("--cpu-runs", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures a single GPU: the solver has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1207_6720_amd import fmgsr, workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    wl = W.WORKLOADS[args.workload]
+    n = wl.n
+    k, c = W.modes(wl.law, wl.n_modes, 0)
+    log(f"{fmgsr.version()} workload {wl.name}: {wl.description}")
+    f = W.rhs_torch(n, k, c, dev)
+    u = torch.empty_like(f)
+    kw = dict(levels=wl.levels, segments=wl.segments, buffer=wl.buffer, nu=(2, 1),
+              sr_levels=args.sr_levels, tau=args.tau)
+    ws = fmgsr.alloc_workspace(n, wl.levels, dev, nu=(2, 1), sr_levels=args.sr_levels,
+                               tau=args.tau)
+    stream = torch.cuda.current_stream(dev)
+    torch.cuda.synchronize()
+    mem_inputs = torch.cuda.memory_allocated(dev)
+
+    # warm-up; the first warm-up solve is profiled kernel by kernel
+    fmgsr.profile_enable(None)
+    fmgsr.solve(f, out=u, workspace=ws, stream=stream, **kw)
+    torch.cuda.synchronize()
+    prof_all = fmgsr.profile_collect()
+    for _ in range(max(args.warmup - 1, 0)):
+        fmgsr.solve(f, out=u, workspace=ws, stream=stream, **kw)
+    torch.cuda.synchronize()
+    dominant = max(prof_all, key=lambda kname: prof_all[kname]["total_ms"])
+    model_bytes = sum(v["algo_bytes"] for v in prof_all.values())
+    log(f"warm-up done; dominant kernel {dominant} "
+        f"({prof_all[dominant]['total_ms']:.3f} of {sum(v['total_ms'] for v in prof_all.values()):.3f} ms profiled)")
+
+    # timed region: K solves; events around the dominant kernel's launches
+    fmgsr.profile_enable(dominant)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fmgsr.solve(f, out=u, workspace=ws, stream=stream, **kw)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dom = fmgsr.profile_collect()[dominant]
+    ms = ev0.elapsed_time(ev1) / args.steps
+    log(f"timed {args.steps} steps: {ms:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f} ms/step)")
+
+    # accuracy of the benchmarked result (closed-form discrete solution)
+    ustar, uex = closed_form(n, k, c, dev)
+    nrm = lambda t: float(torch.linalg.vector_norm(t))
+    acc = {"alg_rel": nrm(u - ustar) / nrm(ustar), "disc_rel": nrm(ustar - uex) / nrm(uex),
+           "total_rel": nrm(u - uex) / nrm(uex)}
+    acc["alg_over_disc"] = acc["alg_rel"] / acc["disc_rel"] if acc["disc_rel"] > 0 else None
+    del ustar, uex
+    peak_mem = torch.cuda.max_memory_allocated(dev)
+
+    dom_launch_ms = dom["total_ms"] / dom["launches"]
+    dom_bytes = dom["algo_bytes"] / dom["launches"]
+    achieved = dom_bytes / (dom_launch_ms * 1e-3) / 1e9
+    traffic = traffic_for(dominant, kernel_source_hash())
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": dominant,
+                "algo_bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_launch_ms, 4),
+                "launches": dom["launches"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, args.cpu_log2n, args.cpu_runs, dev)
+
+    value = n / (ms * 1e-3)
+    out = {
+        "metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.description}", "n": n, "levels": wl.levels,
+                   "segments": wl.segments, "buffer": wl.buffer, "nu": [2, 1],
+                   "smoother": "red-black GS", "tau": args.tau, "sr_levels": args.sr_levels,
+                   "seed": 0, "modes": wl.n_modes},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "solve_model": {"algo_bytes_per_step": model_bytes,
+                        "algo_bytes_per_unknown": round(model_bytes / n, 2),
+                        "effective_GBps": round(model_bytes / (ms * 1e-3) / 1e9, 1),
+                        "frac_of_hbm_peak": round(model_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "accuracy": acc,
+        "memory": {"inputs_and_workspace_bytes": mem_inputs, "peak_allocated_bytes": peak_mem,
+                   "workspace_bytes": ws.numel()},
+        "kernels": {kname: {"launches": v["launches"], "ms": round(v["total_ms"], 4),
+                            "GBps": round(v["algo_bytes"] / max(v["total_ms"], 1e-9) / 1e6, 1)}
+                    for kname, v in sorted(prof_all.items(), key=lambda kv: -kv[1]["total_ms"])},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,448 @@
+// fmgsr.hip -- C ABI (include/fmgsr.h) and launch schedule of the gfx950
+// FMG-FAS-SR solver.
+//
+// Schedule of one FMG cycle (Fig. 3) on levels 0..M (M = levels - 1):
+//   forcing hierarchy   F^l = I F^{l+1}, l = M-1..0 (F^M = f)
+//   coarse core         levels 0..C (C = largest level <= M-1 with at most
+//                       kCoreMaxCells cells) in one workgroup: the FMG cycles
+//                       up to level C, then one V-cycle bottom per later step
+//   step t = C+1..M     down visits t..C+1, coarse core, up visits C+1..t
+// A stored level keeps two arrays: U (pre-smoothed iterate, written by the
+// down visit, read by the up visit) and V (post-smoothed iterate; the FMG
+// result of step t that step t+1 interpolates from).  Separate arrays keep
+// every launch free of read/write overlap between workgroups.  The SR level
+// (t = M with sr_levels = 1) is never stored: its down pass writes only
+// I^ of the smoothed cores (Uh) and its up pass streams the cores to u_out.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fmgsr.h"
+#include "fmgsr_kernels.hpp"
+
+namespace fmgsr {
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+inline int64_t lvl_off_h(int64_t n0, int l) { return n0 * (((int64_t)1 << l) - 1); }
+
+struct Plan {
+  int64_t n = 0, n0 = 0;
+  int M = 0, C = 0;
+  int nu1 = 2, nu2 = 1, nsr = 1, literal = 0;
+  int64_t S = 1, s = 0, b = 0, pad = 0;
+  int seg_threads = 0;
+  // workspace layout (byte offsets)
+  size_t off_F = 0, off_U = 0, off_V = 0, off_Uh = 0, off_Q = 0, off_Utop = 0, total = 0;
+};
+
+// Geometry, options and workspace layout (segment arguments excluded).
+fmgsr_status make_plan(int64_t n, int32_t levels, const fmgsr_options& o, Plan* p) {
+  if (n < 1 || levels < 1 || levels > 40) return FMGSR_EINVAL;
+  const int M = levels - 1;
+  if ((n % ((int64_t)1 << M)) != 0) return FMGSR_EINVAL;
+  const int64_t n0 = n >> M;
+  if (n0 > kMaxN0) return FMGSR_EINVAL;
+  if (o.nu1 < 0 || o.nu1 > 16 || o.nu2 < 0 || o.nu2 > 16) return FMGSR_EINVAL;
+  if (o.sr_levels < 0) return FMGSR_EINVAL;
+  if (o.sr_levels > 1) return FMGSR_ENOTSUP;
+  if (o.sr_levels == 1 && M < 1) return FMGSR_EINVAL;
+  if (o.tau_mode != FMGSR_TAU_SPLIT && o.tau_mode != FMGSR_TAU_LITERAL) return FMGSR_EINVAL;
+  p->n = n;
+  p->n0 = n0;
+  p->M = M;
+  p->nu1 = o.nu1;
+  p->nu2 = o.nu2;
+  p->nsr = o.sr_levels;
+  p->literal = (o.tau_mode == FMGSR_TAU_LITERAL);
+  // coarse core top level
+  int C = 0;
+  while (C + 1 <= M - 1 && (n0 << (C + 1)) <= kCoreMaxCells) ++C;
+  p->C = C;
+  // workspace layout
+  const size_t hier = (size_t)(M >= 1 ? lvl_off_h(n0, M) : 0) * sizeof(double);  // levels 0..M-1
+  size_t off = 0;
+  p->off_F = off; off = align_up(off + hier);
+  p->off_U = off; off = align_up(off + hier);
+  p->off_V = off; off = align_up(off + hier);
+  p->off_Uh = off; off = align_up(off + (p->nsr ? (size_t)(n / 2) * sizeof(double) : 0));
+  p->off_Q = off; off = align_up(off + (p->literal ? hier : 0));
+  p->off_Utop = off; off = align_up(off + (p->nsr == 0 && M >= 1 ? (size_t)n * sizeof(double) : 0));
+  p->total = std::max<size_t>(off, kAlign);
+  return FMGSR_OK;
+}
+
+// Segments of the SR level: core s = n / n_segments (even), window of
+// s + 2 pad cells per workgroup, pad = even >= buffer + 1.
+fmgsr_status plan_segments(int64_t n_segments, int32_t buffer, Plan* p) {
+  if (p->nsr == 0) return FMGSR_OK;
+  if (buffer < 0 || buffer > 1024) return FMGSR_EINVAL;
+  if (n_segments < 1 || p->n % n_segments != 0) return FMGSR_EINVAL;
+  const int64_t s = p->n / n_segments;
+  if (s < 2 || (s & 1)) return FMGSR_EINVAL;
+  const int64_t pad = ((int64_t)buffer + 2) & ~(int64_t)1;
+  const int64_t cells = s + 2 * pad;
+  if (cells > (int64_t)kRun * kSegMaxThreads) return FMGSR_EINVAL;
+  const int64_t thr = (cells + kRun - 1) / kRun;
+  p->S = n_segments;
+  p->s = s;
+  p->b = buffer;
+  p->pad = pad;
+  p->seg_threads = (int)((thr + 63) / 64 * 64);
+  return FMGSR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Optional per-launch timing (fmgsr_profile_*)
+// ---------------------------------------------------------------------------
+struct ProfRecord {
+  const char* name;
+  hipEvent_t start, stop;
+  double bytes;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::string g_prof_filter;
+std::vector<ProfRecord> g_prof;
+
+struct ProfScope {
+  ProfRecord rec{};
+  bool on = false;
+  hipStream_t st;
+  ProfScope(const char* name, double bytes, hipStream_t s) : st(s) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    if (!g_prof_filter.empty() && std::string(name).find(g_prof_filter) == std::string::npos) return;
+    if (hipEventCreate(&rec.start) != hipSuccess) return;
+    if (hipEventCreate(&rec.stop) != hipSuccess) { (void)hipEventDestroy(rec.start); return; }
+    rec.name = name;
+    rec.bytes = bytes;
+    on = (hipEventRecord(rec.start, st) == hipSuccess);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (hipEventRecord(rec.stop, st) == hipSuccess) g_prof.push_back(rec);
+  }
+};
+
+bool is_device_ptr(const void* ptr) {
+  if (!ptr) return false;
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+struct Ctx {
+  const Plan* p;
+  hipStream_t st;
+  double gL, gR;
+  const double* f;
+  double* u_out;
+  double *F, *U, *V, *Uh, *Q, *Utop;
+  fmgsr_status err = FMGSR_OK;
+
+  double* lv(double* base, int l) const { return base + lvl_off_h(p->n0, l); }
+  int64_t nl(int l) const { return p->n0 << l; }
+  const double* forcing(int l) const { return l == p->M ? f : lv(F, l); }
+
+  void check() {
+    if (hipGetLastError() != hipSuccess) err = FMGSR_EDEVICE;
+  }
+
+  void tile_launch(bool up, int l, int nu, int src_kind, const double* src, const double* pre,
+                   const double* coarse, const double* rhs, double* out) {
+    LevelArgs a;
+    a.n = nl(l);
+    a.gL = gL;
+    a.gR = gR;
+    a.nu = nu;
+    a.halo = std::max(2, 2 * nu);
+    a.core = (int64_t)kRun * kTileThreads - 2 * a.halo;
+    a.src_kind = src_kind;
+    a.src = src;
+    a.pre = pre;
+    a.coarse = coarse;
+    a.rhs = rhs;
+    a.out = out;
+    const int64_t blocks = (a.n + a.core - 1) / a.core;
+    const double nb = (double)a.n * 8.0;
+    const double bytes = up ? nb * 3.5  // pre, rhs, out: n each; coarse: n/2
+                            : nb * 2.0 + (src_kind == kSrcInterp ? nb * 0.5
+                                          : src_kind == kSrcRestrict ? nb * 2.0 : nb);
+    ProfScope ps(up ? "k_level_up" : "k_level_down", bytes, st);
+    if (up)
+      hipLaunchKernelGGL(k_level_up<kRun>, dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_level_down<kRun>, dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+    check();
+  }
+
+  void tau_launch(const double* ufine, const double* Ffine, int lcoarse, double* out) {
+    const int64_t nc = nl(lcoarse);
+    const int thr = 256;
+    ProfScope ps("k_tau_literal", (double)nc * 8.0 * 5.0, st);  // u, F: 2 nc each; out: nc
+    hipLaunchKernelGGL(k_tau_literal, dim3((unsigned)((nc + thr - 1) / thr)), dim3(thr), 0, st,
+                       ufine, Ffine, nc, gL, gR, out);
+    check();
+  }
+
+  void core_launch(int mode, int src_kind, const double* src, const double* rhs_top) {
+    CoreArgs a;
+    a.top = p->C;
+    a.n0 = p->n0;
+    a.gL = gL;
+    a.gR = gR;
+    a.nu1 = p->nu1;
+    a.nu2 = p->nu2;
+    a.literal = p->literal;
+    a.mode = mode;
+    a.src_kind = src_kind;
+    a.F = (p->M >= 1) ? F : f;
+    a.src = src;
+    a.rhs_top = rhs_top;
+    a.out = (p->M >= 1) ? lv(V, p->C) : u_out;
+    const int64_t ntot = lvl_off_h(p->n0, p->C + 1);
+    const int64_t esz = (p->C > 0) ? (p->n0 << (p->C - 1)) : 1;
+    const size_t lds = (size_t)(2 * ntot + esz + 4 * p->n0) * sizeof(double);
+    const int64_t nC = p->n0 << p->C;
+    double bytes = (double)ntot * 8.0 + (double)nC * 8.0;  // forcing levels, result
+    if (mode == 1) bytes += (double)nC * 8.0 * (src_kind == kSrcRestrict ? 3.0 : 2.0);
+    ProfScope ps("k_coarse_core", bytes, st);
+    hipLaunchKernelGGL(k_coarse_core, dim3(1), dim3(kCoreThreads), lds, st, a);
+    check();
+  }
+
+  void seg_launch(bool up, const double* coarse, double* out, double* q_out) {
+    SegArgs a;
+    a.n = p->n;
+    a.gL = gL;
+    a.gR = gR;
+    a.nu = up ? p->nu2 : p->nu1;
+    a.s = p->s;
+    a.buffer = p->b;
+    a.pad = p->pad;
+    a.coarse = coarse;
+    a.f = f;
+    a.out = out;
+    a.q_out = q_out;
+    const double nb = (double)p->n * 8.0;
+    // coarse n/2 and f n read; down writes n/2 (+ n/2 literal tau), up writes n
+    const double bytes = up ? nb * 2.5 : nb * 2.0 + (q_out ? nb * 0.5 : 0.0);
+    ProfScope ps(up ? "k_sr_up" : "k_sr_down", bytes, st);
+    if (up)
+      hipLaunchKernelGGL(k_sr_up<kRun>, dim3((unsigned)p->S), dim3(p->seg_threads), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_sr_down<kRun>, dim3((unsigned)p->S), dim3(p->seg_threads), 0, st, a);
+    check();
+  }
+
+  void run() {
+    const Plan& P = *p;
+    const int M = P.M, C = P.C;
+    if (M == 0) {  // a single grid: exact solve
+      core_launch(0, kSrcDirect, nullptr, nullptr);
+      return;
+    }
+    // forcing on all levels
+    for (int l = M - 1; l >= 0; --l) {
+      const int64_t nc = nl(l);
+      const int thr = 256;
+      ProfScope ps("k_restrict_fw", (double)nc * 8.0 * 3.0, st);
+      hipLaunchKernelGGL(k_restrict_fw, dim3((unsigned)((nc + thr - 1) / thr)), dim3(thr), 0, st,
+                         forcing(l + 1), nc, lv(F, l));
+      check();
+    }
+    // FMG cycles on the coarse core levels
+    core_launch(0, kSrcDirect, nullptr, nullptr);
+    for (int t = C + 1; t <= M && err == FMGSR_OK; ++t) {
+      const bool sr = (P.nsr == 1 && t == M);
+      double* Ut = (t == M) ? Utop : lv(U, t);
+      // rhs in use on level l during this step
+      auto rhs_of = [&](int l) -> const double* {
+        if (l == t) return forcing(t);
+        return P.literal ? lv(Q, l) : lv(F, l);
+      };
+      int top;  // highest stored level visited below the top of the step
+      if (sr) {
+        seg_launch(false, lv(V, M - 1), Uh, P.literal ? lv(Q, M - 1) : nullptr);
+        top = M - 1;
+      } else {
+        tile_launch(false, t, P.nu1, kSrcInterp, lv(V, t - 1), nullptr, nullptr, forcing(t), Ut);
+        top = t - 1;
+      }
+      // pre-smoothing leg on the stored levels above the coarse core
+      for (int l = top; l >= C + 1; --l) {
+        const bool from_uh = sr && l == M - 1;
+        if (P.literal && !from_uh) {
+          const double* uf = (l + 1 == t) ? Ut : lv(U, l + 1);
+          tau_launch(uf, rhs_of(l + 1), l, lv(Q, l));
+        }
+        if (from_uh)
+          tile_launch(false, l, P.nu1, kSrcDirect, Uh, nullptr, nullptr, rhs_of(l), lv(U, l));
+        else
+          tile_launch(false, l, P.nu1, kSrcRestrict, (l + 1 == t) ? Ut : lv(U, l + 1), nullptr,
+                      nullptr, rhs_of(l), lv(U, l));
+      }
+      // coarse core: V-cycle bottom from level C
+      if (sr && C == M - 1) {
+        core_launch(1, kSrcDirect, Uh, rhs_of(C));
+      } else {
+        const double* uf = (C + 1 == t) ? Ut : lv(U, C + 1);
+        if (P.literal) tau_launch(uf, rhs_of(C + 1), C, lv(Q, C));
+        core_launch(1, kSrcRestrict, uf, rhs_of(C));
+      }
+      // post-smoothing leg
+      for (int l = C + 1; l <= top; ++l)
+        tile_launch(true, l, P.nu2, kSrcDirect, nullptr, lv(U, l), lv(V, l - 1), rhs_of(l),
+                    lv(V, l));
+      if (sr)
+        seg_launch(true, lv(V, M - 1), u_out, nullptr);
+      else
+        tile_launch(true, t, P.nu2, kSrcDirect, nullptr, Ut, lv(V, t - 1), forcing(t),
+                    (t == M) ? u_out : lv(V, t));
+    }
+  }
+};
+
+}  // namespace
+}  // namespace fmgsr
+
+using namespace fmgsr;
+
+extern "C" {
+
+void fmgsr_default_options(fmgsr_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->nu1 = 2;
+  opt->nu2 = 1;
+  opt->sr_levels = 1;
+  opt->tau_mode = FMGSR_TAU_SPLIT;
+}
+
+size_t fmgsr_workspace_bytes(int64_t n, int32_t levels, const fmgsr_options* opt) {
+  fmgsr_options o;
+  if (opt) o = *opt;
+  else fmgsr_default_options(&o);
+  Plan p;
+  if (make_plan(n, levels, o, &p) != FMGSR_OK) return 0;
+  return p.total;
+}
+
+fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_left,
+                         double g_right, int64_t n, int32_t levels, int64_t n_segments,
+                         int32_t buffer, const fmgsr_options* opt, double* u_out,
+                         void* hip_stream) {
+  if (op && (op->kind != FMGSR_OP_POISSON || op->kappa != nullptr)) return FMGSR_ENOTSUP;
+  fmgsr_options o;
+  if (opt) o = *opt;
+  else fmgsr_default_options(&o);
+  Plan p;
+  fmgsr_status st = make_plan(n, levels, o, &p);
+  if (st == FMGSR_OK) st = plan_segments(n_segments, buffer, &p);
+  if (st != FMGSR_OK) return st;
+  if (!is_device_ptr(f) || !is_device_ptr(u_out)) return FMGSR_EINVAL;
+  if ((const void*)f == (const void*)u_out) return FMGSR_EINVAL;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  char* ws = (char*)o.workspace;
+  bool own = false;
+  if (ws) {
+    if (o.workspace_bytes < p.total || !is_device_ptr(ws)) return FMGSR_ENOMEM;
+  } else {
+    if (hipMallocAsync((void**)&ws, p.total, stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return FMGSR_ENOMEM;
+    }
+    own = true;
+  }
+  Ctx c;
+  c.p = &p;
+  c.st = stream;
+  c.gL = g_left;
+  c.gR = g_right;
+  c.f = f;
+  c.u_out = u_out;
+  c.F = (double*)(ws + p.off_F);
+  c.U = (double*)(ws + p.off_U);
+  c.V = (double*)(ws + p.off_V);
+  c.Uh = (double*)(ws + p.off_Uh);
+  c.Q = (double*)(ws + p.off_Q);
+  c.Utop = (double*)(ws + p.off_Utop);
+  c.run();
+  if (own && hipFreeAsync(ws, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    if (c.err == FMGSR_OK) c.err = FMGSR_EDEVICE;
+  }
+  return c.err;
+}
+
+fmgsr_status fmgsr_profile_enable(const char* filter) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& r : g_prof) {
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+  g_prof.clear();
+  g_prof_filter = filter ? filter : "";
+  g_prof_on = true;
+  return FMGSR_OK;
+}
+
+int32_t fmgsr_profile_collect(fmgsr_kernel_stat* stats, int32_t max_stats) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = false;
+  std::vector<fmgsr_kernel_stat> agg;
+  int32_t status = 0;
+  for (auto& r : g_prof) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) {
+      (void)hipGetLastError();
+      status = FMGSR_EDEVICE;
+    }
+    size_t k = 0;
+    while (k < agg.size() && std::strcmp(agg[k].name, r.name) != 0) ++k;
+    if (k == agg.size()) {
+      fmgsr_kernel_stat z;
+      std::memset(&z, 0, sizeof(z));
+      std::strncpy(z.name, r.name, sizeof(z.name) - 1);
+      agg.push_back(z);
+    }
+    agg[k].launches += 1;
+    agg[k].total_ms += ms;
+    agg[k].algo_bytes += r.bytes;
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+  g_prof.clear();
+  if (status != 0) return status;
+  for (size_t k = 0; k < agg.size() && (int32_t)k < max_stats; ++k)
+    if (stats) stats[k] = agg[k];
+  return (int32_t)agg.size();
+}
+
+const char* fmgsr_status_string(int32_t status) {
+  switch (status) {
+    case FMGSR_OK: return "FMGSR_OK";
+    case FMGSR_EINVAL: return "FMGSR_EINVAL: invalid argument";
+    case FMGSR_ENOMEM: return "FMGSR_ENOMEM: workspace allocation failed or too small";
+    case FMGSR_EDEVICE: return "FMGSR_EDEVICE: HIP runtime or launch failure";
+    case FMGSR_ENOTSUP: return "FMGSR_ENOTSUP: not implemented by this library";
+    default: return "unknown fmgsr status";
+  }
+}
+
+const char* fmgsr_version(void) { return "fmgsr 0.1 gfx950"; }
+
+}  // extern "C"

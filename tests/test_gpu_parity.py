@@ -1,0 +1,158 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Both sides receive the same input bits.  The bar is the FP64 tolerance of
+1e-12 relative (2-norm over the whole solution).  Where the coarsest grid is
+a single cell the two implementations evaluate identical expression trees
+(no FMA contraction on either side), so the results are also required to be
+bitwise equal; with N0 > 1 the coarsest solve differs (parallel cyclic
+reduction vs Thomas) and only the tolerance applies.
+"""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_1207_6720_amd import fmgsr, workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def gpu_solve(dev, f_host, **kw):
+    f = torch.from_numpy(np.ascontiguousarray(f_host)).to(dev)
+    u = fmgsr.solve(f, **kw)
+    torch.cuda.synchronize()
+    return u.cpu().numpy()
+
+
+def oracle_solve(f_host, g=(0.0, 0.0), levels=None, segments=1, buffer=0, nu=(2, 1),
+                 sr_levels=1, tau="split"):
+    return oracle.fmgsr_solve(f_host, g[0], g[1], levels=levels, segments=segments, buffer=buffer,
+                              nu1=nu[0], nu2=nu[1], nsr=sr_levels, tau=tau)
+
+
+def rhs(n, seed, law="inv_k2", nm=16):
+    k, c = W.modes(law, nm, seed, n)
+    return W.rhs_numpy(n, k, c)
+
+
+def compare(u_gpu, u_ref, bitwise):
+    denom = max(np.linalg.norm(u_ref), 1e-300)
+    err = np.linalg.norm(u_gpu - u_ref) / denom
+    assert np.all(np.isfinite(u_gpu))
+    assert err <= TOL, f"relative difference {err:.3e}"
+    if bitwise:
+        nbad = int(np.count_nonzero(u_gpu != u_ref))
+        assert nbad == 0, f"{nbad} cells differ (max |d| = {np.abs(u_gpu - u_ref).max():.3e})"
+    return err
+
+
+# (n, levels, segments, buffer, nu, sr_levels, tau, g, seed)
+CASES = [
+    # the small workload and its seeds
+    (1 << 10, 11, 4, 4, (2, 1), 1, "split", (0.0, 0.0), 0),
+    (1 << 10, 11, 4, 4, (2, 1), 1, "split", (0.0, 0.0), 1),
+    (1 << 10, 11, 4, 4, (2, 1), 1, "split", (0.0, 0.0), 2),
+    # tiny hierarchies (coarse core only, one-cell levels, nc = 1 interpolation)
+    (1, 1, 1, 0, (2, 1), 0, "split", (0.3, -0.2), 3),
+    (2, 2, 1, 0, (2, 1), 1, "split", (0.3, -0.2), 3),
+    (2, 2, 1, 0, (2, 1), 0, "split", (0.3, -0.2), 3),
+    (4, 3, 2, 1, (2, 1), 1, "split", (0.0, 1.0), 4),
+    (8, 4, 2, 3, (1, 1), 1, "literal", (0.5, 0.5), 5),
+    (64, 7, 8, 2, (2, 1), 1, "split", (0.0, 0.0), 6),
+    # several tiles per stored level, coarse core boundary, ragged tiles
+    (1 << 14, 15, 16, 8, (2, 1), 1, "split", (0.0, 0.0), 7),
+    (1 << 16, 17, 16, 8, (2, 1), 1, "split", (0.25, -1.5), 8),
+    (5 << 12, 13, 5, 8, (2, 1), 1, "split", (0.0, 0.0), 9),     # N0 = 5
+    (7 << 12, 12, 28, 3, (2, 1), 1, "split", (0.1, 0.2), 10),   # N0 = 14
+    (3 << 9, 10, 3, 4, (2, 1), 1, "split", (0.0, 0.0), 11),     # N0 = 3
+    # plain FMG-FAS (every level stored)
+    (1 << 12, 13, 1, 0, (2, 1), 0, "split", (0.0, 0.0), 12),
+    (1 << 16, 17, 1, 0, (2, 1), 0, "split", (0.0, 0.0), 13),
+    # literal tau (Eq. 7 as written), stored and per-patch
+    (1 << 12, 13, 8, 8, (2, 1), 1, "literal", (0.0, 0.0), 14),
+    (1 << 12, 13, 8, 1, (2, 1), 1, "literal", (0.4, 0.1), 15),
+    (1 << 15, 16, 8, 8, (2, 1), 0, "literal", (0.0, 0.0), 16),
+    # sweep counts and thin buffers (segments genuinely change the result)
+    (1 << 12, 13, 64, 0, (2, 1), 1, "split", (0.0, 0.0), 17),
+    (1 << 12, 13, 64, 1, (1, 1), 1, "split", (0.0, 0.0), 18),
+    (1 << 12, 13, 32, 2, (3, 2), 1, "split", (0.0, 0.0), 19),
+    (1 << 12, 13, 16, 5, (0, 1), 1, "split", (0.0, 0.0), 20),
+    (1 << 12, 13, 16, 5, (1, 0), 1, "split", (0.0, 0.0), 21),
+    (1 << 12, 13, 2048, 4, (2, 1), 1, "split", (0.0, 0.0), 22),  # two-cell cores
+    (1 << 13, 14, 2, 9, (4, 4), 1, "split", (0.0, 0.0), 23),
+    # levels = 1 with N0 > 1 (one exact solve)
+    (1000, 1, 1, 0, (2, 1), 0, "split", (0.2, 0.7), 24),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"n{c[0]}_L{c[1]}_S{c[2]}_b{c[3]}_nu{c[4][0]}{c[4][1]}_sr{c[5]}_{c[6]}")
+def test_parity_vs_oracle(dev, case):
+    n, levels, S, b, nu, sr, tau, g, seed = case
+    print(f"case n={n} levels={levels} S={S} b={b} nu={nu} sr={sr} tau={tau}", flush=True)
+    f = rhs(n, seed)
+    kw = dict(g=g, levels=levels, segments=S, buffer=b, nu=nu, sr_levels=sr, tau=tau)
+    u_gpu = gpu_solve(dev, f, **kw)
+    u_ref = oracle_solve(f, **kw)
+    n0 = n >> (levels - 1)
+    compare(u_gpu, u_ref, bitwise=(n0 == 1))
+
+
+def test_repeatable_and_workspace_reuse(dev):
+    n, levels = 1 << 14, 15
+    f = torch.from_numpy(rhs(n, 30)).to(dev)
+    ws = fmgsr.alloc_workspace(n, levels, dev)
+    a = fmgsr.solve(f, levels=levels, segments=4, buffer=8, workspace=ws).clone()
+    ws.fill_(255)                          # garbage in the workspace must not matter
+    b = fmgsr.solve(f, levels=levels, segments=4, buffer=8, workspace=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_side_stream(dev):
+    n, levels = 1 << 12, 13
+    f_host = rhs(n, 31)
+    f = torch.from_numpy(f_host).to(dev)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        u = fmgsr.solve(f, levels=levels, segments=4, buffer=4)
+    s.synchronize()
+    compare(u.cpu().numpy(), oracle_solve(f_host, levels=levels, segments=4, buffer=4), True)
+
+
+def test_rejects_host_tensors_and_bad_sizes(dev):
+    with pytest.raises(ValueError):
+        fmgsr.solve(torch.zeros(16, dtype=torch.float64))
+    f = torch.zeros(1000, dtype=torch.float64, device=dev)
+    with pytest.raises(fmgsr.FmgsrError):
+        fmgsr.solve(f, levels=11)
+    ws = torch.empty(16, dtype=torch.uint8, device=dev)
+    with pytest.raises(fmgsr.FmgsrError):
+        fmgsr.solve(torch.zeros(1024, dtype=torch.float64, device=dev), levels=11,
+                    segments=4, buffer=4, workspace=ws)
+
+
+def test_workload_c2_full_size_parity(dev):
+    """N = 2^24, 25 levels, 2^12 segments of 4096 + 8 buffer cells."""
+    wl = W.WORKLOADS["c2"]
+    k, c = W.modes(wl.law, wl.n_modes, 0)
+    f = W.rhs_torch(wl.n, k, c, dev)
+    print("c2: GPU solve", flush=True)
+    u = fmgsr.solve(f, levels=wl.levels, segments=wl.segments, buffer=wl.buffer)
+    torch.cuda.synchronize()
+    f_host = f.cpu().numpy()
+    print("c2: oracle solve", flush=True)
+    u_ref = oracle_solve(f_host, levels=wl.levels, segments=wl.segments, buffer=wl.buffer)
+    err = compare(u.cpu().numpy(), u_ref, bitwise=True)
+    print(f"c2 parity rel = {err:.3e}", flush=True)

@@ -1,0 +1,73 @@
+"""CPU-side checks of the HIP library: it loads, exports every function
+include/fmgsr.h declares, and validates arguments on the host (before any
+GPU work is enqueued)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1207_6720_amd import fmgsr as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "fmgsr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fmgsr_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert "fmgsr_solve" in names and "fmgsr_workspace_bytes" in names
+    L = ctypes.CDLL(F.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version_and_status_strings():
+    assert "gfx950" in F.version()
+    for st in (0, -1, -2, -3, -4, 7):
+        assert F.lib().fmgsr_status_string(st)
+
+
+def _solve_raw(n, levels, segs, buf, **kw):
+    o = F.make_options(**kw)
+    return F.lib().fmgsr_solve(None, None, 0.0, 0.0, n, levels, segs, buf, ctypes.byref(o),
+                               None, None)
+
+
+@pytest.mark.parametrize("args,kw", [
+    ((1000, 11, 4, 4), {}),               # n not divisible by 2^(levels-1)
+    ((1024, 11, 3, 4), {}),               # segments do not divide n
+    ((1024, 11, 1024, 4), {}),            # odd segment core (s = 1)
+    ((1 << 20, 21, 1, 8), {}),            # segment window exceeds one workgroup
+    ((1024, 0, 4, 4), {}),                # no levels
+    ((1024, 41, 4, 4), {}),               # too many levels
+    ((4096, 2, 4, 4), {}),                # coarsest grid of 2048 cells
+    ((1024, 11, 4, -1), {}),              # negative buffer
+    ((1024, 11, 4, 4), {"nu": (17, 1)}),  # too many sweeps
+    ((1024, 11, 4, 4), {}),               # valid sizes, NULL device pointers
+    ((1, 1, 1, 0), {"sr_levels": 1}),     # SR level needs a coarser level
+])
+def test_invalid_arguments_rejected_on_host(args, kw):
+    assert _solve_raw(*args, **kw) == F.FMGSR_EINVAL
+
+
+def test_unsupported_requests():
+    assert _solve_raw(1024, 11, 4, 4, sr_levels=2) == F.FMGSR_ENOTSUP
+    op = F.Operator(1, None)
+    o = F.make_options()
+    assert F.lib().fmgsr_solve(ctypes.byref(op), None, 0.0, 0.0, 1024, 11, 4, 4, ctypes.byref(o),
+                               None, None) == F.FMGSR_ENOTSUP
+
+
+def test_workspace_sizes():
+    n = 1 << 20
+    hier = (n - 1) * 8
+    split = F.workspace_bytes(n, 21)
+    assert split >= 3 * hier + (n // 2) * 8
+    assert F.workspace_bytes(n, 21, tau="literal") >= split + hier
+    assert F.workspace_bytes(n, 21, sr_levels=0) >= 3 * hier + n * 8
+    assert F.workspace_bytes(1000, 11) == 0
