@@ -109,6 +109,9 @@ def main():
     ap.add_argument("--cpu-log2n", type=int, default=24)
     ap.add_argument("--cpu-runs", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain device copy of 2^27 doubles (1 GiB read + 1 GiB "
+                         "written) so hardware-counter runs can scale FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -135,6 +138,14 @@ def main():
     ws = fmgsr.alloc_workspace(n, wl.levels, dev, nu=(2, 1), sr_levels=args.sr_levels,
                                tau=args.tau)
     stream = torch.cuda.current_stream(dev)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 2^27 doubles copied")
     torch.cuda.synchronize()
     mem_inputs = torch.cuda.memory_allocated(dev)
 

@@ -2,17 +2,22 @@
 // FMG-FAS-SR solver.
 //
 // Schedule of one FMG cycle (Fig. 3) on levels 0..M (M = levels - 1):
-//   forcing hierarchy   F^l = I F^{l+1}, l = M-1..0 (F^M = f)
+//   forcing hierarchy   F^l = I F^{l+1}, l = M-1..0 (F^M = f), up to four
+//                       levels per launch
 //   coarse core         levels 0..C (C = largest level <= M-1 with at most
 //                       kCoreMaxCells cells) in one workgroup: the FMG cycles
 //                       up to level C, then one V-cycle bottom per later step
-//   step t = C+1..M     down visits t..C+1, coarse core, up visits C+1..t
+//   step t = C+1..M     vertical down kernels over levels t..C+1 (up to four
+//                       levels each), coarse core, vertical up kernels over
+//                       levels C+1..t
 // A stored level keeps two arrays: U (pre-smoothed iterate, written by the
-// down visit, read by the up visit) and V (post-smoothed iterate; the FMG
+// down leg, read by the up leg) and V (post-smoothed iterate; the FMG
 // result of step t that step t+1 interpolates from).  Separate arrays keep
 // every launch free of read/write overlap between workgroups.  The SR level
 // (t = M with sr_levels = 1) is never stored: its down pass writes only
 // I^ of the smoothed cores (Uh) and its up pass streams the cores to u_out.
+// With literal tau every stored level is its own launch, preceded by the
+// tau kernel that forms its right-hand side.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,15 +34,56 @@ namespace fmgsr {
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int64_t kLevelAlign = 32;  // doubles: every level array starts 256-byte aligned
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-inline int64_t lvl_off_h(int64_t n0, int l) { return n0 * (((int64_t)1 << l) - 1); }
+// Offset (doubles) of level l in a hierarchy array holding levels 0..l-1.
+int64_t lvl_off_ws(int64_t n0, int l) {
+  int64_t off = 0;
+  for (int m = 0; m < l; ++m) off += ((n0 << m) + kLevelAlign - 1) / kLevelAlign * kLevelAlign;
+  return off;
+}
+
+// Stale cells (counted from a window edge) left on each level of a vertical
+// kernel walking `d` levels with nu sweeps per level; the halo must cover
+// them on every level whose core is written or read further on.
+// Stale cells (counted from a window edge) on each level of a vertical
+// kernel walking `d` levels with nu sweeps per level.  The window edge cell
+// is never updated, so every half-sweep spreads staleness by one cell; I^
+// halves it, full weighting of the rhs and the neighbour exchange at the
+// window edge add one coarse cell, P reaches one coarse cell further.
+bool down_fits(int nu, int d, int64_t halo) {
+  int64_t inv = 0, rinv = 0;
+  for (int i = 0; i < d; ++i) {
+    if (i > 0) {
+      rinv = (rinv + 2) / 2;
+      inv = std::max((inv + 1) / 2, rinv);
+    }
+    inv += 2 * nu;
+    if ((halo >> i) < inv) return false;  // core of level i starts halo >> i cells in
+  }
+  return true;
+}
+
+bool up_fits(int nu, int d, int64_t halo) {
+  // bottom level: the exchanged coarse error of the edge pair is unknown
+  int64_t inv = 2 + 2 * nu;
+  for (int i = d - 2; i >= 0; --i) inv = 2 * (inv + 1) + 2 * nu;
+  return halo >= inv;  // only the top level's core is written
+}
+
+int fuse_depth(bool up, int nu) {
+  for (int d = kMaxFuse; d > 1; --d)
+    if (up ? up_fits(nu, d, kTileHalo) : down_fits(nu, d, kTileHalo)) return d;
+  return 1;
+}
 
 struct Plan {
   int64_t n = 0, n0 = 0;
   int M = 0, C = 0;
   int nu1 = 2, nu2 = 1, nsr = 1, literal = 0;
+  int d_down = 1, d_up = 1;
   int64_t S = 1, s = 0, b = 0, pad = 0;
   int seg_threads = 0;
   // workspace layout (byte offsets)
@@ -63,12 +109,14 @@ fmgsr_status make_plan(int64_t n, int32_t levels, const fmgsr_options& o, Plan* 
   p->nu2 = o.nu2;
   p->nsr = o.sr_levels;
   p->literal = (o.tau_mode == FMGSR_TAU_LITERAL);
+  p->d_down = p->literal ? 1 : fuse_depth(false, o.nu1);
+  p->d_up = p->literal ? 1 : fuse_depth(true, o.nu2);
   // coarse core top level
   int C = 0;
   while (C + 1 <= M - 1 && (n0 << (C + 1)) <= kCoreMaxCells) ++C;
   p->C = C;
   // workspace layout
-  const size_t hier = (size_t)(M >= 1 ? lvl_off_h(n0, M) : 0) * sizeof(double);  // levels 0..M-1
+  const size_t hier = (size_t)(M >= 1 ? lvl_off_ws(n0, M) : 0) * sizeof(double);  // levels 0..M-1
   size_t off = 0;
   p->off_F = off; off = align_up(off + hier);
   p->off_U = off; off = align_up(off + hier);
@@ -90,8 +138,8 @@ fmgsr_status plan_segments(int64_t n_segments, int32_t buffer, Plan* p) {
   if (s < 2 || (s & 1)) return FMGSR_EINVAL;
   const int64_t pad = ((int64_t)buffer + 2) & ~(int64_t)1;
   const int64_t cells = s + 2 * pad;
-  if (cells > (int64_t)kRun * kSegMaxThreads) return FMGSR_EINVAL;
-  const int64_t thr = (cells + kRun - 1) / kRun;
+  if (cells > (int64_t)kSegRun * kSegMaxThreads) return FMGSR_EINVAL;
+  const int64_t thr = (cells + kSegRun - 1) / kSegRun;
   p->S = n_segments;
   p->s = s;
   p->b = buffer;
@@ -153,7 +201,7 @@ struct Ctx {
   double *F, *U, *V, *Uh, *Q, *Utop;
   fmgsr_status err = FMGSR_OK;
 
-  double* lv(double* base, int l) const { return base + lvl_off_h(p->n0, l); }
+  double* lv(double* base, int l) const { return base + lvl_off_ws(p->n0, l); }
   int64_t nl(int l) const { return p->n0 << l; }
   const double* forcing(int l) const { return l == p->M ? f : lv(F, l); }
 
@@ -161,31 +209,72 @@ struct Ctx {
     if (hipGetLastError() != hipSuccess) err = FMGSR_EDEVICE;
   }
 
-  void tile_launch(bool up, int l, int nu, int src_kind, const double* src, const double* pre,
-                   const double* coarse, const double* rhs, double* out) {
-    LevelArgs a;
-    a.n = nl(l);
+  static int64_t tile_core() { return (int64_t)kRun * kTileThreads - 2 * kTileHalo; }
+
+  VertArgs vargs(int top, int levels, int nu) const {
+    VertArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = nl(top);
     a.gL = gL;
     a.gR = gR;
     a.nu = nu;
-    a.halo = std::max(2, 2 * nu);
-    a.core = (int64_t)kRun * kTileThreads - 2 * a.halo;
+    a.levels = levels;
+    a.core = tile_core();
+    a.halo = kTileHalo;
+    return a;
+  }
+
+  // Down leg over levels top..top-levels+1.
+  void down_launch(int top, int levels, int src_kind, const double* src, const double* rhs,
+                   double* top_out) {
+    VertArgs a = vargs(top, levels, p->nu1);
     a.src_kind = src_kind;
     a.src = src;
-    a.pre = pre;
-    a.coarse = coarse;
     a.rhs = rhs;
-    a.out = out;
-    const int64_t blocks = (a.n + a.core - 1) / a.core;
+    double bytes = 0.0;
+    for (int i = 0; i < levels; ++i) {
+      a.out[i] = (i == 0) ? top_out : lv(U, top - i);
+      bytes += (double)nl(top - i) * 8.0;  // U written
+    }
     const double nb = (double)a.n * 8.0;
-    const double bytes = up ? nb * 3.5  // pre, rhs, out: n each; coarse: n/2
-                            : nb * 2.0 + (src_kind == kSrcInterp ? nb * 0.5
-                                          : src_kind == kSrcRestrict ? nb * 2.0 : nb);
-    ProfScope ps(up ? "k_level_up" : "k_level_down", bytes, st);
-    if (up)
-      hipLaunchKernelGGL(k_level_up<kRun>, dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
-    else
-      hipLaunchKernelGGL(k_level_down<kRun>, dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+    bytes += nb + (src_kind == kSrcInterp ? nb * 0.5 : src_kind == kSrcRestrict ? nb * 2.0 : nb);
+    const int64_t blocks = (a.n + a.core - 1) / a.core;
+    ProfScope ps("k_down", bytes, st);
+    hipLaunchKernelGGL(k_down<kRun>, dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+    check();
+  }
+
+  // Up leg over levels top-levels+1..top; result of the top level to out.
+  void up_launch(int top, int levels, const double* rhs, const double* coarse,
+                 const double* top_pre, double* out) {
+    VertArgs a = vargs(top, levels, p->nu2);
+    a.rhs = rhs;
+    a.coarse = coarse;
+    double bytes = 0.0;
+    for (int i = 0; i < levels; ++i) {
+      a.pre[i] = (i == 0) ? top_pre : lv(U, top - i);
+      bytes += (double)nl(top - i) * 8.0;  // pre read
+    }
+    bytes += (double)a.n * 16.0 + (double)nl(top - levels) * 8.0;  // rhs, out; coarse
+    a.out[0] = out;
+    const int64_t blocks = (a.n + a.core - 1) / a.core;
+    ProfScope ps("k_up", bytes, st);
+    hipLaunchKernelGGL(k_up<kRun>, dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+    check();
+  }
+
+  // Forcing of levels src_level-1 .. src_level-levels from level src_level.
+  void forcing_launch(int src_level, int levels) {
+    VertArgs a = vargs(src_level, levels, 0);
+    a.rhs = forcing(src_level);
+    double bytes = (double)a.n * 8.0;
+    for (int i = 0; i < levels; ++i) {
+      a.out[i] = lv(F, src_level - 1 - i);
+      bytes += (double)nl(src_level - 1 - i) * 8.0;
+    }
+    const int64_t blocks = (a.n + a.core - 1) / a.core;
+    ProfScope ps("k_forcing", bytes, st);
+    hipLaunchKernelGGL(k_forcing<kRun>, dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
     check();
   }
 
@@ -200,6 +289,7 @@ struct Ctx {
 
   void core_launch(int mode, int src_kind, const double* src, const double* rhs_top) {
     CoreArgs a;
+    std::memset(&a, 0, sizeof(a));
     a.top = p->C;
     a.n0 = p->n0;
     a.gL = gL;
@@ -209,13 +299,13 @@ struct Ctx {
     a.literal = p->literal;
     a.mode = mode;
     a.src_kind = src_kind;
-    a.F = (p->M >= 1) ? F : f;
+    for (int l = 0; l <= p->C; ++l) a.F[l] = forcing(l);
     a.src = src;
     a.rhs_top = rhs_top;
     a.out = (p->M >= 1) ? lv(V, p->C) : u_out;
-    const int64_t ntot = lvl_off_h(p->n0, p->C + 1);
-    const int64_t esz = (p->C > 0) ? (p->n0 << (p->C - 1)) : 1;
-    const size_t lds = (size_t)(2 * ntot + esz + 4 * p->n0) * sizeof(double);
+    const int64_t ntot = p->n0 * (((int64_t)1 << (p->C + 1)) - 1);
+    const int64_t esz = (p->C > 0) ? (p->n0 << (p->C - 1)) : 0;
+    const size_t lds = (size_t)(2 * ntot + esz + 8 * p->n0) * sizeof(double);
     const int64_t nC = p->n0 << p->C;
     double bytes = (double)ntot * 8.0 + (double)nC * 8.0;  // forcing levels, result
     if (mode == 1) bytes += (double)nC * 8.0 * (src_kind == kSrcRestrict ? 3.0 : 2.0);
@@ -226,6 +316,7 @@ struct Ctx {
 
   void seg_launch(bool up, const double* coarse, double* out, double* q_out) {
     SegArgs a;
+    std::memset(&a, 0, sizeof(a));
     a.n = p->n;
     a.gL = gL;
     a.gR = gR;
@@ -233,6 +324,7 @@ struct Ctx {
     a.s = p->s;
     a.buffer = p->b;
     a.pad = p->pad;
+    a.win = (int)(p->s + 2 * p->pad);
     a.coarse = coarse;
     a.f = f;
     a.out = out;
@@ -240,11 +332,13 @@ struct Ctx {
     const double nb = (double)p->n * 8.0;
     // coarse n/2 and f n read; down writes n/2 (+ n/2 literal tau), up writes n
     const double bytes = up ? nb * 2.5 : nb * 2.0 + (q_out ? nb * 0.5 : 0.0);
+    const size_t lds = (size_t)p->seg_threads * (kSegRun + 1 + 4) * sizeof(double);
     ProfScope ps(up ? "k_sr_up" : "k_sr_down", bytes, st);
     if (up)
-      hipLaunchKernelGGL(k_sr_up<kRun>, dim3((unsigned)p->S), dim3(p->seg_threads), 0, st, a);
+      hipLaunchKernelGGL(k_sr_up<kSegRun>, dim3((unsigned)p->S), dim3(p->seg_threads), lds, st, a);
     else
-      hipLaunchKernelGGL(k_sr_down<kRun>, dim3((unsigned)p->S), dim3(p->seg_threads), 0, st, a);
+      hipLaunchKernelGGL(k_sr_down<kSegRun>, dim3((unsigned)p->S), dim3(p->seg_threads), lds, st,
+                         a);
     check();
   }
 
@@ -256,62 +350,52 @@ struct Ctx {
       return;
     }
     // forcing on all levels
-    for (int l = M - 1; l >= 0; --l) {
-      const int64_t nc = nl(l);
-      const int thr = 256;
-      ProfScope ps("k_restrict_fw", (double)nc * 8.0 * 3.0, st);
-      hipLaunchKernelGGL(k_restrict_fw, dim3((unsigned)((nc + thr - 1) / thr)), dim3(thr), 0, st,
-                         forcing(l + 1), nc, lv(F, l));
-      check();
-    }
+    for (int l = M; l > 0; l -= kMaxFuse) forcing_launch(l, std::min(kMaxFuse, l));
     // FMG cycles on the coarse core levels
     core_launch(0, kSrcDirect, nullptr, nullptr);
     for (int t = C + 1; t <= M && err == FMGSR_OK; ++t) {
       const bool sr = (P.nsr == 1 && t == M);
       double* Ut = (t == M) ? Utop : lv(U, t);
-      // rhs in use on level l during this step
+      auto U_of = [&](int l) -> double* { return l == t ? Ut : lv(U, l); };
+      // right-hand side in use on level l during this step
       auto rhs_of = [&](int l) -> const double* {
         if (l == t) return forcing(t);
         return P.literal ? lv(Q, l) : lv(F, l);
       };
-      int top;  // highest stored level visited below the top of the step
+      int top = t;  // highest stored level of this step
       if (sr) {
         seg_launch(false, lv(V, M - 1), Uh, P.literal ? lv(Q, M - 1) : nullptr);
         top = M - 1;
-      } else {
-        tile_launch(false, t, P.nu1, kSrcInterp, lv(V, t - 1), nullptr, nullptr, forcing(t), Ut);
-        top = t - 1;
       }
-      // pre-smoothing leg on the stored levels above the coarse core
-      for (int l = top; l >= C + 1; --l) {
-        const bool from_uh = sr && l == M - 1;
-        if (P.literal && !from_uh) {
-          const double* uf = (l + 1 == t) ? Ut : lv(U, l + 1);
-          tau_launch(uf, rhs_of(l + 1), l, lv(Q, l));
-        }
-        if (from_uh)
-          tile_launch(false, l, P.nu1, kSrcDirect, Uh, nullptr, nullptr, rhs_of(l), lv(U, l));
-        else
-          tile_launch(false, l, P.nu1, kSrcRestrict, (l + 1 == t) ? Ut : lv(U, l + 1), nullptr,
-                      nullptr, rhs_of(l), lv(U, l));
+      // pre-smoothing leg: stored levels top..C+1
+      for (int hi = top; hi >= C + 1;) {
+        const int d = std::min(P.d_down, hi - C);
+        int src_kind;
+        const double* src;
+        if (hi == t) { src_kind = kSrcInterp; src = lv(V, t - 1); }
+        else if (sr && hi == M - 1) { src_kind = kSrcDirect; src = Uh; }
+        else { src_kind = kSrcRestrict; src = U_of(hi + 1); }
+        if (P.literal && src_kind == kSrcRestrict) tau_launch(U_of(hi + 1), rhs_of(hi + 1), hi, lv(Q, hi));
+        down_launch(hi, d, src_kind, src, rhs_of(hi), U_of(hi));
+        hi -= d;
       }
       // coarse core: V-cycle bottom from level C
       if (sr && C == M - 1) {
         core_launch(1, kSrcDirect, Uh, rhs_of(C));
       } else {
-        const double* uf = (C + 1 == t) ? Ut : lv(U, C + 1);
+        const double* uf = U_of(C + 1);
         if (P.literal) tau_launch(uf, rhs_of(C + 1), C, lv(Q, C));
         core_launch(1, kSrcRestrict, uf, rhs_of(C));
       }
-      // post-smoothing leg
-      for (int l = C + 1; l <= top; ++l)
-        tile_launch(true, l, P.nu2, kSrcDirect, nullptr, lv(U, l), lv(V, l - 1), rhs_of(l),
-                    lv(V, l));
-      if (sr)
-        seg_launch(true, lv(V, M - 1), u_out, nullptr);
-      else
-        tile_launch(true, t, P.nu2, kSrcDirect, nullptr, Ut, lv(V, t - 1), forcing(t),
-                    (t == M) ? u_out : lv(V, t));
+      // post-smoothing leg: stored levels C+1..top
+      for (int lo = C + 1; lo <= top;) {
+        const int d = std::min(P.d_up, top - lo + 1);
+        const int hi = lo + d - 1;
+        double* out = (hi == top && !sr) ? ((t == M) ? u_out : lv(V, t)) : lv(V, hi);
+        up_launch(hi, d, rhs_of(hi), lv(V, lo - 1), U_of(hi), out);
+        lo += d;
+      }
+      if (sr) seg_launch(true, lv(V, M - 1), u_out, nullptr);
     }
   }
 };
@@ -367,6 +451,16 @@ fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_lef
     }
     own = true;
   }
+  static std::once_flag attr_once;
+  std::call_once(attr_once, [] {
+    (void)hipFuncSetAttribute((const void*)k_coarse_core, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    (void)hipFuncSetAttribute((const void*)k_sr_down<kSegRun>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void*)k_sr_up<kSegRun>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();
+  });
   Ctx c;
   c.p = &p;
   c.st = stream;

@@ -1,16 +1,24 @@
 // fmgsr_kernels.hpp -- gfx950 kernels of the FMG-FAS-SR solver (1D model
 // problem, FP64).  Included by fmgsr.hip only.
 //
-// Data layout.  Every level is a contiguous FP64 array in HBM.  A tile kernel
-// gives each workgroup a contiguous window of cells; each thread owns K
-// consecutive cells of the window in registers ("run").  Red-black
-// Gauss-Seidel then touches LDS only to pass one boundary value between
-// neighbouring threads per half-sweep: red cells (even index) need the left
-// neighbour's last (black) cell, black cells need the right neighbour's first
-// (red) cell.  Windows overlap by a halo of redundantly computed cells, so a
-// tile reproduces the whole-level sweep exactly on its core: after nu sweeps
-// the cells within 2 nu of a window edge are stale, the rest equal what a
-// sweep over the whole level computes (same operations on the same operands).
+// Execution model.  A tile kernel gives each workgroup a contiguous window
+// of W*K cells of a level; thread t owns the run of K consecutive cells
+// [t K, t K + K) of the window in registers.  HBM is only touched through
+// coalesced lane-per-element loops (lane i handles window cells i + k W)
+// that go through a padded LDS stage; the smoothing itself runs on the
+// register runs, and LDS only carries one boundary value per thread per
+// half-sweep: red cells (even index) need the left neighbour's last cell,
+// black cells the right neighbour's first.
+//
+// Vertical processing (Sec. 1, Sec. 3: the multigrid cycle is walked
+// "vertically" through each patch).  A down kernel starts from the window
+// of its top level, smooths, restricts the run in registers (I^ of the
+// iterate, full weighting of the right-hand side) and continues on the next
+// coarser level with half-length runs, writing every level's core once.  An
+// up kernel walks the same levels bottom-up and writes only its top level.
+// Windows overlap by a halo that absorbs the cells made stale by the window
+// edge (the host sizes it), so every core value equals what a sweep over
+// the whole level computes: same operations on the same operands.
 //
 // Stencils (Sec. 4; appendix operator assembly), level with n cells, h = 1/n,
 // Dirichlet values gL, gR entering through odd reflections about the faces:
@@ -22,7 +30,7 @@
 //   I  (rhs, FW)   ((r_{2J-1} + r_{2J+2}) + 3 (r_{2J} + r_{2J+1})) / 8
 //   P  (correction) child 2J: (3 e_J + e_{J-1}) / 4, child 2J+1 mirrored
 // Each is one fixed expression tree; the library is built without FMA
-// contraction so that the results are reproducible operation by operation.
+// contraction so that results are reproducible operation by operation.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,9 +38,12 @@
 
 namespace fmgsr {
 
-constexpr int kRun = 16;          // cells per thread in tile kernels
-constexpr int kTileThreads = 256; // threads per stored-level tile
-constexpr int kSegMaxThreads = 512;
+constexpr int kRun = 16;           // cells per thread at the top of a tile
+constexpr int kTileThreads = 256;  // threads per stored-level tile
+constexpr int kMaxFuse = 4;        // levels per vertical kernel
+constexpr int kTileHalo = 64;      // window halo (cells of the top level)
+constexpr int kSegRun = 8;         // cells per thread on the SR level
+constexpr int kSegMaxThreads = 1024;
 
 // ---------------------------------------------------------------------------
 // Small helpers
@@ -76,200 +87,424 @@ __device__ __forceinline__ double relax(double fj, double l, double r, int64_t g
 }
 
 // ---------------------------------------------------------------------------
-// Register runs
+// Neighbour exchange: each thread publishes its first and last value and
+// reads its left neighbour's last and right neighbour's first.  Two LDS
+// buffers are used alternately, so one barrier per exchange suffices.
 // ---------------------------------------------------------------------------
-
-// One half-sweep of colour C (0 = red = even index) over the run
-// u[0..K) = cells g0..g0+K-1 (g0 even), updating only cells in [lo, hi).
-// xbuf: one LDS slot per thread, a different buffer per colour so that a
-// single barrier per half-sweep suffices.
-template <int K, int C>
-__device__ __forceinline__ void rb_half(double (&u)[K], const double (&f)[K], int64_t g0,
-                                        int64_t lo, int64_t hi, int64_t n, double h2,
-                                        double gL2, double gR2, double* xbuf) {
-  const int t = threadIdx.x;
-  xbuf[t] = (C == 0) ? u[K - 1] : u[0];
-  __syncthreads();
-  double nb = 0.0;
-  if (C == 0) {
-    if (t > 0) nb = xbuf[t - 1];
-  } else {
-    if (t + 1 < (int)blockDim.x) nb = xbuf[t + 1];
+struct Xch {
+  double* buf;  // 4 * W doubles
+  int sel;
+  __device__ void swap(double first, double last, double& left_last, double& right_first) {
+    const int W = blockDim.x, t = threadIdx.x;
+    double* b = buf + (sel ? 2 * W : 0);
+    sel ^= 1;
+    b[t] = first;
+    b[W + t] = last;
+    __syncthreads();
+    left_last = (t > 0) ? b[W + t - 1] : 0.0;
+    right_first = (t + 1 < W) ? b[t + 1] : 0.0;
   }
+};
+
+// Per-run bounds in 32-bit local indices (0..K): updatable cells [jlo, jhi)
+// and the run positions of the first and last cell of the level (-1 if the
+// run does not hold them).
+struct RunBounds {
+  int jlo, jhi, jb0, jbn;
+};
+
+__device__ __forceinline__ RunBounds run_bounds(int64_t g0, int K, int64_t lo, int64_t hi,
+                                                int64_t n) {
+  RunBounds b;
+  const int64_t a = lo - g0, c = hi - g0, z = -g0, e = n - 1 - g0;
+  b.jlo = (int)(a < 0 ? 0 : (a > K ? K : a));
+  b.jhi = (int)(c < 0 ? 0 : (c > K ? K : c));
+  b.jb0 = (z >= 0 && z < K) ? (int)z : -1;
+  b.jbn = (e >= 0 && e < K) ? (int)e : -1;
+  return b;
+}
+
+// One half-sweep of colour C (0 = red = even index) over the run u[0..K)
+// (first cell even), updating the cells [jlo, jhi) of the run.
+template <int K, int C>
+__device__ __forceinline__ void rb_half(double (&u)[K], const double (&f)[K], const RunBounds& rb,
+                                        double h2, double gL2, double gR2, double bdiv, Xch& x) {
+  double ll, rf;
+  x.swap(u[0], u[K - 1], ll, rf);
 #pragma unroll
   for (int j = C; j < K; j += 2) {
-    const int64_t g = g0 + j;
-    const double l = (j == 0) ? nb : u[j - 1];
-    const double r = (j == K - 1) ? nb : u[j + 1];
-    if (g >= lo && g < hi) u[j] = relax(f[j], l, r, g, n, h2, gL2, gR2);
+    double l = (j == 0) ? ll : u[j - 1];
+    double r = (j == K - 1) ? rf : u[j + 1];
+    double v;
+    if (j != rb.jb0 && j != rb.jbn) {
+      v = (f[j] * h2 + (l + r)) * 0.5;
+    } else {
+      if (j == rb.jb0) l = gL2;
+      if (j == rb.jbn) r = gR2;
+      v = (f[j] * h2 + (l + r)) / bdiv;
+    }
+    if (j >= rb.jlo && j < rb.jhi) u[j] = v;
   }
 }
 
 template <int K>
 __device__ __forceinline__ void rb_sweeps(double (&u)[K], const double (&f)[K], int64_t g0,
                                           int nu, int64_t lo, int64_t hi, int64_t n,
-                                          double gL, double gR, double* xr, double* xb) {
+                                          double gL, double gR, Xch& x) {
   const double h2 = 1.0 / ((double)n * (double)n);
   const double gL2 = 2.0 * gL, gR2 = 2.0 * gR;
+  const double bdiv = (n == 1) ? 4.0 : 3.0;
+  const RunBounds rb = run_bounds(g0, K, lo, hi, n);
   for (int s = 0; s < nu; ++s) {
-    rb_half<K, 0>(u, f, g0, lo, hi, n, h2, gL2, gR2, xr);
-    rb_half<K, 1>(u, f, g0, lo, hi, n, h2, gL2, gR2, xb);
-  }
-}
-
-// u <- Pi c on the run (cells outside [0,n) are set to 0 and never used).
-template <int K>
-__device__ __forceinline__ void load_interp(double (&u)[K], int64_t g0, int64_t n,
-                                            const double* __restrict__ c, double gL, double gR) {
-  const int64_t nc = n >> 1;
-  const int64_t J0 = g0 >> 1;  // g0 even (also when negative)
-  double cv[K / 2 + 4];
-#pragma unroll
-  for (int q = 0; q < K / 2 + 4; ++q) {
-    const int64_t J = J0 - 2 + q;
-    cv[q] = (J >= -2 && J <= nc + 1) ? coarse_at(c, nc, J, gL, gR) : 0.0;
-  }
-#pragma unroll
-  for (int p = 0; p < K / 2; ++p) {
-    const int64_t g = g0 + 2 * p;
-    const bool in = (g >= 0 && g < n);
-    u[2 * p] = in ? interp_even(cv[p], cv[p + 1], cv[p + 2], cv[p + 3]) : 0.0;
-    u[2 * p + 1] = in ? interp_odd(cv[p + 1], cv[p + 2], cv[p + 3], cv[p + 4]) : 0.0;
-  }
-}
-
-// u <- I^ fine (two-cell average of the finer level).
-template <int K>
-__device__ __forceinline__ void load_restrict(double (&u)[K], int64_t g0, int64_t n,
-                                              const double* __restrict__ fine) {
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    const int64_t g = g0 + j;
-    u[j] = (g >= 0 && g < n) ? (fine[2 * g] + fine[2 * g + 1]) * 0.5 : 0.0;
-  }
-}
-
-template <int K>
-__device__ __forceinline__ void load_direct(double (&u)[K], int64_t g0, int64_t n,
-                                            const double* __restrict__ src) {
-#pragma unroll
-  for (int j = 0; j < K; ++j) u[j] = ld(src, g0 + j, n);
-}
-
-template <int K>
-__device__ __forceinline__ void store_range(const double (&u)[K], int64_t g0, int64_t lo,
-                                            int64_t hi, double* __restrict__ out) {
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    const int64_t g = g0 + j;
-    if (g >= lo && g < hi) out[g] = u[j];
+    rb_half<K, 0>(u, f, rb, h2, gL2, gR2, bdiv, x);
+    rb_half<K, 1>(u, f, rb, h2, gL2, gR2, bdiv, x);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Stored-level visits
+// LDS stage: window cell e lives at e + e / K (one pad slot per run, so a
+// thread reading its run and lanes walking consecutive cells are both free
+// of bank conflicts).
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ int sidx(int e) { return e + e / K; }
+
+// stage -> registers: thread t takes cells [t K, t K + K)
+template <int K>
+__device__ __forceinline__ void stage_to_run(const double* st, double (&v)[K]) {
+  const int base = threadIdx.x * (K + 1);
+#pragma unroll
+  for (int j = 0; j < K; ++j) v[j] = st[base + j];
+}
+template <int K>
+__device__ __forceinline__ void run_to_stage(double* st, const double (&v)[K]) {
+  const int base = threadIdx.x * (K + 1);
+#pragma unroll
+  for (int j = 0; j < K; ++j) st[base + j] = v[j];
+}
+
+// Coalesced load of window cells [0, W K) (cell e = global wlo + e, valid
+// while e < wcount) into registers through the stage: v = val(global index)
+// for cells in [0, n), 0 elsewhere.  All K loads are issued unconditionally
+// (at a clamped, in-range index) before any is consumed, so their latencies
+// overlap; the validity test only selects the value.
+template <int K, class Fn>
+__device__ __forceinline__ void load_run(double* st, double (&v)[K], int64_t wlo, int wcount,
+                                         int64_t n, Fn val) {
+  const int W = blockDim.x;
+  double tmp[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t g = wlo + threadIdx.x + k * W;
+    tmp[k] = val(g < 0 ? 0 : (g >= n ? n - 1 : g));
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = threadIdx.x + k * W;
+    const int64_t g = wlo + e;
+    st[sidx<K>(e)] = (e < wcount && g >= 0 && g < n) ? tmp[k] : 0.0;
+  }
+  __syncthreads();
+  stage_to_run<K>(st, v);
+  __syncthreads();
+}
+
+// Registers -> coalesced store of window cells whose global index lies in
+// [lo, hi).
+template <int K>
+__device__ __forceinline__ void store_run(double* st, const double (&v)[K], int64_t wlo,
+                                          int64_t lo, int64_t hi, double* __restrict__ out) {
+  const int W = blockDim.x;
+  run_to_stage<K>(st, v);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = threadIdx.x + k * W;
+    const int64_t g = wlo + e;
+    if (g >= lo && g < hi) out[g] = st[sidx<K>(e)];
+  }
+  __syncthreads();
+}
+
+// Pi of the coarse level into the runs.  The coarse cells under the run,
+// c[0..K/2) = J0..J0+K/2-1, arrive as one coalesced load; the two coarse
+// values on each side come from the neighbouring threads (window-edge
+// threads read them from HBM), so Pi is exact on the whole window.  Cells
+// beyond the domain use the Dirichlet reflections (nested for a one-cell
+// level), cells outside [0, n) are set to 0.
+template <int K>
+__device__ __forceinline__ void interp_from_run(double (&u)[K], const double (&c)[K / 2],
+                                                int64_t g0, int64_t n,
+                                                const double* __restrict__ cg, double gL,
+                                                double gR, Xch& x) {
+  const int64_t nc = n >> 1;
+  const int64_t J0 = g0 >> 1;
+  double l1, r0, l2, r1;
+  x.swap(c[0], c[K / 2 - 1], l1, r0);
+  x.swap(c[1], c[K / 2 - 2], l2, r1);
+  auto at = [&](int64_t j) { return cg[j < 0 ? 0 : (j >= nc ? nc - 1 : j)]; };
+  if (threadIdx.x == 0) { l2 = at(J0 - 2); l1 = at(J0 - 1); }
+  if (threadIdx.x == blockDim.x - 1) { r0 = at(J0 + K / 2); r1 = at(J0 + K / 2 + 1); }
+  double e[K / 2 + 4];  // coarse J0-2 .. J0+K/2+1
+  e[0] = l2;
+  e[1] = l1;
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) e[p + 2] = c[p];
+  e[K / 2 + 2] = r0;
+  e[K / 2 + 3] = r1;
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) {
+    const int64_t J = J0 + p;
+    const double r0p = e[p + 2];
+    const double vm1 = (J >= 1) ? e[p + 1] : 2.0 * gL - r0p;
+    const double vp1 = (J + 1 < nc) ? e[p + 3] : 2.0 * gR - r0p;
+    const double vm2 = (J >= 2) ? e[p] : ((J == 1) ? 2.0 * gL - e[p + 1] : 2.0 * gL - vp1);
+    const double vp2 = (J + 2 < nc) ? e[p + 4] : ((J + 2 == nc) ? 2.0 * gR - e[p + 3] : 2.0 * gR - vm1);
+    const bool in = (J >= 0 && J < nc);
+    u[2 * p] = in ? interp_even(vm2, vm1, r0p, vp1) : 0.0;
+    u[2 * p + 1] = in ? interp_odd(vm1, r0p, vp1, vp2) : 0.0;
+  }
+}
+
+// Pi of the coarse level into the window (coarse run loaded here).
+template <int K>
+__device__ __forceinline__ void load_interp_run(double* st, double (&v)[K], int64_t wlo,
+                                                int wcount, int64_t n,
+                                                const double* __restrict__ c, double gL,
+                                                double gR, Xch& x) {
+  // coarse cells under the window plus the two the last valid pairs reach
+  double cr[K / 2];
+  load_run<K / 2>(st, cr, wlo >> 1, (wcount + 1) / 2 + 2, n >> 1, [&](int64_t J) { return c[J]; });
+  interp_from_run<K>(v, cr, wlo + (int64_t)threadIdx.x * K, n, c, gL, gR, x);
+}
+
+// I^ of the finer level (pairs read as one 16-byte load) into the window.
+template <int K>
+__device__ __forceinline__ void load_restrict_run(double* st, double (&v)[K], int64_t wlo,
+                                                  int wcount, int64_t n,
+                                                  const double* __restrict__ fine) {
+  const double2* __restrict__ f2 = reinterpret_cast<const double2*>(fine);
+  load_run<K>(st, v, wlo, wcount, n, [&](int64_t g) {
+    const double2 p = f2[g];
+    return (p.x + p.y) * 0.5;
+  });
+}
+
+// In-register restriction of a run to the next coarser level:
+// u1 = I^ u (local pairs), f1 = I f (full weighting; needs the neighbours'
+// edge values).  g0 is the global index of u[0] on the finer level (nf cells).
+template <int K>
+__device__ __forceinline__ void restrict_runs(const double (&u)[K], const double (&f)[K],
+                                              double (&u1)[K / 2], double (&f1)[K / 2],
+                                              int64_t g0, int64_t nf, Xch& x) {
+  double fl, fr;
+  x.swap(f[0], f[K - 1], fl, fr);
+  const RunBounds rb = run_bounds(g0, K, 0, nf, nf);
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) {
+    u1[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
+    double rm = (p == 0) ? fl : f[2 * p - 1];
+    double rp = (p == K / 2 - 1) ? fr : f[2 * p + 2];
+    if (2 * p == rb.jb0) rm = -f[2 * p];
+    if (2 * p + 1 == rb.jbn) rp = -f[2 * p + 1];
+    f1[p] = ((rm + rp) + 3.0 * (f[2 * p] + f[2 * p + 1])) * 0.125;
+  }
+}
+
+// Same full weighting for a right-hand side only.
+template <int K>
+__device__ __forceinline__ void restrict_rhs_run(const double (&f)[K], double (&f1)[K / 2],
+                                                 int64_t g0, int64_t nf, Xch& x) {
+  double fl, fr;
+  x.swap(f[0], f[K - 1], fl, fr);
+  const RunBounds rb = run_bounds(g0, K, 0, nf, nf);
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) {
+    double rm = (p == 0) ? fl : f[2 * p - 1];
+    double rp = (p == K / 2 - 1) ? fr : f[2 * p + 2];
+    if (2 * p == rb.jb0) rm = -f[2 * p];
+    if (2 * p + 1 == rb.jbn) rp = -f[2 * p + 1];
+    f1[p] = ((rm + rp) + 3.0 * (f[2 * p] + f[2 * p + 1])) * 0.125;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stored levels: vertical down / up kernels
 // ---------------------------------------------------------------------------
 
 enum SourceKind : int { kSrcInterp = 0, kSrcRestrict = 1, kSrcDirect = 2 };
 
-struct LevelArgs {
-  int64_t n;          // cells on this level
+struct VertArgs {
+  int64_t n;             // cells on the top level of this kernel
   double gL, gR;
-  int nu;             // sweeps
-  int64_t core;       // core cells per workgroup
-  int64_t halo;       // halo cells on each side (even, >= 2 nu)
-  int src_kind;       // down visit: how the initial iterate is formed
-  const double* src;  // down: coarser (Pi), finer (I^) or same-level array
-  const double* pre;  // up: pre-smoothed iterate of this level
-  const double* coarse;  // up: post-smoothed coarser level
-  const double* rhs;  // right-hand side of this level
-  double* out;        // result on the cores
+  int nu;                // sweeps per level
+  int levels;            // levels walked by this kernel (1..kMaxFuse)
+  int64_t core;          // top-level core cells per workgroup (divisible by 2^kMaxFuse)
+  int64_t halo;          // top-level halo (divisible by 2^kMaxFuse)
+  int src_kind;          // down: how the top-level iterate starts
+  const double* src;     // down: coarser (Pi), finer (I^) or same-level array
+  const double* rhs;     // right-hand side of the top level
+  const double* coarse;  // up: post-smoothed level below the bottom level
+  const double* pre[kMaxFuse];  // up: pre-smoothed iterates, index = levels below top
+  double* out[kMaxFuse];        // down: U of each level; up: out[0] = top result
 };
 
-// Down visit of a stored level (Fig. 3 steps 1-2, or restrict + smooth of
-// the pre-smoothing leg): initial iterate from Pi / I^ / a copy, nu sweeps.
-template <int K>
-__global__ __launch_bounds__(kTileThreads) void k_level_down(LevelArgs a) {
-  __shared__ double xr[kTileThreads], xb[kTileThreads];
-  const int64_t tile_lo = (int64_t)blockIdx.x * a.core - a.halo;
-  const int64_t tile_hi = tile_lo + (int64_t)blockDim.x * K;
-  const int64_t g0 = tile_lo + (int64_t)threadIdx.x * K;
-  double u[K], f[K];
-#pragma unroll
-  for (int j = 0; j < K; ++j) f[j] = ld(a.rhs, g0 + j, a.n);
-  if (a.src_kind == kSrcInterp) load_interp<K>(u, g0, a.n, a.src, a.gL, a.gR);
-  else if (a.src_kind == kSrcRestrict) load_restrict<K>(u, g0, a.n, a.src);
-  else load_direct<K>(u, g0, a.n, a.src);
-  const int64_t lo = tile_lo <= 0 ? 0 : tile_lo + 1;
-  const int64_t hi = tile_hi >= a.n ? a.n : tile_hi - 1;
-  rb_sweeps<K>(u, f, g0, a.nu, lo, hi, a.n, a.gL, a.gR, xr, xb);
-  const int64_t clo = (int64_t)blockIdx.x * a.core;
-  const int64_t chi = (clo + a.core < a.n) ? clo + a.core : a.n;
-  store_range<K>(u, g0, clo, chi, a.out);
+struct TileGeom {
+  int64_t wlo;   // window start on this level
+  int64_t g0;    // first cell of this thread's run
+  int64_t lo, hi;  // updatable cells
+  int64_t clo, chi;  // core cells (clipped)
+  int64_t n;
+};
+
+__device__ __forceinline__ TileGeom tile_geom(const VertArgs& a, int i, int K) {
+  TileGeom g;
+  g.n = a.n >> i;
+  const int64_t W = blockDim.x;
+  g.wlo = ((int64_t)blockIdx.x * a.core - a.halo) >> i;
+  const int64_t whi = g.wlo + W * K;
+  g.g0 = g.wlo + (int64_t)threadIdx.x * K;
+  g.lo = g.wlo <= 0 ? 0 : g.wlo + 1;
+  g.hi = whi >= g.n ? g.n : whi - 1;
+  g.clo = ((int64_t)blockIdx.x * a.core) >> i;
+  const int64_t c1 = ((int64_t)blockIdx.x * a.core + a.core) >> i;
+  g.chi = c1 < g.n ? c1 : g.n;
+  return g;
 }
 
-// Up visit of a stored level (Fig. 3 post-smoothing leg, Eq. 4):
-// u = pre + P(coarse - I^ pre), then nu sweeps.
+template <int K, int I>
+__device__ void down_level(const VertArgs& a, double* st, Xch& x, double (&u)[K],
+                           const double (&f)[K]) {
+  const TileGeom G = tile_geom(a, I, K);
+  rb_sweeps<K>(u, f, G.g0, a.nu, G.lo, G.hi, G.n, a.gL, a.gR, x);
+  store_run<K>(st, u, G.wlo, G.clo, G.chi, a.out[I]);
+  if constexpr (I + 1 < kMaxFuse && K >= 4) {
+    if (I + 1 < a.levels) {
+      double u1[K / 2], f1[K / 2];
+      restrict_runs<K>(u, f, u1, f1, G.g0, G.n, x);
+      down_level<K / 2, I + 1>(a, st, x, u1, f1);
+    }
+  }
+}
+
+// Down leg over `levels` stored levels (Fig. 3 steps 1-2 on the top level,
+// then restrict + smooth of the pre-smoothing leg), split tau: the coarse
+// right-hand side is the full weighting of the finer one (the Laplacian
+// part of tau is identically zero with I^ = average, I = full weighting).
 template <int K>
-__global__ __launch_bounds__(kTileThreads) void k_level_up(LevelArgs a) {
-  __shared__ double xr[kTileThreads], xb[kTileThreads];
-  const int64_t n = a.n, nc = n >> 1;
-  const int64_t tile_lo = (int64_t)blockIdx.x * a.core - a.halo;
-  const int64_t tile_hi = tile_lo + (int64_t)blockDim.x * K;
-  const int64_t g0 = tile_lo + (int64_t)threadIdx.x * K;
-  const int64_t J0 = g0 >> 1;
+__global__ __launch_bounds__(kTileThreads) void k_down(VertArgs a) {
+  __shared__ double st[kTileThreads * (K + 1)];
+  __shared__ double xb[4 * kTileThreads];
+  Xch x{xb, 0};
+  const int wcount = kTileThreads * K;
+  const TileGeom G = tile_geom(a, 0, K);
   double u[K], f[K];
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    f[j] = ld(a.rhs, g0 + j, n);
-    u[j] = ld(a.pre, g0 + j, n);
+  load_run<K>(st, f, G.wlo, wcount, G.n, [&](int64_t g) { return a.rhs[g]; });
+  if (a.src_kind == kSrcInterp)
+    load_interp_run<K>(st, u, G.wlo, wcount, G.n, a.src, a.gL, a.gR, x);
+  else if (a.src_kind == kSrcRestrict)
+    load_restrict_run<K>(st, u, G.wlo, wcount, G.n, a.src);
+  else
+    load_run<K>(st, u, G.wlo, wcount, G.n, [&](int64_t g) { return a.src[g]; });
+  down_level<K, 0>(a, st, x, u, f);
+}
+
+// Up leg, level I of the kernel (I = 0 is the top).  On entry f holds this
+// level's right-hand side; on return u holds its post-smoothed iterate.
+template <int K, int I>
+__device__ void up_level(const VertArgs& a, double* st, Xch& x, const double (&f)[K],
+                         double (&u)[K]) {
+  const TileGeom G = tile_geom(a, I, K);
+  const int wcount = (int)blockDim.x * K;
+  const int64_t nc = G.n >> 1;
+  double c[K / 2];  // post-smoothed coarse iterate of this run's pairs
+  bool done = false;
+  if constexpr (I + 1 < kMaxFuse && K >= 4) {
+    if (I + 1 < a.levels) {
+      double f1[K / 2];
+      restrict_rhs_run<K>(f, f1, G.g0, G.n, x);
+      up_level<K / 2, I + 1>(a, st, x, f1, c);
+      done = true;
+    }
   }
-  // coarse error e_J = c_J - I^ pre, for J0-1 .. J0+K/2
-  double e[K / 2 + 2];
-#pragma unroll
-  for (int q = 0; q < K / 2 + 2; ++q) {
-    const int64_t J = J0 - 1 + q;
-    double p0, p1;
-    if (q == 0) { p0 = ld(a.pre, g0 - 2, n); p1 = ld(a.pre, g0 - 1, n); }
-    else if (q == K / 2 + 1) { p0 = ld(a.pre, g0 + K, n); p1 = ld(a.pre, g0 + K + 1, n); }
-    else { p0 = u[2 * (q - 1)]; p1 = u[2 * (q - 1) + 1]; }
-    e[q] = (J >= 0 && J < nc) ? a.coarse[J] - (p0 + p1) * 0.5 : 0.0;
+  if (!done) {
+    // bottom of the kernel: coarse iterate from HBM (coalesced via the stage)
+    const int64_t cwlo = G.wlo >> 1;
+    load_run<K / 2>(st, c, cwlo, wcount / 2, nc, [&](int64_t J) { return a.coarse[J]; });
   }
+  // correction (Eq. 4): u = pre + P(c - I^ pre)
+  load_run<K>(st, u, G.wlo, wcount, G.n, [&](int64_t g) { return a.pre[I][g]; });
+  double e[K / 2];
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) e[p] = c[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
+  double el, er;
+  x.swap(e[0], e[K / 2 - 1], el, er);
+  // pairs of the run inside the level, and the first / last pair of the level
+  const RunBounds pb = run_bounds(G.g0 >> 1, K / 2, 0, nc, nc);
 #pragma unroll
   for (int p = 0; p < K / 2; ++p) {
-    const int64_t J = J0 + p;
-    if (J >= 0 && J < nc) {
-      const double eJ = e[p + 1];
-      const double em = (J > 0) ? e[p] : -eJ;
-      const double ep = (J < nc - 1) ? e[p + 2] : -eJ;
+    if (p >= pb.jlo && p < pb.jhi) {
+      const double eJ = e[p];
+      const double em = (p != pb.jb0) ? ((p == 0) ? el : e[p - 1]) : -eJ;
+      const double ep = (p != pb.jbn) ? ((p == K / 2 - 1) ? er : e[p + 1]) : -eJ;
       u[2 * p] = u[2 * p] + (3.0 * eJ + em) * 0.25;
       u[2 * p + 1] = u[2 * p + 1] + (3.0 * eJ + ep) * 0.25;
     }
   }
-  const int64_t lo = tile_lo <= 0 ? 0 : tile_lo + 1;
-  const int64_t hi = tile_hi >= n ? n : tile_hi - 1;
-  rb_sweeps<K>(u, f, g0, a.nu, lo, hi, n, a.gL, a.gR, xr, xb);
-  const int64_t clo = (int64_t)blockIdx.x * a.core;
-  const int64_t chi = (clo + a.core < n) ? clo + a.core : n;
-  store_range<K>(u, g0, clo, chi, a.out);
+  rb_sweeps<K>(u, f, G.g0, a.nu, G.lo, G.hi, G.n, a.gL, a.gR, x);
+}
+
+// Up leg over `levels` stored levels, bottom-up (Fig. 3 post-smoothing leg,
+// Eq. 4); only the top level's core is written.  Lower right-hand sides are
+// the full weighting of the top one (split tau).
+template <int K>
+__global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
+  __shared__ double st[kTileThreads * (K + 1)];
+  __shared__ double xb[4 * kTileThreads];
+  Xch x{xb, 0};
+  const int wcount = kTileThreads * K;
+  const TileGeom G = tile_geom(a, 0, K);
+  double u[K], f[K];
+  load_run<K>(st, f, G.wlo, wcount, G.n, [&](int64_t g) { return a.rhs[g]; });
+  up_level<K, 0>(a, st, x, f, u);
+  store_run<K>(st, u, G.wlo, G.clo, G.chi, a.out[0]);
 }
 
 // ---------------------------------------------------------------------------
-// Full-weighting restriction of the forcing (rhs hierarchy) and literal tau
+// Forcing hierarchy: up to kMaxFuse full-weighting restrictions per launch
 // ---------------------------------------------------------------------------
 
-// out[J] = I fine, J < nc.
-__global__ void k_restrict_fw(const double* __restrict__ fine, int64_t nc, double* __restrict__ out) {
-  const int64_t J = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (J >= nc) return;
-  const int64_t nf = 2 * nc;
-  const double rm = (J > 0) ? fine[2 * J - 1] : -fine[0];
-  const double rp = (2 * J + 2 < nf) ? fine[2 * J + 2] : -fine[nf - 1];
-  out[J] = ((rm + rp) + 3.0 * (fine[2 * J] + fine[2 * J + 1])) * 0.125;
+template <int K, int I>
+__device__ void forcing_level(const VertArgs& a, double* st, Xch& x, const double (&f)[K]) {
+  // f holds level I (I >= 1 are written); the next level is its restriction
+  const TileGeom G = tile_geom(a, I, K);
+  if constexpr (I > 0) store_run<K>(st, f, G.wlo, G.clo, G.chi, a.out[I - 1]);
+  if constexpr (I < kMaxFuse && K >= 2) {
+    if (I < a.levels) {
+      double f1[K / 2];
+      restrict_rhs_run<K>(f, f1, G.g0, G.n, x);
+      forcing_level<K / 2, I + 1>(a, st, x, f1);
+    }
+  }
 }
 
-// FAS coarse right-hand side, literal Eq. 7 assembled over a stored level:
-//   Q_H = I(F_h - L_h u) + L_H(I^ u),  for J < nc.
+// a.rhs: level with a.n cells; writes a.levels coarser levels into
+// out[0..levels) (out[i] = level i+1 below).
+template <int K>
+__global__ __launch_bounds__(kTileThreads) void k_forcing(VertArgs a) {
+  __shared__ double st[kTileThreads * (K + 1)];
+  __shared__ double xb[4 * kTileThreads];
+  Xch x{xb, 0};
+  const TileGeom G = tile_geom(a, 0, K);
+  double f[K];
+  load_run<K>(st, f, G.wlo, kTileThreads * K, G.n, [&](int64_t g) { return a.rhs[g]; });
+  forcing_level<K, 0>(a, st, x, f);
+}
+
+// ---------------------------------------------------------------------------
+// Literal tau (Eq. 7) on a stored level: Q_H = I(F_h - L_h u) + L_H(I^ u)
+// ---------------------------------------------------------------------------
+
 __device__ __forceinline__ double fine_residual(const double* __restrict__ u,
                                                 const double* __restrict__ F, int64_t k,
                                                 int64_t nf, double w, double gL, double gR) {
@@ -297,18 +532,19 @@ __global__ void k_tau_literal(const double* __restrict__ u, const double* __rest
 
 // ---------------------------------------------------------------------------
 // SR level: segments with buffers (Sec. 3, Fig. 3; compatible relaxation
-// Sec. 3.1, Fig. 5).  One workgroup per segment; the window starts `pad`
+// Sec. 3.1, Fig. 5).  One workgroup per segment; its window starts `pad`
 // cells left of the core (pad even, >= buffer + 1) so the frozen neighbours
-// of the extended patch are inside it.
+// of the extended patch are inside it; cells past the window are dead.
 // ---------------------------------------------------------------------------
 
 struct SegArgs {
-  int64_t n;           // fine cells
+  int64_t n;             // fine cells
   double gL, gR;
   int nu;
-  int64_t s;           // core cells per segment
-  int64_t buffer;      // buffer cells per side
-  int64_t pad;         // window offset left of the core
+  int64_t s;             // core cells per segment
+  int64_t buffer;        // buffer cells per side
+  int64_t pad;           // window offset left of the core
+  int win;               // window cells actually used (s + 2 pad)
   const double* coarse;  // level n/2 iterate (Pi source; Kaczmarz target)
   const double* f;       // fine right-hand side
   double* out;           // down: I^ of the smoothed cores [n/2]; up: u_out [n]
@@ -317,68 +553,68 @@ struct SegArgs {
 
 // Down pass (Fig. 3 steps 1-5 fused): Pi, nu sweeps on the extended patch,
 // then I^ (and literal tau) on the core's coarse cells.  The fine iterate
-// never leaves registers.
+// never leaves the chip.
 template <int K>
 __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
-  __shared__ double xr[kSegMaxThreads], xb[kSegMaxThreads];
-  __shared__ double xl2[2 * kSegMaxThreads], xr2[2 * kSegMaxThreads];
-  const int64_t n = a.n;
+  extern __shared__ double sm[];
+  const int W = blockDim.x;
+  double* st = sm;                   // W (K+1)
+  Xch x{sm + W * (K + 1), 0};        // 4 W
+  const int64_t n = a.n, nc = n >> 1;
   const int64_t seg = blockIdx.x;
   const int64_t core_lo = seg * a.s, core_hi = core_lo + a.s;
-  const int64_t tile_lo = core_lo - a.pad;
-  const int64_t g0 = tile_lo + (int64_t)threadIdx.x * K;
+  const int64_t wlo = core_lo - a.pad;
+  const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
   double u[K], f[K];
-#pragma unroll
-  for (int j = 0; j < K; ++j) f[j] = ld(a.f, g0 + j, n);
-  load_interp<K>(u, g0, n, a.coarse, a.gL, a.gR);
+  load_run<K>(st, f, wlo, a.win, n, [&](int64_t g) { return a.f[g]; });
+  load_interp_run<K>(st, u, wlo, a.win, n, a.coarse, a.gL, a.gR, x);
   const int64_t lo = (core_lo - a.buffer > 0) ? core_lo - a.buffer : 0;
   const int64_t hi = (core_hi + a.buffer < n) ? core_hi + a.buffer : n;
-  rb_sweeps<K>(u, f, g0, a.nu, lo, hi, n, a.gL, a.gR, xr, xb);
+  rb_sweeps<K>(u, f, g0, a.nu, lo, hi, n, a.gL, a.gR, x);
+  double uc[K / 2];
 #pragma unroll
-  for (int p = 0; p < K / 2; ++p) {
-    const int64_t g = g0 + 2 * p;
-    if (g >= core_lo && g < core_hi) a.out[g >> 1] = (u[2 * p] + u[2 * p + 1]) * 0.5;
-  }
+  for (int p = 0; p < K / 2; ++p) uc[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
+  store_run<K / 2>(st, uc, wlo >> 1, core_lo >> 1, core_hi >> 1, a.out);
   if (a.q_out == nullptr) return;  // uniform per launch
-  // Literal tau per patch: needs two cells beyond the run on each side.
-  const int t = threadIdx.x;
-  xl2[2 * t] = u[K - 2];
-  xl2[2 * t + 1] = u[K - 1];
-  xr2[2 * t] = u[0];
-  xr2[2 * t + 1] = u[1];
-  __syncthreads();
+  // Literal tau per patch: two cells beyond the run on each side.
+  double l1, r0, l2, r1;
+  x.swap(u[0], u[K - 1], l1, r0);
+  x.swap(u[1], u[K - 2], l2, r1);
   double w[K + 4];
-  w[0] = (t > 0) ? xl2[2 * (t - 1)] : 0.0;
-  w[1] = (t > 0) ? xl2[2 * (t - 1) + 1] : 0.0;
+  w[0] = l2;
+  w[1] = l1;
 #pragma unroll
   for (int j = 0; j < K; ++j) w[j + 2] = u[j];
-  w[K + 2] = (t + 1 < (int)blockDim.x) ? xr2[2 * (t + 1)] : 0.0;
-  w[K + 3] = (t + 1 < (int)blockDim.x) ? xr2[2 * (t + 1) + 1] : 0.0;
-  const int64_t nc = n >> 1;
+  w[K + 2] = r0;
+  w[K + 3] = r1;
   const double wf = (double)n * (double)n, wc = (double)nc * (double)nc;
   const double gL = a.gL, gR = a.gR;
-  // w[m] holds cell g0 - 2 + m.  Residual F - L w at local offset m (cell k).
+  // w[m] holds cell g0 - 2 + m.  Residual F - L w at offset m.
   auto res = [&](int m) -> double {
     const int64_t k = g0 - 2 + m;
     const double l = (k > 0) ? w[m - 1] : 2.0 * gL - w[m];
     const double r = (k < n - 1) ? w[m + 1] : 2.0 * gR - w[m];
     return ld(a.f, k, n) - (2.0 * w[m] - (l + r)) * wf;
   };
+  double q[K / 2];
 #pragma unroll
   for (int p = 0; p < K / 2; ++p) {
     const int64_t g = g0 + 2 * p;
-    if (!(g >= core_lo && g < core_hi)) continue;
     const int64_t J = g >> 1;
     const int m = 2 * p + 2;  // offset of cell 2J
-    const double r1 = res(m), r2 = res(m + 1);
-    const double rm = (J > 0) ? res(m - 1) : -r1;
-    const double rp = (2 * J + 2 < n) ? res(m + 2) : -r2;
-    const double IR = ((rm + rp) + 3.0 * (r1 + r2)) * 0.125;
-    const double u0 = (w[m] + w[m + 1]) * 0.5;
-    const double ul = (J > 0) ? (w[m - 2] + w[m - 1]) * 0.5 : 2.0 * gL - u0;
-    const double ur = (J < nc - 1) ? (w[m + 2] + w[m + 3]) * 0.5 : 2.0 * gR - u0;
-    a.q_out[J] = IR + (2.0 * u0 - (ul + ur)) * wc;
+    q[p] = 0.0;
+    if (g >= core_lo && g < core_hi) {
+      const double ra = res(m), rb = res(m + 1);
+      const double rm = (J > 0) ? res(m - 1) : -ra;
+      const double rp = (2 * J + 2 < n) ? res(m + 2) : -rb;
+      const double IR = ((rm + rp) + 3.0 * (ra + rb)) * 0.125;
+      const double u0 = (w[m] + w[m + 1]) * 0.5;
+      const double ul = (J > 0) ? (w[m - 2] + w[m - 1]) * 0.5 : 2.0 * gL - u0;
+      const double ur = (J < nc - 1) ? (w[m + 2] + w[m + 3]) * 0.5 : 2.0 * gR - u0;
+      q[p] = IR + (2.0 * u0 - (ul + ur)) * wc;
+    }
   }
+  store_run<K / 2>(st, q, wlo >> 1, core_lo >> 1, core_hi >> 1, a.q_out);
 }
 
 // Up pass (Fig. 3 SR branch): full update u = Pi c (Eq. 5), then nu times
@@ -386,46 +622,51 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
 // the extended patch; the core streams to u_out.
 template <int K>
 __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
-  __shared__ double xr[kSegMaxThreads], xb[kSegMaxThreads];
+  extern __shared__ double sm[];
+  const int W = blockDim.x;
+  double* st = sm;
+  Xch x{sm + W * (K + 1), 0};
   const int64_t n = a.n, nc = n >> 1;
   const int64_t seg = blockIdx.x;
   const int64_t core_lo = seg * a.s, core_hi = core_lo + a.s;
-  const int64_t tile_lo = core_lo - a.pad;
-  const int64_t g0 = tile_lo + (int64_t)threadIdx.x * K;
-  const int64_t J0 = g0 >> 1;
+  const int64_t wlo = core_lo - a.pad;
+  const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
   double u[K], f[K], c[K / 2];
-#pragma unroll
-  for (int j = 0; j < K; ++j) f[j] = ld(a.f, g0 + j, n);
-#pragma unroll
-  for (int p = 0; p < K / 2; ++p) c[p] = ld(a.coarse, J0 + p, nc);
-  load_interp<K>(u, g0, n, a.coarse, a.gL, a.gR);
+  load_run<K>(st, f, wlo, a.win, n, [&](int64_t g) { return a.f[g]; });
+  load_run<K / 2>(st, c, wlo >> 1, a.win / 2 + 2, nc, [&](int64_t J) { return a.coarse[J]; });
+  interp_from_run<K>(u, c, g0, n, a.coarse, a.gL, a.gR, x);
   const int64_t lo = (core_lo - a.buffer > 0) ? core_lo - a.buffer : 0;
   const int64_t hi = (core_hi + a.buffer < n) ? core_hi + a.buffer : n;
   const double h2 = 1.0 / ((double)n * (double)n);
   const double gL2 = 2.0 * a.gL, gR2 = 2.0 * a.gR;
+  const double bdiv = (n == 1) ? 4.0 : 3.0;
+  const RunBounds rb = run_bounds(g0, K, lo, hi, n);
   for (int it = 0; it < a.nu; ++it) {
 #pragma unroll
     for (int p = 0; p < K / 2; ++p) {
-      const int64_t g = g0 + 2 * p;
-      if (g >= lo && g + 1 < hi) {
+      if (2 * p >= rb.jlo && 2 * p + 1 < rb.jhi) {  // both children in the patch
         const double r = c[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
         u[2 * p] = u[2 * p] + r;
         u[2 * p + 1] = u[2 * p + 1] + r;
       }
     }
-    rb_half<K, 0>(u, f, g0, lo, hi, n, h2, gL2, gR2, xr);
-    rb_half<K, 1>(u, f, g0, lo, hi, n, h2, gL2, gR2, xb);
+    rb_half<K, 0>(u, f, rb, h2, gL2, gR2, bdiv, x);
+    rb_half<K, 1>(u, f, rb, h2, gL2, gR2, bdiv, x);
   }
-  store_range<K>(u, g0, core_lo, core_hi < n ? core_hi : n, a.out);
+  store_run<K>(st, u, wlo, core_lo, core_hi < n ? core_hi : n, a.out);
 }
 
 // ---------------------------------------------------------------------------
 // Coarse core: all levels with at most kCoreMaxCells cells, in one workgroup
-// with the level stack resident in LDS.
+// with the level stack resident in LDS.  The coarse levels are tiny, so this
+// kernel is bound by latency: the code is kept compact (rolled loops, 32-bit
+// indices, one call site per phase) because a lone workgroup starts with a
+// cold instruction cache and every distinct instruction line it runs costs a
+// fetch from L2.
 // ---------------------------------------------------------------------------
 
-constexpr int kCoreThreads = 1024;
-constexpr int64_t kCoreMaxCells = 1024;
+constexpr int kCoreThreads = 256;
+constexpr int64_t kCoreMaxCells = 2048;
 constexpr int64_t kMaxN0 = 1024;
 
 struct CoreArgs {
@@ -436,181 +677,228 @@ struct CoreArgs {
   int literal;         // literal tau on the levels below C
   int mode;            // 0: FMG on levels 0..C; 1: V-cycle from a level-C guess
   int src_kind;        // mode 1: kSrcRestrict (from level C+1) or kSrcDirect
-  const double* F;     // forcing hierarchy, level l at offset n0 (2^l - 1)
+  const double* F[12]; // forcing of levels 0..C (C <= 11)
   const double* src;   // mode 1: level C+1 iterate or level-C initial iterate
   const double* rhs_top;  // mode 1: right-hand side of level C
   double* out;         // level-C result
 };
 
-__device__ __forceinline__ int64_t lvl_off(int64_t n0, int l) { return n0 * (((int64_t)1 << l) - 1); }
+__device__ __forceinline__ int lvl_off(int n0, int l) { return n0 * ((1 << l) - 1); }
 
-__device__ void core_rb(double* u, const double* q, int64_t n, double gL, double gR) {
+// One red-black sweep of a level (n cells) in LDS.
+__device__ __forceinline__ void core_rb(double* u, const double* q, int n, double gL2, double gR2) {
   const double h2 = 1.0 / ((double)n * (double)n);
-  const double gL2 = 2.0 * gL, gR2 = 2.0 * gR;
+  const double bdiv = (n == 1) ? 4.0 : 3.0;
+#pragma unroll 1
   for (int colour = 0; colour < 2; ++colour) {
-    for (int64_t i = 2 * (int64_t)threadIdx.x + colour; i < n; i += 2 * (int64_t)blockDim.x) {
-      const double l = (i > 0) ? u[i - 1] : 0.0;
-      const double r = (i < n - 1) ? u[i + 1] : 0.0;
-      u[i] = relax(q[i], l, r, i, n, h2, gL2, gR2);
+#pragma unroll 1
+    for (int i = 2 * (int)threadIdx.x + colour; i < n; i += 2 * (int)blockDim.x) {
+      double l = (i > 0) ? u[i - 1] : gL2;
+      double r = (i < n - 1) ? u[i + 1] : gR2;
+      const double num = q[i] * h2 + (l + r);
+      u[i] = (i > 0 && i < n - 1) ? num * 0.5 : num / bdiv;
     }
     __syncthreads();
   }
-}
-
-__device__ void core_interp(const double* c, int64_t nc, double* fine, double gL, double gR) {
-  for (int64_t J = threadIdx.x; J < nc; J += blockDim.x) {
-    const double cm2 = coarse_at(c, nc, J - 2, gL, gR), cm1 = coarse_at(c, nc, J - 1, gL, gR);
-    const double c0 = c[J];
-    const double cp1 = coarse_at(c, nc, J + 1, gL, gR), cp2 = coarse_at(c, nc, J + 2, gL, gR);
-    fine[2 * J] = interp_even(cm2, cm1, c0, cp1);
-    fine[2 * J + 1] = interp_odd(cm1, c0, cp1, cp2);
-  }
-  __syncthreads();
-}
-
-__device__ void core_restrict(const double* fine, int64_t nc, double* c) {
-  for (int64_t J = threadIdx.x; J < nc; J += blockDim.x) c[J] = (fine[2 * J] + fine[2 * J + 1]) * 0.5;
-  __syncthreads();
-}
-
-// Literal tau (Eq. 7) for the coarse core: qc = I(qf - L_f uf) + L_c(I^ uf).
-__device__ void core_tau(const double* uf, const double* qf, int64_t nc, double* qc, double gL,
-                         double gR) {
-  const int64_t nf = 2 * nc;
-  const double w = (double)nf * (double)nf, wc = (double)nc * (double)nc;
-  for (int64_t J = threadIdx.x; J < nc; J += blockDim.x) {
-    const double r1 = fine_residual(uf, qf, 2 * J, nf, w, gL, gR);
-    const double r2 = fine_residual(uf, qf, 2 * J + 1, nf, w, gL, gR);
-    const double rm = (J > 0) ? fine_residual(uf, qf, 2 * J - 1, nf, w, gL, gR) : -r1;
-    const double rp = (2 * J + 2 < nf) ? fine_residual(uf, qf, 2 * J + 2, nf, w, gL, gR) : -r2;
-    const double IR = ((rm + rp) + 3.0 * (r1 + r2)) * 0.125;
-    const double u0 = (uf[2 * J] + uf[2 * J + 1]) * 0.5;
-    const double ul = (J > 0) ? (uf[2 * J - 2] + uf[2 * J - 1]) * 0.5 : 2.0 * gL - u0;
-    const double ur = (J < nc - 1) ? (uf[2 * J + 2] + uf[2 * J + 3]) * 0.5 : 2.0 * gR - u0;
-    qc[J] = IR + (2.0 * u0 - (ul + ur)) * wc;
-  }
-  __syncthreads();
-}
-
-// Correction (Eq. 4) of the fine iterate (still the pre-smoothed one) from
-// the post-smoothed coarse iterate: uf += P(uc - I^ uf).
-__device__ void core_correct(const double* uc, int64_t nc, double* uf, double* e) {
-  for (int64_t J = threadIdx.x; J < nc; J += blockDim.x)
-    e[J] = uc[J] - (uf[2 * J] + uf[2 * J + 1]) * 0.5;
-  __syncthreads();
-  for (int64_t J = threadIdx.x; J < nc; J += blockDim.x) {
-    const double eJ = e[J];
-    const double em = (J > 0) ? e[J - 1] : -eJ;
-    const double ep = (J < nc - 1) ? e[J + 1] : -eJ;
-    uf[2 * J] = uf[2 * J] + (3.0 * eJ + em) * 0.25;
-    uf[2 * J + 1] = uf[2 * J + 1] + (3.0 * eJ + ep) * 0.25;
-  }
-  __syncthreads();
-}
-
-// Exact solve of the coarsest level: one-cell closed form, else parallel
-// cyclic reduction on h^2 L u = h^2 q + boundary terms (tridiagonal with -1
-// off the diagonal, 2 inside, 3 at the ends).
-__device__ void core_coarse_solve(double* u, const double* q, int64_t n, double gL, double gR,
-                                  double* pa, double* pb, double* pc, double* pd) {
-  const double h2 = 1.0 / ((double)n * (double)n);
-  if (n == 1) {
-    if (threadIdx.x == 0) u[0] = (q[0] * h2 + (2.0 * gL + 2.0 * gR)) / 4.0;
-    __syncthreads();
-    return;
-  }
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    pa[i] = (i > 0) ? -1.0 : 0.0;
-    pc[i] = (i < n - 1) ? -1.0 : 0.0;
-    pb[i] = (i == 0 || i == n - 1) ? 3.0 : 2.0;
-    double d = q[i] * h2;
-    if (i == 0) d += 2.0 * gL;
-    if (i == n - 1) d += 2.0 * gR;
-    pd[i] = d;
-  }
-  __syncthreads();
-  for (int64_t st = 1; st < n; st <<= 1) {
-    // n <= kMaxN0 <= blockDim: one row per thread
-    const int64_t i = threadIdx.x;
-    double na = 0.0, nb = 1.0, ncv = 0.0, nd = 0.0;
-    if (i < n) {
-      double ai = pa[i], bi = pb[i], ci = pc[i], di = pd[i];
-      double k1 = 0.0, k2 = 0.0;
-      double am = 0.0, cm = 0.0, dm = 0.0, ap = 0.0, cp = 0.0, dp = 0.0;
-      if (i - st >= 0) { k1 = ai / pb[i - st]; am = pa[i - st]; cm = pc[i - st]; dm = pd[i - st]; }
-      if (i + st < n) { k2 = ci / pb[i + st]; ap = pa[i + st]; cp = pc[i + st]; dp = pd[i + st]; }
-      na = -am * k1;
-      ncv = -cp * k2;
-      nb = (bi - cm * k1) - ap * k2;
-      nd = (di - dm * k1) - dp * k2;
-    }
-    __syncthreads();
-    if (i < n) { pa[i] = na; pb[i] = nb; pc[i] = ncv; pd[i] = nd; }
-    __syncthreads();
-  }
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) u[i] = pd[i] / pb[i];
-  __syncthreads();
 }
 
 __global__ __launch_bounds__(kCoreThreads) void k_coarse_core(CoreArgs a) {
   extern __shared__ double sm[];
   const int C = a.top;
-  const int64_t n0 = a.n0;
-  const int64_t ntot = lvl_off(n0, C + 1);
+  const int n0 = (int)a.n0;
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int ntot = lvl_off(n0, C + 1);
   double* U = sm;                 // iterates, levels 0..C
   double* Q = sm + ntot;          // right-hand sides in use, levels 0..C
-  double* E = Q + ntot;           // coarse error scratch
-  const int64_t esz = (C > 0) ? (n0 << (C - 1)) : 1;
-  double* PA = E + esz;
-  double* PB = PA + n0;
-  double* PC = PB + n0;
-  double* PD = PC + n0;
-  const double gL = a.gL, gR = a.gR;
-  for (int64_t i = threadIdx.x; i < ntot; i += blockDim.x) Q[i] = a.F[i];
-  const int64_t nC = n0 << C;
+  double* E = Q + ntot;           // coarse error of the correction
+  const int esz = (C > 0) ? (n0 << (C - 1)) : 0;
+  double* PA = E + esz;           // parallel cyclic reduction, two buffers
+  const double gL = a.gL, gR = a.gR, gL2 = 2.0 * gL, gR2 = 2.0 * gR;
+  const int nC = n0 << C;
+  // inputs: all global loads of a level are issued before any is consumed
+#pragma unroll 1
+  for (int l = 0; l <= C; ++l) {
+    const int nl = n0 << l;
+    const double* Fl = (l == C && a.mode == 1) ? a.rhs_top : a.F[l];
+    double v[kCoreMaxCells / kCoreThreads];
+#pragma unroll
+    for (int k = 0; k < (int)(kCoreMaxCells / kCoreThreads); ++k) {
+      const int i = tid + k * T;
+      v[k] = Fl[i < nl ? i : nl - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < (int)(kCoreMaxCells / kCoreThreads); ++k) {
+      const int i = tid + k * T;
+      if (i < nl) Q[lvl_off(n0, l) + i] = v[k];
+    }
+  }
   if (a.mode == 1) {
-    for (int64_t i = threadIdx.x; i < nC; i += blockDim.x) {
-      Q[lvl_off(n0, C) + i] = a.rhs_top[i];
-      U[lvl_off(n0, C) + i] = (a.src_kind == kSrcRestrict)
-                                   ? (a.src[2 * i] + a.src[2 * i + 1]) * 0.5
-                                   : a.src[i];
+    double v[kCoreMaxCells / kCoreThreads];
+#pragma unroll
+    for (int k = 0; k < (int)(kCoreMaxCells / kCoreThreads); ++k) {
+      int i = tid + k * T;
+      i = i < nC ? i : nC - 1;
+      v[k] = (a.src_kind == kSrcRestrict) ? (a.src[2 * i] + a.src[2 * i + 1]) * 0.5 : a.src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < (int)(kCoreMaxCells / kCoreThreads); ++k) {
+      const int i = tid + k * T;
+      if (i < nC) U[lvl_off(n0, C) + i] = v[k];
     }
   }
   __syncthreads();
-  // V-cycle on levels 0..t, entered with u^t holding its initial iterate.
-  auto vcycle = [&](int t) {
-    if (t == 0) {
-      core_coarse_solve(U, Q, n0, gL, gR, PA, PB, PC, PD);
-      return;
+  // FMG (mode 0): V-cycles on levels 0..t for t = 0..C, each entered with the
+  // FMG interpolation of the level below; mode 1: one V-cycle on levels
+  // 0..C.  V-cycle (Fig. 1): smooth and restrict from t down to 1, exact
+  // solve of level 0, then correct (Eq. 4) and smooth back up to t.
+#pragma unroll 1
+  for (int t = (a.mode == 0) ? 0 : C; t <= C; ++t) {
+    if (a.mode == 0 && t > 0) {
+      const int nc = n0 << (t - 1);
+      const double* c = U + lvl_off(n0, t - 1);
+      double* fine = U + lvl_off(n0, t);
+#pragma unroll 1
+      for (int J = tid; J < nc; J += T) {
+        const double cm2 = coarse_at(c, nc, J - 2, gL, gR), cm1 = coarse_at(c, nc, J - 1, gL, gR);
+        const double c0 = c[J];
+        const double cp1 = coarse_at(c, nc, J + 1, gL, gR), cp2 = coarse_at(c, nc, J + 2, gL, gR);
+        fine[2 * J] = interp_even(cm2, cm1, c0, cp1);
+        fine[2 * J + 1] = interp_odd(cm1, c0, cp1, cp2);
+      }
+      __syncthreads();
     }
-    for (int s = 0; s < a.nu1; ++s) core_rb(U + lvl_off(n0, t), Q + lvl_off(n0, t), n0 << t, gL, gR);
-    for (int m = t - 1; m >= 0; --m) {
-      const int64_t nm = n0 << m;
-      double* um = U + lvl_off(n0, m);
-      double* uf = U + lvl_off(n0, m + 1);
-      if (a.literal) core_tau(uf, Q + lvl_off(n0, m + 1), nm, Q + lvl_off(n0, m), gL, gR);
-      core_restrict(uf, nm, um);
-      if (m == 0) core_coarse_solve(um, Q, n0, gL, gR, PA, PB, PC, PD);
-      else
-        for (int s = 0; s < a.nu1; ++s) core_rb(um, Q + lvl_off(n0, m), nm, gL, gR);
+    // down leg
+#pragma unroll 1
+    for (int m = t; m >= 1; --m) {
+      const int nm = n0 << m, nc = nm >> 1;
+      double* uf = U + lvl_off(n0, m);
+      double* qf = Q + lvl_off(n0, m);
+#pragma unroll 1
+      for (int s = 0; s < a.nu1; ++s) core_rb(uf, qf, nm, gL2, gR2);
+      double* uc = U + lvl_off(n0, m - 1);
+      double* qc = Q + lvl_off(n0, m - 1);
+      const double w = (double)nm * (double)nm, wc = (double)nc * (double)nc;
+#pragma unroll 1
+      for (int J = tid; J < nc; J += T) {
+        const double u0 = (uf[2 * J] + uf[2 * J + 1]) * 0.5;
+        if (a.literal) {  // Eq. 7 as written: I(q - L u) + L_c(I^ u)
+          auto res = [&](int k) {
+            const double l = (k > 0) ? uf[k - 1] : gL2 - uf[0];
+            const double r = (k < nm - 1) ? uf[k + 1] : gR2 - uf[nm - 1];
+            return qf[k] - (2.0 * uf[k] - (l + r)) * w;
+          };
+          const double r1 = res(2 * J), r2 = res(2 * J + 1);
+          const double rm = (J > 0) ? res(2 * J - 1) : -r1;
+          const double rp = (2 * J + 2 < nm) ? res(2 * J + 2) : -r2;
+          const double IR = ((rm + rp) + 3.0 * (r1 + r2)) * 0.125;
+          const double ul = (J > 0) ? (uf[2 * J - 2] + uf[2 * J - 1]) * 0.5 : gL2 - u0;
+          const double ur = (J < nc - 1) ? (uf[2 * J + 2] + uf[2 * J + 3]) * 0.5 : gR2 - u0;
+          qc[J] = IR + (2.0 * u0 - (ul + ur)) * wc;
+        }
+        uc[J] = u0;
+      }
+      __syncthreads();
     }
+    // exact solve of level 0: one-cell closed form, else parallel cyclic
+    // reduction on h^2 L u = h^2 q + boundary terms (tridiagonal with -1
+    // off the diagonal, 2 inside, 3 at the ends); up to 64 unknowns in one
+    // wavefront's registers with cross-lane shuffles, else through LDS.
+    {
+      const double h2 = 1.0 / ((double)n0 * (double)n0);
+      if (n0 == 1) {
+        if (tid == 0) U[0] = (Q[0] * h2 + (gL2 + gR2)) / 4.0;
+      } else if (n0 <= 64) {
+        if (tid < 64) {
+          const int i = tid;
+          const bool in = i < n0;
+          double aa = (in && i > 0) ? -1.0 : 0.0;
+          double cc = (in && i < n0 - 1) ? -1.0 : 0.0;
+          double bb = in ? ((i == 0 || i == n0 - 1) ? 3.0 : 2.0) : 1.0;
+          double dd = 0.0;
+          if (in) {
+            dd = Q[i] * h2;
+            if (i == 0) dd += gL2;
+            if (i == n0 - 1) dd += gR2;
+          }
+#pragma unroll 1
+          for (int st = 1; st < n0; st <<= 1) {
+            const bool hasm = (i - st >= 0), hasp = (i + st < n0);
+            const int im = hasm ? i - st : i, ip = hasp ? i + st : i;
+            const double am = __shfl(aa, im), bm = __shfl(bb, im), cm = __shfl(cc, im), dm = __shfl(dd, im);
+            const double ap = __shfl(aa, ip), bp = __shfl(bb, ip), cp = __shfl(cc, ip), dp = __shfl(dd, ip);
+            const double k1 = (in && hasm) ? aa / bm : 0.0;
+            const double k2 = (in && hasp) ? cc / bp : 0.0;
+            const double na = hasm ? -am * k1 : 0.0;
+            const double nc2 = hasp ? -cp * k2 : 0.0;
+            const double nb = (bb - (hasm ? cm * k1 : 0.0)) - (hasp ? ap * k2 : 0.0);
+            const double nd = (dd - (hasm ? dm * k1 : 0.0)) - (hasp ? dp * k2 : 0.0);
+            if (in) { aa = na; bb = nb; cc = nc2; dd = nd; }
+          }
+          if (in) U[i] = dd / bb;
+        }
+      } else {
+        double *A = PA, *B = PA + n0, *Cc = PA + 2 * n0, *D = PA + 3 * n0;
+        double *A2 = PA + 4 * n0, *B2 = PA + 5 * n0, *C2 = PA + 6 * n0, *D2 = PA + 7 * n0;
+#pragma unroll 1
+        for (int i = tid; i < n0; i += T) {
+          A[i] = (i > 0) ? -1.0 : 0.0;
+          Cc[i] = (i < n0 - 1) ? -1.0 : 0.0;
+          B[i] = (i == 0 || i == n0 - 1) ? 3.0 : 2.0;
+          double d = Q[i] * h2;
+          if (i == 0) d += gL2;
+          if (i == n0 - 1) d += gR2;
+          D[i] = d;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int st = 1; st < n0; st <<= 1) {
+#pragma unroll 1
+          for (int i = tid; i < n0; i += T) {
+            const double ai = A[i], bi = B[i], ci = Cc[i], di = D[i];
+            double k1 = 0.0, k2 = 0.0, am = 0.0, cm = 0.0, dm = 0.0, ap = 0.0, cp = 0.0, dp = 0.0;
+            if (i - st >= 0) { k1 = ai / B[i - st]; am = A[i - st]; cm = Cc[i - st]; dm = D[i - st]; }
+            if (i + st < n0) { k2 = ci / B[i + st]; ap = A[i + st]; cp = Cc[i + st]; dp = D[i + st]; }
+            A2[i] = -am * k1;
+            C2[i] = -cp * k2;
+            B2[i] = (bi - cm * k1) - ap * k2;
+            D2[i] = (di - dm * k1) - dp * k2;
+          }
+          __syncthreads();
+          double* tmp;
+          tmp = A; A = A2; A2 = tmp;
+          tmp = B; B = B2; B2 = tmp;
+          tmp = Cc; Cc = C2; C2 = tmp;
+          tmp = D; D = D2; D2 = tmp;
+        }
+#pragma unroll 1
+        for (int i = tid; i < n0; i += T) U[i] = D[i] / B[i];
+      }
+      __syncthreads();
+    }
+    // up leg
+#pragma unroll 1
     for (int m = 0; m < t; ++m) {
-      const int64_t nm = n0 << m;
-      core_correct(U + lvl_off(n0, m), nm, U + lvl_off(n0, m + 1), E);
-      for (int s = 0; s < a.nu2; ++s)
-        core_rb(U + lvl_off(n0, m + 1), Q + lvl_off(n0, m + 1), nm << 1, gL, gR);
+      const int nc = n0 << m, nf = nc << 1;
+      const double* uc = U + lvl_off(n0, m);
+      double* uf = U + lvl_off(n0, m + 1);
+#pragma unroll 1
+      for (int J = tid; J < nc; J += T) E[J] = uc[J] - (uf[2 * J] + uf[2 * J + 1]) * 0.5;
+      __syncthreads();
+#pragma unroll 1
+      for (int J = tid; J < nc; J += T) {
+        const double eJ = E[J];
+        const double em = (J > 0) ? E[J - 1] : -eJ;
+        const double ep = (J < nc - 1) ? E[J + 1] : -eJ;
+        uf[2 * J] = uf[2 * J] + (3.0 * eJ + em) * 0.25;
+        uf[2 * J + 1] = uf[2 * J + 1] + (3.0 * eJ + ep) * 0.25;
+      }
+      __syncthreads();
+#pragma unroll 1
+      for (int s = 0; s < a.nu2; ++s) core_rb(uf, Q + lvl_off(n0, m + 1), nf, gL2, gR2);
     }
-  };
-  if (a.mode == 0) {
-    core_coarse_solve(U, Q, n0, gL, gR, PA, PB, PC, PD);
-    for (int t = 1; t <= C; ++t) {
-      core_interp(U + lvl_off(n0, t - 1), n0 << (t - 1), U + lvl_off(n0, t), gL, gR);
-      vcycle(t);
-    }
-  } else {
-    vcycle(C);
   }
-  for (int64_t i = threadIdx.x; i < nC; i += blockDim.x) a.out[i] = U[lvl_off(n0, C) + i];
+#pragma unroll 1
+  for (int i = tid; i < nC; i += T) a.out[i] = U[lvl_off(n0, C) + i];
 }
 
 }  // namespace fmgsr
