@@ -104,6 +104,24 @@ struct Xch {
     left_last = (t > 0) ? b[W + t - 1] : 0.0;
     right_first = (t + 1 < W) ? b[t + 1] : 0.0;
   }
+  // one value only: the left neighbour's `mine` (0 for the first thread)
+  __device__ double from_left(double mine) {
+    const int W = blockDim.x, t = threadIdx.x;
+    double* b = buf + (sel ? 2 * W : 0);
+    sel ^= 1;
+    b[t] = mine;
+    __syncthreads();
+    return (t > 0) ? b[t - 1] : 0.0;
+  }
+  // the right neighbour's `mine` (0 for the last thread)
+  __device__ double from_right(double mine) {
+    const int W = blockDim.x, t = threadIdx.x;
+    double* b = buf + (sel ? 2 * W : 0);
+    sel ^= 1;
+    b[t] = mine;
+    __syncthreads();
+    return (t + 1 < W) ? b[t + 1] : 0.0;
+  }
 };
 
 // Per-run bounds in 32-bit local indices (0..K): updatable cells [jlo, jhi)
@@ -329,6 +347,175 @@ __device__ __forceinline__ void restrict_rhs_run(const double (&f)[K], double (&
 }
 
 // ---------------------------------------------------------------------------
+// Interior fast paths.  A workgroup whose window lies inside the level with a
+// margin (no domain boundary, no reflection, no clipping) takes these: loads
+// and stores at plain offsets from one base pointer, Pi and full weighting
+// without boundary cases, and red-black updates without per-cell tests.  An
+// interior update is computed as fma(l + r, 1/2, F h^2 / 2): the product by
+// 1/2 is exact, so this rounds exactly like (F h^2 + (l + r)) / 2 (for normal
+// numbers; scaling by 2 commutes with rounding).  Cells at the window edge of
+// a tile are updated from a missing neighbour instead of being frozen; they
+// go stale at the same rate either way and the halo absorbs them.
+// ---------------------------------------------------------------------------
+
+// Coalesced load of window cells [0, W K) from base (all inside the level),
+// through the stage, into the runs.  Cells e >= count read base[0] and are
+// set to 0 (they lie past the part of the window in use).
+template <int K, bool kAll>
+__device__ __forceinline__ void load_run_fast(double* st, double (&v)[K],
+                                              const double* __restrict__ base, int count) {
+  const int W = blockDim.x;
+  double tmp[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = threadIdx.x + k * W;
+    tmp[k] = base[(kAll || e < count) ? e : 0];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = threadIdx.x + k * W;
+    st[sidx<K>(e)] = (kAll || e < count) ? tmp[k] : 0.0;
+  }
+  __syncthreads();
+  stage_to_run<K>(st, v);
+  __syncthreads();
+}
+
+// The same in two halves, so that several loads can be in flight together:
+// issue_loads puts window cells [0, W K) from base into tmp (lane layout,
+// cell threadIdx.x + k W in tmp[k]); stage_tmp moves them into the runs.
+template <int K, bool kAll>
+__device__ __forceinline__ void issue_loads(double (&tmp)[K], const double* __restrict__ base,
+                                            int count) {
+  const int W = blockDim.x;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = threadIdx.x + k * W;
+    tmp[k] = base[(kAll || e < count) ? e : 0];
+  }
+}
+template <int K, bool kAll>
+__device__ __forceinline__ void stage_tmp(double* st, const double (&tmp)[K], double (&v)[K],
+                                          int count) {
+  const int W = blockDim.x;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = threadIdx.x + k * W;
+    st[sidx<K>(e)] = (kAll || e < count) ? tmp[k] : 0.0;
+  }
+  __syncthreads();
+  stage_to_run<K>(st, v);
+  __syncthreads();
+}
+
+// Registers -> coalesced store of window cells [clo, chi) to base.
+template <int K>
+__device__ __forceinline__ void store_run_fast(double* st, const double (&v)[K],
+                                               double* __restrict__ base, int clo, int chi) {
+  const int W = blockDim.x;
+  run_to_stage<K>(st, v);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = threadIdx.x + k * W;
+    if (e >= clo && e < chi) base[e] = st[sidx<K>(e)];
+  }
+  __syncthreads();
+}
+
+// Pi from the coarse run c (cells J0..J0+K/2-1 of this thread, cbase =
+// address of J0 in HBM): two coarse cells on each side from the neighbours,
+// from HBM at the window edges.  No boundary cases.
+template <int K>
+__device__ __forceinline__ void interp_fast(double (&u)[K], const double (&c)[K / 2],
+                                            const double* __restrict__ cbase, Xch& x) {
+  double l1, r0, l2, r1;
+  x.swap(c[0], c[K / 2 - 1], l1, r0);
+  x.swap(c[1], c[K / 2 - 2], l2, r1);
+  if (threadIdx.x == 0) { l2 = cbase[-2]; l1 = cbase[-1]; }
+  if (threadIdx.x == blockDim.x - 1) { r0 = cbase[K / 2]; r1 = cbase[K / 2 + 1]; }
+  double e[K / 2 + 4];
+  e[0] = l2;
+  e[1] = l1;
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) e[p + 2] = c[p];
+  e[K / 2 + 2] = r0;
+  e[K / 2 + 3] = r1;
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) {
+    u[2 * p] = interp_even(e[p], e[p + 1], e[p + 2], e[p + 3]);
+    u[2 * p + 1] = interp_odd(e[p + 1], e[p + 2], e[p + 3], e[p + 4]);
+  }
+}
+
+// Full weighting of a run (no boundary cases).
+template <int K>
+__device__ __forceinline__ void fw_fast(const double (&f)[K], double (&f1)[K / 2], Xch& x) {
+  double fl, fr;
+  x.swap(f[0], f[K - 1], fl, fr);
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) {
+    const double rm = (p == 0) ? fl : f[2 * p - 1];
+    const double rp = (p == K / 2 - 1) ? fr : f[2 * p + 2];
+    f1[p] = ((rm + rp) + 3.0 * (f[2 * p] + f[2 * p + 1])) * 0.125;
+  }
+}
+
+// fh = F h^2 / 2 for the fused interior update.
+template <int K>
+__device__ __forceinline__ void half_scaled(const double (&f)[K], double (&fh)[K], int64_t n) {
+  const double h2 = 1.0 / ((double)n * (double)n);
+#pragma unroll
+  for (int j = 0; j < K; ++j) fh[j] = (f[j] * h2) * 0.5;
+}
+
+// nu red-black sweeps updating every cell of the run.
+template <int K>
+__device__ __forceinline__ void rb_sweeps_fast(double (&u)[K], const double (&fh)[K], int nu,
+                                               Xch& x) {
+  for (int s = 0; s < nu; ++s) {
+    const double ll = x.from_left(u[K - 1]);
+#pragma unroll
+    for (int j = 0; j < K; j += 2) u[j] = __builtin_fma((j == 0 ? ll : u[j - 1]) + u[j + 1], 0.5, fh[j]);
+    const double rf = x.from_right(u[0]);
+#pragma unroll
+    for (int j = 1; j < K; j += 2) u[j] = __builtin_fma(u[j - 1] + (j == K - 1 ? rf : u[j + 1]), 0.5, fh[j]);
+  }
+}
+
+// nu red-black sweeps updating the run cells [jlo, jhi) only (interior of
+// the level; used on SR segments, whose extended patch ends inside threads).
+template <int K>
+__device__ __forceinline__ void rb_sweeps_masked(double (&u)[K], const double (&fh)[K], int nu,
+                                                 int jlo, int jhi, Xch& x) {
+  const bool all = (jlo == 0 && jhi == K);
+  for (int s = 0; s < nu; ++s) {
+    const double ll = x.from_left(u[K - 1]);
+    if (all) {
+#pragma unroll
+      for (int j = 0; j < K; j += 2) u[j] = __builtin_fma((j == 0 ? ll : u[j - 1]) + u[j + 1], 0.5, fh[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < K; j += 2) {
+        const double v = __builtin_fma((j == 0 ? ll : u[j - 1]) + u[j + 1], 0.5, fh[j]);
+        if (j >= jlo && j < jhi) u[j] = v;
+      }
+    }
+    const double rf = x.from_right(u[0]);
+    if (all) {
+#pragma unroll
+      for (int j = 1; j < K; j += 2) u[j] = __builtin_fma(u[j - 1] + (j == K - 1 ? rf : u[j + 1]), 0.5, fh[j]);
+    } else {
+#pragma unroll
+      for (int j = 1; j < K; j += 2) {
+        const double v = __builtin_fma(u[j - 1] + (j == K - 1 ? rf : u[j + 1]), 0.5, fh[j]);
+        if (j >= jlo && j < jhi) u[j] = v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Stored levels: vertical down / up kernels
 // ---------------------------------------------------------------------------
 
@@ -387,6 +574,37 @@ __device__ void down_level(const VertArgs& a, double* st, Xch& x, double (&u)[K]
   }
 }
 
+constexpr int64_t kInteriorMargin = 4 << kMaxFuse;  // cells kept from the domain ends
+
+// Window of this workgroup on the top level: [wlo, wlo + W K).
+__device__ __forceinline__ int64_t top_wlo(const VertArgs& a) {
+  return (int64_t)blockIdx.x * a.core - a.halo;
+}
+__device__ __forceinline__ bool window_interior(int64_t wlo, int64_t cells, int64_t n) {
+  return wlo >= kInteriorMargin && wlo + cells + kInteriorMargin <= n;
+}
+
+template <int K, int I>
+__device__ void down_level_fast(const VertArgs& a, double* st, Xch& x, double (&u)[K],
+                                double (&f)[K], int64_t wlo0) {
+  const int64_t wlo = wlo0 >> I;
+  double f1[K / 2];
+  const bool more = (I + 1 < kMaxFuse && K >= 4) && (I + 1 < a.levels);
+  if constexpr (I + 1 < kMaxFuse && K >= 4)
+    if (more) fw_fast<K>(f, f1, x);
+  half_scaled<K>(f, f, a.n >> I);
+  rb_sweeps_fast<K>(u, f, a.nu, x);
+  store_run_fast<K>(st, u, a.out[I] + wlo, (int)(a.halo >> I), (int)((a.halo + a.core) >> I));
+  if constexpr (I + 1 < kMaxFuse && K >= 4) {
+    if (more) {
+      double u1[K / 2];
+#pragma unroll
+      for (int p = 0; p < K / 2; ++p) u1[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
+      down_level_fast<K / 2, I + 1>(a, st, x, u1, f1, wlo0);
+    }
+  }
+}
+
 // Down leg over `levels` stored levels (Fig. 3 steps 1-2 on the top level,
 // then restrict + smooth of the pre-smoothing leg), split tau: the coarse
 // right-hand side is the full weighting of the finer one (the Laplacian
@@ -397,8 +615,38 @@ __global__ __launch_bounds__(kTileThreads) void k_down(VertArgs a) {
   __shared__ double xb[4 * kTileThreads];
   Xch x{xb, 0};
   const int wcount = kTileThreads * K;
-  const TileGeom G = tile_geom(a, 0, K);
+  const int64_t wlo0 = top_wlo(a);
   double u[K], f[K];
+  if (window_interior(wlo0, wcount, a.n)) {
+    double tf[K];
+    issue_loads<K, true>(tf, a.rhs + wlo0, 0);  // rhs and source loads in flight together
+    if (a.src_kind == kSrcInterp) {
+      const double* cb = a.src + (wlo0 >> 1);
+      double tc[K / 2], c[K / 2];
+      issue_loads<K / 2, true>(tc, cb, 0);
+      stage_tmp<K, true>(st, tf, f, 0);
+      stage_tmp<K / 2, true>(st, tc, c, 0);
+      interp_fast<K>(u, c, cb + threadIdx.x * (K / 2), x);
+    } else if (a.src_kind == kSrcRestrict) {
+      const double2* fb = reinterpret_cast<const double2*>(a.src) + wlo0;
+      double tu[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double2 q = fb[threadIdx.x + k * kTileThreads];
+        tu[k] = (q.x + q.y) * 0.5;
+      }
+      stage_tmp<K, true>(st, tf, f, 0);
+      stage_tmp<K, true>(st, tu, u, 0);
+    } else {
+      double tu[K];
+      issue_loads<K, true>(tu, a.src + wlo0, 0);
+      stage_tmp<K, true>(st, tf, f, 0);
+      stage_tmp<K, true>(st, tu, u, 0);
+    }
+    down_level_fast<K, 0>(a, st, x, u, f, wlo0);
+    return;
+  }
+  const TileGeom G = tile_geom(a, 0, K);
   load_run<K>(st, f, G.wlo, wcount, G.n, [&](int64_t g) { return a.rhs[g]; });
   if (a.src_kind == kSrcInterp)
     load_interp_run<K>(st, u, G.wlo, wcount, G.n, a.src, a.gL, a.gR, x);
@@ -454,6 +702,47 @@ __device__ void up_level(const VertArgs& a, double* st, Xch& x, const double (&f
   rb_sweeps<K>(u, f, G.g0, a.nu, G.lo, G.hi, G.n, a.gL, a.gR, x);
 }
 
+// tp holds this level's pre-smoothed iterate in flight (lane layout); the
+// coarser levels' loads are issued before descending, so every HBM read of
+// the kernel is outstanding at once.
+template <int K, int I>
+__device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, double (&f)[K],
+                              double (&u)[K], const double (&tp)[K], int64_t wlo0) {
+  const int64_t wlo = wlo0 >> I;
+  double c[K / 2];
+  bool done = false;
+  if constexpr (I + 1 < kMaxFuse && K >= 4) {
+    if (I + 1 < a.levels) {
+      double tp1[K / 2];
+      issue_loads<K / 2, true>(tp1, a.pre[I + 1] + (wlo >> 1), 0);
+      double f1[K / 2];
+      fw_fast<K>(f, f1, x);
+      up_level_fast<K / 2, I + 1>(a, st, x, f1, c, tp1, wlo0);
+      done = true;
+    }
+  }
+  if (!done) {
+    double tc[K / 2];
+    issue_loads<K / 2, true>(tc, a.coarse + (wlo >> 1), 0);
+    stage_tmp<K / 2, true>(st, tc, c, 0);
+  }
+  half_scaled<K>(f, f, a.n >> I);
+  stage_tmp<K, true>(st, tp, u, 0);
+  double e[K / 2];
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) e[p] = c[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
+  double el, er;
+  x.swap(e[0], e[K / 2 - 1], el, er);
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) {
+    const double em = (p == 0) ? el : e[p - 1];
+    const double ep = (p == K / 2 - 1) ? er : e[p + 1];
+    u[2 * p] = u[2 * p] + (3.0 * e[p] + em) * 0.25;
+    u[2 * p + 1] = u[2 * p + 1] + (3.0 * e[p] + ep) * 0.25;
+  }
+  rb_sweeps_fast<K>(u, f, a.nu, x);
+}
+
 // Up leg over `levels` stored levels, bottom-up (Fig. 3 post-smoothing leg,
 // Eq. 4); only the top level's core is written.  Lower right-hand sides are
 // the full weighting of the top one (split tau).
@@ -463,8 +752,18 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
   __shared__ double xb[4 * kTileThreads];
   Xch x{xb, 0};
   const int wcount = kTileThreads * K;
-  const TileGeom G = tile_geom(a, 0, K);
+  const int64_t wlo0 = top_wlo(a);
   double u[K], f[K];
+  if (window_interior(wlo0, wcount, a.n)) {
+    double tf[K], tp[K];
+    issue_loads<K, true>(tf, a.rhs + wlo0, 0);
+    issue_loads<K, true>(tp, a.pre[0] + wlo0, 0);
+    stage_tmp<K, true>(st, tf, f, 0);
+    up_level_fast<K, 0>(a, st, x, f, u, tp, wlo0);
+    store_run_fast<K>(st, u, a.out[0] + wlo0, (int)a.halo, (int)(a.halo + a.core));
+    return;
+  }
+  const TileGeom G = tile_geom(a, 0, K);
   load_run<K>(st, f, G.wlo, wcount, G.n, [&](int64_t g) { return a.rhs[g]; });
   up_level<K, 0>(a, st, x, f, u);
   store_run<K>(st, u, G.wlo, G.clo, G.chi, a.out[0]);
@@ -488,6 +787,21 @@ __device__ void forcing_level(const VertArgs& a, double* st, Xch& x, const doubl
   }
 }
 
+template <int K, int I>
+__device__ void forcing_level_fast(const VertArgs& a, double* st, Xch& x, double (&f)[K],
+                                   int64_t wlo0) {
+  if constexpr (I > 0)
+    store_run_fast<K>(st, f, a.out[I - 1] + (wlo0 >> I), (int)(a.halo >> I),
+                      (int)((a.halo + a.core) >> I));
+  if constexpr (I < kMaxFuse && K >= 2) {
+    if (I < a.levels) {
+      double f1[K / 2];
+      fw_fast<K>(f, f1, x);
+      forcing_level_fast<K / 2, I + 1>(a, st, x, f1, wlo0);
+    }
+  }
+}
+
 // a.rhs: level with a.n cells; writes a.levels coarser levels into
 // out[0..levels) (out[i] = level i+1 below).
 template <int K>
@@ -495,8 +809,14 @@ __global__ __launch_bounds__(kTileThreads) void k_forcing(VertArgs a) {
   __shared__ double st[kTileThreads * (K + 1)];
   __shared__ double xb[4 * kTileThreads];
   Xch x{xb, 0};
-  const TileGeom G = tile_geom(a, 0, K);
+  const int64_t wlo0 = top_wlo(a);
   double f[K];
+  if (window_interior(wlo0, kTileThreads * K, a.n)) {
+    load_run_fast<K, true>(st, f, a.rhs + wlo0, 0);
+    forcing_level_fast<K, 0>(a, st, x, f, wlo0);
+    return;
+  }
+  const TileGeom G = tile_geom(a, 0, K);
   load_run<K>(st, f, G.wlo, kTileThreads * K, G.n, [&](int64_t g) { return a.rhs[g]; });
   forcing_level<K, 0>(a, st, x, f);
 }
@@ -566,10 +886,27 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
   const int64_t wlo = core_lo - a.pad;
   const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
   double u[K], f[K];
-  load_run<K>(st, f, wlo, a.win, n, [&](int64_t g) { return a.f[g]; });
-  load_interp_run<K>(st, u, wlo, a.win, n, a.coarse, a.gL, a.gR, x);
   const int64_t lo = (core_lo - a.buffer > 0) ? core_lo - a.buffer : 0;
   const int64_t hi = (core_hi + a.buffer < n) ? core_hi + a.buffer : n;
+  if (a.q_out == nullptr && window_interior(wlo, (int64_t)W * K, n)) {
+    const double* cb = a.coarse + (wlo >> 1);
+    double tf[K], tc[K / 2], c[K / 2];
+    issue_loads<K, false>(tf, a.f + wlo, a.win);
+    issue_loads<K / 2, false>(tc, cb, a.win / 2 + 2);
+    stage_tmp<K, false>(st, tf, f, a.win);
+    stage_tmp<K / 2, false>(st, tc, c, a.win / 2 + 2);
+    interp_fast<K>(u, c, cb + threadIdx.x * (K / 2), x);
+    half_scaled<K>(f, f, n);
+    const RunBounds rb = run_bounds(g0, K, lo, hi, n);
+    rb_sweeps_masked<K>(u, f, a.nu, rb.jlo, rb.jhi, x);
+    double uc[K / 2];
+#pragma unroll
+    for (int p = 0; p < K / 2; ++p) uc[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
+    store_run_fast<K / 2>(st, uc, a.out + (wlo >> 1), (int)(a.pad >> 1), (int)((a.pad + a.s) >> 1));
+    return;
+  }
+  load_run<K>(st, f, wlo, a.win, n, [&](int64_t g) { return a.f[g]; });
+  load_interp_run<K>(st, u, wlo, a.win, n, a.coarse, a.gL, a.gR, x);
   rb_sweeps<K>(u, f, g0, a.nu, lo, hi, n, a.gL, a.gR, x);
   double uc[K / 2];
 #pragma unroll
@@ -632,11 +969,45 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
   const int64_t wlo = core_lo - a.pad;
   const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
   double u[K], f[K], c[K / 2];
+  const int64_t lo = (core_lo - a.buffer > 0) ? core_lo - a.buffer : 0;
+  const int64_t hi = (core_hi + a.buffer < n) ? core_hi + a.buffer : n;
+  if (window_interior(wlo, (int64_t)W * K, n)) {
+    const double* cb = a.coarse + (wlo >> 1);
+    double tf[K], tc[K / 2];
+    issue_loads<K, false>(tf, a.f + wlo, a.win);
+    issue_loads<K / 2, false>(tc, cb, a.win / 2 + 2);
+    stage_tmp<K, false>(st, tf, f, a.win);
+    stage_tmp<K / 2, false>(st, tc, c, a.win / 2 + 2);
+    interp_fast<K>(u, c, cb + threadIdx.x * (K / 2), x);
+    half_scaled<K>(f, f, n);
+    const RunBounds rb = run_bounds(g0, K, lo, hi, n);
+    const bool all = (rb.jlo == 0 && rb.jhi == K);
+    for (int it = 0; it < a.nu; ++it) {
+      if (all) {
+#pragma unroll
+        for (int p = 0; p < K / 2; ++p) {
+          const double r = c[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
+          u[2 * p] = u[2 * p] + r;
+          u[2 * p + 1] = u[2 * p + 1] + r;
+        }
+      } else {
+#pragma unroll
+        for (int p = 0; p < K / 2; ++p) {
+          if (2 * p >= rb.jlo && 2 * p + 1 < rb.jhi) {
+            const double r = c[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
+            u[2 * p] = u[2 * p] + r;
+            u[2 * p + 1] = u[2 * p + 1] + r;
+          }
+        }
+      }
+      rb_sweeps_masked<K>(u, f, 1, rb.jlo, rb.jhi, x);
+    }
+    store_run_fast<K>(st, u, a.out + wlo, (int)a.pad, (int)(a.pad + a.s));
+    return;
+  }
   load_run<K>(st, f, wlo, a.win, n, [&](int64_t g) { return a.f[g]; });
   load_run<K / 2>(st, c, wlo >> 1, a.win / 2 + 2, nc, [&](int64_t J) { return a.coarse[J]; });
   interp_from_run<K>(u, c, g0, n, a.coarse, a.gL, a.gR, x);
-  const int64_t lo = (core_lo - a.buffer > 0) ? core_lo - a.buffer : 0;
-  const int64_t hi = (core_hi + a.buffer < n) ? core_hi + a.buffer : n;
   const double h2 = 1.0 / ((double)n * (double)n);
   const double gL2 = 2.0 * a.gL, gR2 = 2.0 * a.gR;
   const double bdiv = (n == 1) ? 4.0 : 3.0;
@@ -659,10 +1030,9 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
 // ---------------------------------------------------------------------------
 // Coarse core: all levels with at most kCoreMaxCells cells, in one workgroup
 // with the level stack resident in LDS.  The coarse levels are tiny, so this
-// kernel is bound by latency: the code is kept compact (rolled loops, 32-bit
-// indices, one call site per phase) because a lone workgroup starts with a
-// cold instruction cache and every distinct instruction line it runs costs a
-// fetch from L2.
+// kernel is bound by the latency of its chain of about a hundred dependent
+// LDS phases; the code is kept compact (rolled loops, 32-bit indices, one
+// call site per phase) so that each phase issues few instructions.
 // ---------------------------------------------------------------------------
 
 constexpr int kCoreThreads = 256;
