@@ -33,6 +33,19 @@ def options(nu1=2, nu2=1, nsr=1, rhs_restrict="fw", tau="split", smoother="rb",
                    int(bool(tau_assembled)), int(block_all))
 
 
+class RxOptions(ctypes.Structure):
+    """Mirror of ``orc_rx_options`` (see fmgsr_oracle_reaction.c)."""
+    _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
+                ("nsr", ctypes.c_int32), ("tau_mode", ctypes.c_int32)]
+
+
+RX_KINDS = {"poisson": 0, "cubic": 1, "linear": 2}
+
+
+def rx_options(nu1=2, nu2=1, nsr=1, tau="split"):
+    return RxOptions(nu1, nu2, nsr, {"split": 0, "literal": 1}[tau])
+
+
 def lib():
     global _LIB
     if _LIB is None:
@@ -58,6 +71,23 @@ def lib():
         L.orc_fas_vcycle.argtypes = [_ptr, _ptr, _dbl, _dbl, _i64, ctypes.c_int,
                                      ctypes.POINTER(Options)]
         L.orc_fas_vcycle.restype = ctypes.c_int
+        _ci = ctypes.c_int
+        L.orc_rx_apply.argtypes = [_ci, _ptr, _ptr, _i64, _dbl, _dbl, _ptr]
+        L.orc_rx_ngs_sweep.argtypes = [_ci, _ptr, _ptr, _ptr, _i64, _i64, _i64, _dbl, _dbl]
+        L.orc_rx_newton.argtypes = [_ci, _ptr, _ptr, _i64, _dbl, _dbl, _ptr, _ci, _dbl,
+                                    ctypes.POINTER(_ci)]
+        L.orc_rx_newton.restype = _ci
+        L.orc_rx_fmgsr_solve_ex.argtypes = [_ci, _ptr, _ptr, _dbl, _dbl, _i64, _ci, _i64, _i64,
+                                            ctypes.POINTER(RxOptions), _ptr, _ci]
+        L.orc_rx_fmgsr_solve_ex.restype = _ci
+        L.orc_rx_fas_vcycle.argtypes = [_ci, _ptr, _ptr, _ptr, _dbl, _dbl, _i64, _ci,
+                                        ctypes.POINTER(RxOptions)]
+        L.orc_rx_fas_vcycle.restype = _ci
+        L.orc_rx_adjoint_direct.argtypes = [_ptr, _ptr, _ptr, _i64, _ptr, _ptr]
+        L.orc_rx_adjoint_direct.restype = _ci
+        L.orc_rx_fmgsr_adjoint.argtypes = [_ptr, _ptr, _ptr, _i64, _ci, _i64, _i64,
+                                           ctypes.POINTER(RxOptions), _ptr, _ptr]
+        L.orc_rx_fmgsr_adjoint.restype = _ci
         _LIB = L
     return _LIB
 
@@ -180,3 +210,109 @@ def fas_vcycle(u, f, gL=0.0, gR=0.0, levels=None, **opt):
     if st != 0:
         raise ValueError(f"orc_fas_vcycle failed with status {st}")
     return u
+
+
+# ---------------------------------------------------------------------------
+# Reaction operators (fmgsr_oracle_reaction.c)
+# ---------------------------------------------------------------------------
+
+def _coef(kind, a, n):
+    if a is None:
+        if RX_KINDS[kind] != 0:
+            raise ValueError("the reaction kinds need a coefficient")
+        a = np.zeros(n)
+    return _c(a)
+
+
+def rx_apply(kind, a, u, gL=0.0, gR=0.0):
+    """N(u) = L u + R(u) (R13)."""
+    u, pu = _c(u)
+    a, pa = _coef(kind, a, u.size)
+    out = np.empty_like(u)
+    lib().orc_rx_apply(RX_KINDS[kind], pa, pu, u.size, gL, gR, out.ctypes.data_as(_ptr))
+    return out
+
+
+def rx_ngs_sweep(kind, a, u, F, lo=None, hi=None, gL=0.0, gR=0.0):
+    u = np.array(u, dtype=np.float64, copy=True)
+    F, pF = _c(F)
+    a, pa = _coef(kind, a, u.size)
+    n = u.size
+    lib().orc_rx_ngs_sweep(RX_KINDS[kind], pa, u.ctypes.data_as(_ptr), pF, n,
+                           0 if lo is None else lo, n if hi is None else hi, gL, gR)
+    return u
+
+
+def rx_newton(kind, a, F, gL=0.0, gR=0.0, u0=None, max_it=30, rtol=1e-14):
+    """Newton's method with exact tridiagonal steps (R17); returns (u, steps)."""
+    F, pF = _c(F)
+    a, pa = _coef(kind, a, F.size)
+    u = np.zeros_like(F) if u0 is None else np.array(u0, dtype=np.float64, copy=True)
+    it = ctypes.c_int(0)
+    st = lib().orc_rx_newton(RX_KINDS[kind], pa, pF, F.size, gL, gR, u.ctypes.data_as(_ptr),
+                             max_it, rtol, ctypes.byref(it))
+    if st != 0:
+        raise RuntimeError(f"orc_rx_newton failed: {st}")
+    return u, it.value
+
+
+def rx_fmgsr_solve(kind, f, a=None, gL=0.0, gR=0.0, levels=None, segments=1, buffer=0,
+                   order=0, **opt):
+    """One FMG-FAS(-SR) iteration for the reaction operators (R13-R17)."""
+    f, pf = _c(f)
+    n = f.size
+    a, pa = _coef(kind, a, n)
+    if levels is None:
+        levels = int(np.log2(n)) + 1
+    o = rx_options(**opt)
+    out = np.empty_like(f)
+    st = lib().orc_rx_fmgsr_solve_ex(RX_KINDS[kind], pf, pa, gL, gR, n, levels, segments, buffer,
+                                     ctypes.byref(o), out.ctypes.data_as(_ptr), order)
+    if st != 0:
+        raise ValueError(f"orc_rx_fmgsr_solve failed with status {st}")
+    return out
+
+
+def rx_fas_vcycle(kind, u, f, a=None, gL=0.0, gR=0.0, levels=None, **opt):
+    u = np.array(u, dtype=np.float64, copy=True)
+    f, pf = _c(f)
+    n = f.size
+    a, pa = _coef(kind, a, n)
+    if levels is None:
+        levels = int(np.log2(n)) + 1
+    o = rx_options(**opt)
+    st = lib().orc_rx_fas_vcycle(RX_KINDS[kind], u.ctypes.data_as(_ptr), pf, pa, gL, gR, n,
+                                 levels, ctypes.byref(o))
+    if st != 0:
+        raise ValueError(f"orc_rx_fas_vcycle failed with status {st}")
+    return u
+
+
+def rx_adjoint_direct(kappa, u, dJdu):
+    """(grad_f, grad_kappa) from the exact adjoint solve (R18)."""
+    kappa, pk = _c(kappa)
+    u, pu = _c(u)
+    dJdu, pd = _c(dJdu)
+    gf, gk = np.empty_like(u), np.empty_like(u)
+    st = lib().orc_rx_adjoint_direct(pk, pu, pd, u.size, gf.ctypes.data_as(_ptr),
+                                     gk.ctypes.data_as(_ptr))
+    if st != 0:
+        raise RuntimeError(f"orc_rx_adjoint_direct failed: {st}")
+    return gf, gk
+
+
+def rx_fmgsr_adjoint(kappa, u, dJdu, levels=None, segments=1, buffer=0, **opt):
+    """(grad_f, grad_kappa) with lambda from one FMG-FAS-SR iteration (R18)."""
+    kappa, pk = _c(kappa)
+    u, pu = _c(u)
+    dJdu, pd = _c(dJdu)
+    n = u.size
+    if levels is None:
+        levels = int(np.log2(n)) + 1
+    o = rx_options(**opt)
+    gf, gk = np.empty_like(u), np.empty_like(u)
+    st = lib().orc_rx_fmgsr_adjoint(pk, pu, pd, n, levels, segments, buffer, ctypes.byref(o),
+                                    gf.ctypes.data_as(_ptr), gk.ctypes.data_as(_ptr))
+    if st != 0:
+        raise ValueError(f"orc_rx_fmgsr_adjoint failed with status {st}")
+    return gf, gk

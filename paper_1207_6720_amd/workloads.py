@@ -18,13 +18,25 @@ Workloads (all FP64, Dirichlet data u(0) = u(1) = 0 unless stated):
 
 For u = sum_k c_k sin(k pi x) the forcing is f = sum_k c_k (k pi)^2 sin(k pi x),
 point-sampled at the cell centres x_i = (i + 1/2)/N.
+
+Reaction problems -u'' + kappa(x) u^3 = f (batched and adjoint workloads):
+
+* kappa(x) = 1 + g(x)/2 with g = sum_{m=1..4} c_m cos(m pi x + phi_m) / sum |c_m|,
+  c_m ~ Normal(0, 1), phi_m ~ Uniform[0, 2 pi), so kappa lies in [0.5, 1.5];
+* u = sum_{k=1..8} a_k sin(k pi x), a_k ~ Normal(0, sd 1/k), and
+  f = sum_k a_k (k pi)^2 sin(k pi x) + kappa u^3 at the cell centres;
+* ``c3`` 4096 problems; problem j draws e ~ Uniform[12, 18), L = floor(e) - 5,
+  N0 = clamp(round(2^e / 2^L), 32, 63), N = N0 2^L, L + 1 levels, buffer 8;
+* ``c4`` 64 problems of N = 2^20 (N0 = 32, 16 levels), buffer 8, with a
+  seeded 8-mode target field for the least-squares functional.
 """
 from dataclasses import dataclass
 
 import numpy as np
 
 __all__ = ["Workload", "WORKLOADS", "modes", "rhs_numpy", "exact_numpy",
-           "rhs_torch", "exact_torch", "cell_centres"]
+           "rhs_torch", "exact_torch", "cell_centres", "ReactionBatch", "REACTION_WORKLOADS",
+           "reaction_batch", "reaction_params"]
 
 
 @dataclass(frozen=True)
@@ -106,3 +118,108 @@ def exact_torch(n: int, k, c, device):
     for kk, cc in zip(k, c):
         u.add_(torch.sin(x * (float(kk) * np.pi)), alpha=float(cc))
     return u
+
+
+# ---------------------------------------------------------------------------
+# Reaction problems -u'' + kappa u^3 = f
+# ---------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class ReactionBatch:
+    name: str
+    sizes: tuple      # fine cells per problem
+    levels: tuple     # levels per problem
+    buffer: int
+    seed: int
+
+    @property
+    def batch(self) -> int:
+        return len(self.sizes)
+
+    @property
+    def total(self) -> int:
+        return int(sum(self.sizes))
+
+    @property
+    def offsets(self):
+        return np.concatenate([[0], np.cumsum(self.sizes)[:-1]]).astype(np.int64)
+
+    @property
+    def description(self) -> str:
+        return (f"{self.batch} problems -u''+kappa u^3=f, N in [{min(self.sizes)}, "
+                f"{max(self.sizes)}] (total {self.total}), buffer {self.buffer}, V(2,1)")
+
+
+def reaction_batch(name: str, seed: int = 0, batch: int = None) -> ReactionBatch:
+    """Problem sizes of a reaction workload (``c3``: uneven log-uniform sizes,
+    ``c4``: equal 2^20 problems; ``small``: a quick uneven batch)."""
+    rng = np.random.default_rng([seed, 3])
+    if name in ("c3", "small"):
+        b = batch or (4096 if name == "c3" else 24)
+        lo, hi = (12.0, 18.0) if name == "c3" else (8.0, 12.0)
+        e = rng.uniform(lo, hi, size=b)
+        L = np.floor(e).astype(np.int64) - 5
+        n0 = np.clip(np.rint(2.0 ** e / 2.0 ** L), 32, 63).astype(np.int64)
+        sizes = tuple(int(a) << int(c) for a, c in zip(n0, L))
+        levels = tuple(int(c) + 1 for c in L)
+    elif name == "c4":
+        b = batch or 64
+        sizes = (1 << 20,) * b
+        levels = (16,) * b
+    else:
+        raise ValueError(name)
+    return ReactionBatch(name, sizes, levels, 8, seed)
+
+
+REACTION_WORKLOADS = ("c3", "c4", "small")
+
+
+def reaction_params(seed: int, j: int):
+    """Per-problem parameters: (a_k for k = 1..8, c_m, phi_m, target a_k)."""
+    rng = np.random.default_rng([seed, j, 7])
+    k = np.arange(1, 9, dtype=np.float64)
+    a = rng.normal(0.0, 1.0, size=8) / k
+    cm = rng.normal(0.0, 1.0, size=4)
+    phi = rng.uniform(0.0, 2.0 * np.pi, size=4)
+    target = rng.normal(0.0, 1.0, size=8) / k
+    return a, cm, phi, target
+
+
+def _reaction_fields(xp, x, a, cm, phi, target, pi):
+    """kappa, u_exact, f and u_target at cell centres x (numpy or torch)."""
+    g = 0.0 * x
+    for m in range(4):
+        g = g + float(cm[m]) * xp.cos(x * (float(m + 1) * pi) + float(phi[m]))
+    kappa = 1.0 + 0.5 * g / float(np.sum(np.abs(cm)))
+    u = 0.0 * x
+    lap = 0.0 * x
+    ut = 0.0 * x
+    for k in range(8):
+        s = xp.sin(x * (float(k + 1) * pi))
+        u = u + float(a[k]) * s
+        lap = lap + float(a[k] * ((k + 1) * pi) ** 2) * s
+        ut = ut + float(target[k]) * s
+    f = lap + kappa * (u * u * u)
+    return kappa, u, f, ut
+
+
+def reaction_problem_numpy(n: int, seed: int, j: int):
+    """(f, kappa, u_exact, u_target) of problem j, host FP64."""
+    a, cm, phi, target = reaction_params(seed, j)
+    kappa, u, f, ut = _reaction_fields(np, cell_centres(n), a, cm, phi, target, np.pi)
+    return f, kappa, u, ut
+
+
+def reaction_packed_torch(rb: ReactionBatch, device):
+    """Packed (f, kappa, u_exact, u_target) of a whole batch, generated in
+    device memory problem by problem."""
+    import torch
+    tot = rb.total
+    out = [torch.empty(tot, dtype=torch.float64, device=device) for _ in range(4)]
+    for j, (n, off) in enumerate(zip(rb.sizes, rb.offsets)):
+        a, cm, phi, target = reaction_params(rb.seed, j)
+        x = (torch.arange(n, dtype=torch.float64, device=device) + 0.5) / n
+        fields = _reaction_fields(torch, x, a, cm, phi, target, np.pi)
+        for o, v in zip(out, (fields[2], fields[0], fields[1], fields[3])):
+            o[off:off + n] = v
+    return tuple(out)
