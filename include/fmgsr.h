@@ -56,12 +56,31 @@ typedef enum {
  *   levels per patch, from the patch's extended iterate, Fig. 3 step 4). */
 enum { FMGSR_TAU_SPLIT = 0, FMGSR_TAU_LITERAL = 1 };
 
-/* Operator kinds.  POISSON: -u'' (Sec. 4). */
-enum { FMGSR_OP_POISSON = 0 };
+/* Operator kinds.
+ * POISSON          -u'' = f (Sec. 4).
+ * CUBIC_REACTION   -u'' + kappa(x) u^3 = f: the nonlinear problem FAS is made
+ *                  for (Sec. 2.2, Eqs. 1-2); smoother = red-black nonlinear
+ *                  Gauss-Seidel (one Newton step per point), coarse
+ *                  coefficient = two-cell average, coarsest level = Newton
+ *                  with exact tridiagonal steps.
+ * LINEAR_REACTION  -u'' + c(x) u = f (kappa holds c >= 0); the operator of the
+ *                  adjoint of the cubic problem.
+ * With the reaction kinds tau (Eq. 7) is nonzero: its Laplacian part cancels
+ * exactly (see FMGSR_TAU_SPLIT) and the reaction part R_H(I^ u) - I R_h(u)
+ * is added to every coarse right-hand side. */
+enum { FMGSR_OP_POISSON = 0, FMGSR_OP_CUBIC_REACTION = 1, FMGSR_OP_LINEAR_REACTION = 2 };
+
+/* Arithmetic of the smoother.  FP64: everything in FP64.  FP32_RELAX: each
+ * smoother call forms the FP64 residual once, runs its sweeps on an FP32
+ * correction (exterior correction 0; the same iteration in exact
+ * arithmetic) and adds it to the FP64 iterate; residuals, tau, transfers and
+ * the coarsest solve stay FP64.  Batched entry points only. */
+enum { FMGSR_FP64 = 0, FMGSR_FP32_RELAX = 1 };
 
 typedef struct {
-  int32_t kind;          /* FMGSR_OP_POISSON                                 */
-  const double *kappa;   /* reserved for reaction terms; must be NULL        */
+  int32_t kind;          /* FMGSR_OP_*                                        */
+  const double *kappa;   /* fmgsr_solve / fmgsr_adjoint: [n] coefficient at
+                            the cell centres (device), NULL for POISSON       */
 } fmgsr_operator;
 
 typedef struct {
@@ -75,9 +94,12 @@ typedef struct {
                             bytes, or NULL: the library then allocates and
                             frees it stream-ordered around the call            */
   size_t workspace_bytes;
+  int32_t precision;     /* FMGSR_FP64 or FMGSR_FP32_RELAX                    */
+  int32_t reserved;      /* must be 0                                         */
 } fmgsr_options;
 
-/* Defaults: V(2,1), sr_levels = 1, split tau, library-managed workspace. */
+/* Defaults: V(2,1), sr_levels = 1, split tau, FP64, library-managed
+ * workspace. */
 void fmgsr_default_options(fmgsr_options *opt);
 
 /* Bytes of device workspace fmgsr_solve needs for these sizes and options
@@ -87,7 +109,10 @@ size_t fmgsr_workspace_bytes(int64_t n, int32_t levels, const fmgsr_options *opt
 /*
  * fmgsr_solve -- one FMG-FAS-SR iteration (Fig. 3) for -u'' = f.
  *
- *   op          operator descriptor (NULL = Poisson).
+ *   op          operator descriptor (NULL = Poisson).  The reaction kinds
+ *               run as a batch of one problem (fmgsr_solve_batched: one
+ *               workgroup, N0 <= 256) and return after the stream has
+ *               finished the solve.
  *   f           [n] right-hand side at the cell centres of the finest level.
  *   g_left,
  *   g_right     Dirichlet values u(0), u(1).
@@ -116,6 +141,113 @@ fmgsr_status fmgsr_solve(const fmgsr_operator *op, const double *f, double g_lef
                          int32_t buffer, const fmgsr_options *opt, double *u_out,
                          void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Batched solves: many independent problems of uneven size in ONE persistent
+ * launch.  Every workgroup takes problems from an atomic queue (longest
+ * first) and runs the whole FMG-FAS-SR iteration of each (Fig. 3); the
+ * data-driven execution of Sec. 3 at problem granularity.
+ *
+ * Problem j has n_j fine cells (device arrays packed: its cells start at
+ * offset_j), levels_j grids with N0_j = n_j >> (levels_j - 1) <= 256 coarsest
+ * cells, Dirichlet values g[2j], g[2j+1], and (levels_j >= 2) an SR finest
+ * level cut into segments of core s_j = n_j / segments_j with `buffer` cells
+ * on each side (0..64).  A plan holds the descriptors, the launch shape and
+ * the workspace (every problem's stored levels, about 5.5 n_j doubles), so
+ * that executing it needs no allocation and no host-to-device copy.
+ * ------------------------------------------------------------------------ */
+typedef struct fmgsr_batch_s *fmgsr_batch;
+
+typedef struct {
+  int32_t threads;       /* workgroup size                                    */
+  int32_t run;           /* cells per thread (window = threads * run)         */
+  int32_t grid;          /* persistent workgroups                             */
+  int32_t halo;          /* stored-level tile halo (cells)                    */
+  int64_t lds_bytes;     /* LDS per workgroup                                 */
+  int64_t workspace_bytes;
+} fmgsr_batch_shape;
+
+/*
+ * fmgsr_batch_create -- validate a batch and build its plan (synchronous:
+ * allocates device memory and uploads descriptors).
+ *
+ *   batch          number of problems, 1..2^24.
+ *   n_host         [batch] fine cells per problem (host memory).
+ *   offset_host    [batch] offsets (elements) into the packed arrays, or NULL
+ *                  for back-to-back packing (prefix sums of n).
+ *   levels_host    [batch] grids per problem (1..31).
+ *   segments_host  [batch] SR segments per problem, or NULL: the library
+ *                  picks the largest segment core N0 2^k whose extended patch
+ *                  fits one workgroup window.  A given count must divide n_j,
+ *                  give an even core and fit the window (EINVAL otherwise).
+ *   buffer         SR buffer cells per side, 0..64.
+ *   g_host         [2 batch] Dirichlet values (g_left, g_right) per problem,
+ *                  or NULL for homogeneous data.
+ *   op_kind        FMGSR_OP_*; kappa is passed at execution.
+ *   opt            nu1, nu2 (0..16), precision; sr_levels must be 1 and
+ *                  tau_mode split (others: ENOTSUP); workspace ignored.
+ *   out            receives the plan.
+ */
+fmgsr_status fmgsr_batch_create(int32_t batch, const int64_t *n_host, const int64_t *offset_host,
+                                const int32_t *levels_host, const int64_t *segments_host,
+                                int32_t buffer, const double *g_host, int32_t op_kind,
+                                const fmgsr_options *opt, fmgsr_batch *out);
+
+/* One FMG-FAS-SR iteration of every problem (asynchronous on hip_stream).
+ * f_packed, kappa_packed (NULL for POISSON) and u_packed are device arrays
+ * covering every problem's [offset_j, offset_j + n_j).  Executions of one
+ * plan share its workspace: do not overlap them on different streams.  The
+ * enqueued work is one reset kernel and one persistent kernel, so the call
+ * can be captured into a HIP graph. */
+fmgsr_status fmgsr_batch_solve(fmgsr_batch plan, const double *f_packed,
+                               const double *kappa_packed, double *u_packed, void *hip_stream);
+
+/* Adjoint of the cubic problem (plan made with FMGSR_OP_CUBIC_REACTION): for
+ * a functional J(u) of the discrete solution u of -u'' + kappa u^3 = f,
+ * lambda solves (L + diag(3 kappa u^2)) lambda = dJ/du with homogeneous
+ * Dirichlet data (the matrix is symmetric), computed by one FMG-FAS-SR
+ * iteration of the linear reaction problem with c = 3 kappa u_fwd^2 formed
+ * on the fly on every level (nothing of the forward solve is stored but
+ * u_fwd).  Outputs grad_f = lambda and grad_kappa = -u_fwd^3 lambda (either
+ * may be NULL, not both). */
+fmgsr_status fmgsr_batch_adjoint(fmgsr_batch plan, const double *kappa_packed,
+                                 const double *u_fwd_packed, const double *dJdu_packed,
+                                 double *grad_f_packed, double *grad_kappa_packed,
+                                 void *hip_stream);
+
+/* Project autotuner: times the plan's candidate launch shapes (workgroup
+ * size) and segment sizes (the largest fitting core and half of it, unless
+ * segments were given) on these inputs, keeps the fastest and returns its
+ * time per solve in *ms_out (may be NULL).  Synchronises hip_stream;
+ * u_scratch_packed is overwritten.  Segment sizes change the SR iterate
+ * (within the method's accuracy); fmgsr_batch_query reports the choice. */
+fmgsr_status fmgsr_batch_autotune(fmgsr_batch plan, const double *f_packed,
+                                  const double *kappa_packed, double *u_scratch_packed,
+                                  void *hip_stream, double *ms_out);
+
+/* Launch shape and (if segments_out != NULL) the [batch] segment counts. */
+fmgsr_status fmgsr_batch_query(fmgsr_batch plan, fmgsr_batch_shape *shape_out,
+                               int64_t *segments_out);
+
+/* Frees the plan's device memory (synchronises the device first). */
+fmgsr_status fmgsr_batch_destroy(fmgsr_batch plan);
+
+/* One-shot forms (create, execute, synchronise hip_stream, destroy). */
+fmgsr_status fmgsr_solve_batched(int32_t batch, const int64_t *n_host, const int64_t *offset_host,
+                                 const int32_t *levels_host, const int64_t *segments_host,
+                                 int32_t buffer, const fmgsr_operator *op /* kappa packed like f */,
+                                 const double *f_packed, const double *g_host,
+                                 const fmgsr_options *opt, double *u_packed, void *hip_stream);
+
+/* Adjoint of one cubic problem (op->kind = FMGSR_OP_CUBIC_REACTION, op->kappa
+ * [n]).  u_fwd = the forward solution, or NULL: it is then recomputed by one
+ * FMG-FAS-SR iteration with f, g_left, g_right into a temporary buffer.
+ * dJ_du [n]; outputs as fmgsr_batch_adjoint.  Synchronous. */
+fmgsr_status fmgsr_adjoint(const fmgsr_operator *op, const double *f, double g_left,
+                           double g_right, int64_t n, int32_t levels, int64_t n_segments,
+                           int32_t buffer, const fmgsr_options *opt, const double *u_fwd,
+                           const double *dJ_du, double *grad_f, double *grad_kappa,
+                           void *hip_stream);
+
 /* Per-kernel timing for benchmarks.  Between fmgsr_profile_enable() and
  * fmgsr_profile_collect(), every kernel that fmgsr_solve launches whose name
  * contains `filter` (NULL or "" = every kernel) is bracketed by two HIP
@@ -140,7 +272,7 @@ int32_t fmgsr_profile_collect(fmgsr_kernel_stat *stats, int32_t max_stats);
 /* Human-readable name of a status code (static string). */
 const char *fmgsr_status_string(int32_t status);
 
-/* Library version string, e.g. "fmgsr 0.1 gfx950". */
+/* Library version string, e.g. "fmgsr 0.2 gfx950". */
 const char *fmgsr_version(void);
 
 #ifdef __cplusplus

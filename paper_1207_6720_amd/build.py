@@ -11,8 +11,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmgsr.so")
-SOURCES = [os.path.join(CSRC, "fmgsr.hip")]
-HEADERS = [os.path.join(CSRC, "fmgsr_kernels.hpp"), os.path.join(ROOT, "include", "fmgsr.h")]
+SOURCES = [os.path.join(CSRC, "fmgsr.hip"), os.path.join(CSRC, "fmgsr_batched.hip")]
+HEADERS = [os.path.join(CSRC, "fmgsr_kernels.hpp"), os.path.join(CSRC, "fmgsr_device.hpp"),
+           os.path.join(CSRC, "fmgsr_host.hpp"),
+           os.path.join(ROOT, "include", "fmgsr.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

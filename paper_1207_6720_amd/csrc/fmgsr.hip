@@ -28,7 +28,47 @@
 #include <vector>
 
 #include "fmgsr.h"
+#include "fmgsr_host.hpp"
 #include "fmgsr_kernels.hpp"
+
+namespace fmgsr {
+
+// ---------------------------------------------------------------------------
+// Optional per-launch timing (fmgsr_profile_*), shared by every entry point
+// ---------------------------------------------------------------------------
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::string g_prof_filter;
+std::vector<ProfRecord> g_prof;
+
+ProfScope::ProfScope(const char* name, double bytes, hipStream_t s) : st(s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_on) return;
+  if (!g_prof_filter.empty() && std::string(name).find(g_prof_filter) == std::string::npos) return;
+  if (hipEventCreate(&rec.start) != hipSuccess) return;
+  if (hipEventCreate(&rec.stop) != hipSuccess) { (void)hipEventDestroy(rec.start); return; }
+  rec.name = name;
+  rec.bytes = bytes;
+  on = (hipEventRecord(rec.start, st) == hipSuccess);
+}
+
+ProfScope::~ProfScope() {
+  if (!on) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (hipEventRecord(rec.stop, st) == hipSuccess) g_prof.push_back(rec);
+}
+
+bool is_device_ptr(const void* ptr) {
+  if (!ptr) return false;
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+}  // namespace fmgsr
 
 namespace fmgsr {
 namespace {
@@ -148,49 +188,6 @@ fmgsr_status plan_segments(int64_t n_segments, int32_t buffer, Plan* p) {
   return FMGSR_OK;
 }
 
-// ---------------------------------------------------------------------------
-// Optional per-launch timing (fmgsr_profile_*)
-// ---------------------------------------------------------------------------
-struct ProfRecord {
-  const char* name;
-  hipEvent_t start, stop;
-  double bytes;
-};
-std::mutex g_prof_mu;
-bool g_prof_on = false;
-std::string g_prof_filter;
-std::vector<ProfRecord> g_prof;
-
-struct ProfScope {
-  ProfRecord rec{};
-  bool on = false;
-  hipStream_t st;
-  ProfScope(const char* name, double bytes, hipStream_t s) : st(s) {
-    std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (!g_prof_on) return;
-    if (!g_prof_filter.empty() && std::string(name).find(g_prof_filter) == std::string::npos) return;
-    if (hipEventCreate(&rec.start) != hipSuccess) return;
-    if (hipEventCreate(&rec.stop) != hipSuccess) { (void)hipEventDestroy(rec.start); return; }
-    rec.name = name;
-    rec.bytes = bytes;
-    on = (hipEventRecord(rec.start, st) == hipSuccess);
-  }
-  ~ProfScope() {
-    if (!on) return;
-    std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (hipEventRecord(rec.stop, st) == hipSuccess) g_prof.push_back(rec);
-  }
-};
-
-bool is_device_ptr(const void* ptr) {
-  if (!ptr) return false;
-  hipPointerAttribute_t attr;
-  if (hipPointerGetAttributes(&attr, ptr) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
-}
 
 struct Ctx {
   const Plan* p;
@@ -429,10 +426,20 @@ fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_lef
                          double g_right, int64_t n, int32_t levels, int64_t n_segments,
                          int32_t buffer, const fmgsr_options* opt, double* u_out,
                          void* hip_stream) {
-  if (op && (op->kind != FMGSR_OP_POISSON || op->kappa != nullptr)) return FMGSR_ENOTSUP;
+  if (op && (op->kind < FMGSR_OP_POISSON || op->kind > FMGSR_OP_LINEAR_REACTION)) return FMGSR_EINVAL;
+  if (op && op->kind != FMGSR_OP_POISSON) {
+    // reaction operators: a batch of one problem (synchronous)
+    if (!is_device_ptr(op->kappa)) return FMGSR_EINVAL;
+    const double g[2] = {g_left, g_right};
+    return fmgsr_solve_batched(1, &n, nullptr, &levels, n_segments > 0 ? &n_segments : nullptr,
+                               buffer, op, f, g, opt, u_out, hip_stream);
+  }
+  if (op && op->kappa != nullptr) return FMGSR_EINVAL;
   fmgsr_options o;
   if (opt) o = *opt;
   else fmgsr_default_options(&o);
+  if (o.precision != FMGSR_FP64) return o.precision == FMGSR_FP32_RELAX ? FMGSR_ENOTSUP : FMGSR_EINVAL;
+  if (o.reserved != 0) return FMGSR_EINVAL;
   Plan p;
   fmgsr_status st = make_plan(n, levels, o, &p);
   if (st == FMGSR_OK) st = plan_segments(n_segments, buffer, &p);
@@ -537,6 +544,6 @@ const char* fmgsr_status_string(int32_t status) {
   }
 }
 
-const char* fmgsr_version(void) { return "fmgsr 0.1 gfx950"; }
+const char* fmgsr_version(void) { return "fmgsr 0.2 gfx950"; }
 
 }  // extern "C"

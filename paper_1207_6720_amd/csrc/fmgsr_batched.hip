@@ -1,0 +1,1167 @@
+// fmgsr_batched.hip -- batched FMG-FAS-SR for the 1D reaction-diffusion
+// operators (Poisson, -u'' + kappa u^3, -u'' + c u) on gfx950, and the adjoint
+// solve built on it.
+//
+// One persistent launch solves a whole batch of independent problems of
+// uneven size.  Every workgroup takes problems from an atomic queue in
+// longest-first order and runs the complete FMG-FAS-SR iteration of Fig. 3
+// for each: no data crosses workgroups, so the only synchronisation is the
+// workgroup barrier between the phases of one problem.  This is the paper's
+// data-driven execution (Sec. 3: work proceeds as soon as its inputs are
+// ready) at the granularity of problems.
+//
+// Per problem (levels 0..M, level l with n0 2^l cells; level M is the SR
+// level and is never stored):
+//   forcing     R^l = I R^{l+1} (R^M = f), A^l = I^ A^{l+1} (A^M = kappa, or
+//               3 kappa u_fwd^2 for the adjoint)
+//   coarse      Newton on level 0, each step a PCR tridiagonal solve in LDS
+//   step t<M    down visits t..1 (smooth, store U^l, coarse rhs Q^{l-1} =
+//               I F + R_H(I^ u) - I R_h(u)), coarse Newton, up visits 1..t
+//               (V^l = U^l + P(V^{l-1} - I^ U^l), smooth)
+//   step M      SR down pass per segment (Pi V^{M-1}, smooth, write I^ of the
+//               core to Uh and the core's coarse rhs to Q^{M-1}), V-cycle on
+//               the stored levels, SR up pass per segment (Pi, nu2 x
+//               [Kaczmarz, sweep], core to the output)
+// Stored-level visits walk the level in halo-exact register tiles (every
+// core equals a whole-level sweep); each visit reads arrays it does not
+// write, so the tiles of one visit are independent.
+//
+// Smoothing (nonlinear red-black Gauss-Seidel, one Newton step per point):
+//   cubic   u_i <- ((F_i h^2 + (l + r)) + 2 q u_i^3) / (D + 3 q u_i^2)
+//   linear  u_i <- (F_i h^2 + (l + r)) / (D + q),   q = a_i h^2
+// with D = 2 (3 at a boundary cell, 4 on a one-cell level).  In the FP32
+// relaxation mode each smoothing call forms the FP64 residual once, runs the
+// sweeps on an FP32 correction d (exterior d = 0) with the equivalent update
+//   d_i <- ((d_l + d_r) + r_i + q d_i^2 (2 w + u_i)) / (D + 3 q w^2),  w = u_i + d_i
+// and adds d to u in FP64; residuals, tau and the coarse solve stay FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "fmgsr.h"
+#include "fmgsr_device.hpp"
+
+namespace fmgsr {
+namespace bt {
+
+constexpr int kOpPoisson = 0, kOpCubic = 1, kOpLinear = 2;
+constexpr int kF64 = 0, kF32 = 1;
+constexpr int kMaxBatchN0 = 256;     // coarsest level solved in LDS
+constexpr int kMaxThreads = 512;
+constexpr int64_t kLvlAlign = 32;    // doubles: level arrays start 256-byte aligned
+
+enum Src : int { kZero = 0, kInterp = 1, kRestrict = 2, kDirect = 3 };
+
+struct Prob {
+  int64_t n;      // fine cells
+  int64_t off;    // offset of the problem in the packed f / kappa / u arrays
+  int64_t ws;     // offset (doubles) of its workspace slab
+  int64_t seg;    // SR segment core (fine cells)
+  int32_t M;      // levels - 1
+  int32_t n0;     // coarsest cells
+  double gL, gR;
+};
+
+struct Args {
+  const Prob* probs;
+  const int32_t* order;  // queue position -> problem
+  int32_t batch;
+  int32_t* queue;
+  const double* f;       // packed right-hand sides (adjoint: dJ/du)
+  const double* kappa;   // packed coefficient (null for Poisson)
+  const double* ufwd;    // adjoint: packed forward solution (coefficient 3 kappa u^2)
+  double* u;             // packed result (adjoint: grad_f = lambda), may be null
+  double* gk;            // adjoint: packed grad_kappa = -u^3 lambda, may be null
+  double* ws;
+  int nu1, nu2, buffer, halo;
+  int region;            // doubles of the LDS stage / coarse-solve region
+  int adjoint;           // 1: homogeneous boundary values (adjoint solve)
+};
+
+__host__ __device__ inline int64_t lvl_size(int64_t n0, int l) {
+  return ((n0 << l) + kLvlAlign - 1) / kLvlAlign * kLvlAlign;
+}
+__host__ __device__ inline int64_t lvl_off(int64_t n0, int l) {
+  int64_t o = 0;
+  for (int m = 0; m < l; ++m) o += lvl_size(n0, m);
+  return o;
+}
+// Slab of one problem: R, A, U, V, Q (levels 0..M-1 each), then Uh (n/2).
+__host__ __device__ inline int64_t slab_doubles(int64_t n0, int M) {
+  const int64_t h = lvl_off(n0, M);
+  return 5 * h + (M > 0 ? lvl_size(n0, M - 1) : 0);
+}
+
+// Per-problem view used by the device code.
+struct Ctx {
+  int64_t n, n0, seg;
+  int M;
+  double gL, gR;
+  const double* f;
+  const double* kap;
+  const double* uf;
+  double* uo;
+  double* gk;
+  double *R, *A, *U, *V, *Q, *Uh;
+  int64_t hier;  // doubles per hierarchy array
+  __device__ int64_t nl(int l) const { return n0 << l; }
+  __device__ int64_t off(int l) const { return lvl_off(n0, l); }
+  // fine-level coefficient: kappa, or 3 kappa u_fwd^2 for the adjoint
+  __device__ double coef_fine(int64_t g) const {
+    if (!kap) return 0.0;
+    if (uf) { const double v = uf[g]; return (3.0 * kap[g]) * (v * v); }
+    return kap[g];
+  }
+};
+
+__device__ __forceinline__ Ctx make_ctx(const Prob& p, const Args& a) {
+  Ctx c;
+  c.n = p.n; c.n0 = p.n0; c.seg = p.seg; c.M = p.M;
+  c.gL = a.adjoint ? 0.0 : p.gL;
+  c.gR = a.adjoint ? 0.0 : p.gR;
+  c.f = a.f + p.off;
+  c.kap = a.kappa ? a.kappa + p.off : nullptr;
+  c.uf = a.ufwd ? a.ufwd + p.off : nullptr;
+  c.uo = a.u ? a.u + p.off : nullptr;
+  c.gk = a.gk ? a.gk + p.off : nullptr;
+  c.hier = lvl_off(p.n0, p.M);
+  double* s = a.ws + p.ws;
+  c.R = s; c.A = s + c.hier; c.U = s + 2 * c.hier; c.V = s + 3 * c.hier; c.Q = s + 4 * c.hier;
+  c.Uh = s + 5 * c.hier;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// Loads in two halves (issue all, then stage), so that the HBM latencies of
+// all arrays of a tile overlap.  Cell e of the window has global index
+// wlo + e; values outside [0, n) or beyond wcount become 0.
+// ---------------------------------------------------------------------------
+template <int K, class Fn>
+__device__ __forceinline__ void issue(double (&tmp)[K], int64_t wlo, int64_t n, Fn val) {
+  const int W = blockDim.x;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t g = wlo + threadIdx.x + k * W;
+    tmp[k] = val(g < 0 ? 0 : (g >= n ? n - 1 : g));
+  }
+}
+template <int K>
+__device__ __forceinline__ void stage(double* st, const double (&tmp)[K], double (&v)[K],
+                                      int64_t wlo, int wcount, int64_t n) {
+  const int W = blockDim.x;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = threadIdx.x + k * W;
+    const int64_t g = wlo + e;
+    st[sidx<K>(e)] = (e < wcount && g >= 0 && g < n) ? tmp[k] : 0.0;
+  }
+  __syncthreads();
+  stage_to_run<K>(st, v);
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Smoothing on register runs
+// ---------------------------------------------------------------------------
+struct SweepGeom {
+  RunBounds rb;
+  double h2, gL2, gR2, bdiv;
+};
+
+__device__ __forceinline__ SweepGeom sweep_geom(int64_t g0, int K, int64_t lo, int64_t hi,
+                                                int64_t n, double gL, double gR) {
+  SweepGeom s;
+  s.rb = run_bounds(g0, K, lo, hi, n);
+  s.h2 = 1.0 / ((double)n * (double)n);
+  s.gL2 = 2.0 * gL;
+  s.gR2 = 2.0 * gR;
+  s.bdiv = (n == 1) ? 4.0 : 3.0;
+  return s;
+}
+
+// One FP64 half-sweep of colour C (0 = red = even) over the run.
+template <int K, int C, int OP>
+__device__ __forceinline__ void ngs_half(double (&u)[K], const double (&F)[K],
+                                         const double (&a)[K], const SweepGeom& s, Xch& x) {
+  double ll, rf;
+  x.swap(u[0], u[K - 1], ll, rf);
+#pragma unroll
+  for (int j = C; j < K; j += 2) {
+    double l = (j == 0) ? ll : u[j - 1];
+    double r = (j == K - 1) ? rf : u[j + 1];
+    double D = 2.0;
+    const bool bnd = (j == s.rb.jb0 || j == s.rb.jbn);
+    if (j == s.rb.jb0) { l = s.gL2; D = s.bdiv; }
+    if (j == s.rb.jbn) { r = s.gR2; D = s.bdiv; }
+    const double b = F[j] * s.h2 + (l + r);
+    double v;
+    if constexpr (OP == kOpCubic) {
+      const double q = a[j] * s.h2;
+      const double uu = u[j] * u[j];
+      v = (b + (2.0 * q) * (uu * u[j])) / (D + (3.0 * q) * uu);
+    } else if constexpr (OP == kOpLinear) {
+      const double q = a[j] * s.h2;
+      v = b / (D + q);
+    } else {
+      v = bnd ? b / D : b * 0.5;
+    }
+    if (j >= s.rb.jlo && j < s.rb.jhi) u[j] = v;
+  }
+}
+
+// One FP32 half-sweep of the correction d (correction form).
+template <int K, int C, int OP>
+__device__ __forceinline__ void cf_half(float (&d)[K], const float (&r)[K], const float (&q)[K],
+                                        const float (&ut)[K], const SweepGeom& s, float bdiv,
+                                        Xch& x) {
+  double lld, rfd;
+  x.swap((double)d[0], (double)d[K - 1], lld, rfd);
+  const float ll = (float)lld, rf = (float)rfd;
+#pragma unroll
+  for (int j = C; j < K; j += 2) {
+    float l = (j == 0) ? ll : d[j - 1];
+    float rr = (j == K - 1) ? rf : d[j + 1];
+    float D = 2.0f;
+    if (j == s.rb.jb0) { l = 0.0f; D = bdiv; }
+    if (j == s.rb.jbn) { rr = 0.0f; D = bdiv; }
+    float num = (l + rr) + r[j];
+    float den = D;
+    if constexpr (OP == kOpCubic) {
+      const float w = ut[j] + d[j];
+      num = num + q[j] * ((d[j] * d[j]) * (2.0f * w + ut[j]));
+      den = D + (3.0f * q[j]) * (w * w);
+    } else if constexpr (OP == kOpLinear) {
+      den = D + q[j];
+    }
+    const float v = num * __builtin_amdgcn_rcpf(den);
+    if (j >= s.rb.jlo && j < s.rb.jhi) d[j] = v;
+  }
+}
+
+// nu sweeps over the cells [rb.jlo, rb.jhi) of the run; cells outside are
+// frozen.
+template <int K, int OP, int PREC>
+__device__ __forceinline__ void smooth(double (&u)[K], const double (&F)[K], const double (&a)[K],
+                                       const SweepGeom& s, int nu, Xch& x) {
+  if (nu <= 0) return;
+  if constexpr (PREC == kF64) {
+    for (int it = 0; it < nu; ++it) {
+      ngs_half<K, 0, OP>(u, F, a, s, x);
+      ngs_half<K, 1, OP>(u, F, a, s, x);
+    }
+  } else {
+    // FP64 residual r = F h^2 - h^2 N(u), once per call
+    double ll, rf;
+    x.swap(u[0], u[K - 1], ll, rf);
+    float r[K], q[K], ut[K], d[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      double l = (j == 0) ? ll : u[j - 1];
+      double rr = (j == K - 1) ? rf : u[j + 1];
+      double D = 2.0;
+      if (j == s.rb.jb0) { l = s.gL2; D = s.bdiv; }
+      if (j == s.rb.jbn) { rr = s.gR2; D = s.bdiv; }
+      double Ru = 0.0, qd = 0.0;
+      if constexpr (OP == kOpCubic) { qd = a[j] * s.h2; Ru = qd * ((u[j] * u[j]) * u[j]); }
+      else if constexpr (OP == kOpLinear) { qd = a[j] * s.h2; Ru = qd * u[j]; }
+      const double res = (F[j] * s.h2 + (l + rr)) - (D * u[j] + Ru);
+      r[j] = (float)res;
+      q[j] = (float)qd;
+      ut[j] = (float)u[j];
+      d[j] = 0.0f;
+    }
+    const float bd = (float)s.bdiv;
+    for (int it = 0; it < nu; ++it) {
+      cf_half<K, 0, OP>(d, r, q, ut, s, bd, x);
+      cf_half<K, 1, OP>(d, r, q, ut, s, bd, x);
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if (j >= s.rb.jlo && j < s.rb.jhi) u[j] = u[j] + (double)d[j];
+  }
+}
+
+template <int OP>
+__device__ __forceinline__ double reaction(double a, double u) {
+  if constexpr (OP == kOpCubic) return a * ((u * u) * u);
+  else if constexpr (OP == kOpLinear) return a * u;
+  else return 0.0;
+}
+
+// Coarse right-hand side (split tau) of the run's pairs:
+//   Q_J = I F + (R_H(a^H, I^ u) - I R_h(a, u)),  a^H = I^ a.
+// g0 = global index of the run's first cell on a level of nf cells.
+template <int K, int OP>
+__device__ __forceinline__ void coarse_rhs(const double (&u)[K], const double (&F)[K],
+                                           const double (&a)[K], double (&Qc)[K / 2], int64_t g0,
+                                           int64_t nf, Xch& x) {
+  double rv[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) rv[j] = reaction<OP>(a[j], u[j]);
+  double Fl, Fr, Rl, Rr;
+  x.swap(F[0], F[K - 1], Fl, Fr);
+  x.swap(rv[0], rv[K - 1], Rl, Rr);
+  const RunBounds rb = run_bounds(g0, K, 0, nf, nf);
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) {
+    double fm = (p == 0) ? Fl : F[2 * p - 1];
+    double fp = (p == K / 2 - 1) ? Fr : F[2 * p + 2];
+    double rm = (p == 0) ? Rl : rv[2 * p - 1];
+    double rp = (p == K / 2 - 1) ? Rr : rv[2 * p + 2];
+    if (2 * p == rb.jb0) { fm = -F[2 * p]; rm = -rv[2 * p]; }
+    if (2 * p + 1 == rb.jbn) { fp = -F[2 * p + 1]; rp = -rv[2 * p + 1]; }
+    const double IF = ((fm + fp) + 3.0 * (F[2 * p] + F[2 * p + 1])) * 0.125;
+    const double IR = ((rm + rp) + 3.0 * (rv[2 * p] + rv[2 * p + 1])) * 0.125;
+    const double uh = (u[2 * p] + u[2 * p + 1]) * 0.5;
+    const double ac = (a[2 * p] + a[2 * p + 1]) * 0.5;
+    Qc[p] = IF + (reaction<OP>(ac, uh) - IR);
+  }
+}
+
+// Tiling of a stored level of n cells by windows of W = T K cells.
+struct Tiling {
+  int64_t core, ntiles, halo;
+  int wcount;
+};
+__device__ __forceinline__ Tiling tiling(int64_t n, int K, int halo) {
+  Tiling t;
+  const int64_t W = (int64_t)blockDim.x * K;
+  if (n <= W) { t.core = n; t.ntiles = 1; t.halo = 0; t.wcount = (int)n; }
+  else { t.core = W - 2 * halo; t.ntiles = (n + t.core - 1) / t.core; t.halo = halo; t.wcount = (int)W; }
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Level visits
+// ---------------------------------------------------------------------------
+
+// Down visit of stored level l: the iterate starts from src (Pi of the
+// coarser V, I^ of the finer U, or a copy), nu1 sweeps with F, the core is
+// stored to U^l and (reaction operators) the coarse rhs to Q^{l-1}.
+template <int K, int OP, int PREC>
+__device__ void down_visit(const Ctx& c, const Args& ar, int l, int src_kind, const double* src,
+                           const double* F, double* st, Xch& x) {
+  const int64_t n = c.nl(l);
+  const double* A = c.A + c.off(l);
+  double* Uo = c.U + c.off(l);
+  double* Qo = (OP != kOpPoisson) ? c.Q + c.off(l - 1) : nullptr;
+  const Tiling tl = tiling(n, K, ar.halo);
+  for (int64_t ti = 0; ti < tl.ntiles; ++ti) {
+    const int64_t clo = ti * tl.core, chi = min(clo + tl.core, n);
+    const int64_t wlo = clo - tl.halo;
+    const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
+    double u[K], Fr[K], a[K];
+    double tu[K], tf[K], ta[K];
+    double tc[K / 2];
+    if (src_kind == kInterp) {
+      const int64_t nc = n >> 1;
+      issue<K / 2>(tc, wlo >> 1, nc, [&](int64_t J) { return src[J]; });
+    } else if (src_kind == kRestrict) {
+      issue<K>(tu, wlo, n, [&](int64_t g) { return (src[2 * g] + src[2 * g + 1]) * 0.5; });
+    } else {
+      issue<K>(tu, wlo, n, [&](int64_t g) { return src[g]; });
+    }
+    issue<K>(tf, wlo, n, [&](int64_t g) { return F[g]; });
+    if constexpr (OP != kOpPoisson) issue<K>(ta, wlo, n, [&](int64_t g) { return A[g]; });
+    if (src_kind == kInterp) {
+      double cr[K / 2];
+      stage<K / 2>(st, tc, cr, wlo >> 1, (tl.wcount + 1) / 2 + 2, n >> 1);
+      interp_from_run<K>(u, cr, g0, n, src, c.gL, c.gR, x);
+    } else {
+      stage<K>(st, tu, u, wlo, tl.wcount, n);
+    }
+    stage<K>(st, tf, Fr, wlo, tl.wcount, n);
+    if constexpr (OP != kOpPoisson) stage<K>(st, ta, a, wlo, tl.wcount, n);
+    else {
+#pragma unroll
+      for (int j = 0; j < K; ++j) a[j] = 0.0;
+    }
+    const SweepGeom sg = sweep_geom(g0, K, max(wlo, (int64_t)0), min(wlo + tl.wcount, n), n,
+                                    c.gL, c.gR);
+    smooth<K, OP, PREC>(u, Fr, a, sg, ar.nu1, x);
+    store_run<K>(st, u, wlo, clo, chi, Uo);
+    if constexpr (OP != kOpPoisson) {
+      double qc[K / 2];
+      coarse_rhs<K, OP>(u, Fr, a, qc, g0, n, x);
+      store_run<K / 2>(st, qc, wlo >> 1, clo >> 1, chi >> 1, Qo);
+    }
+  }
+  __syncthreads();
+}
+
+// Up visit of stored level l: V^l = U^l + P(V^{l-1} - I^ U^l), nu2 sweeps.
+template <int K, int OP, int PREC>
+__device__ void up_visit(const Ctx& c, const Args& ar, int l, const double* F, double* st,
+                         Xch& x) {
+  const int64_t n = c.nl(l), nc = n >> 1;
+  const double* A = c.A + c.off(l);
+  const double* Up = c.U + c.off(l);
+  const double* Vc = c.V + c.off(l - 1);
+  double* Vo = c.V + c.off(l);
+  const Tiling tl = tiling(n, K, ar.halo);
+  for (int64_t ti = 0; ti < tl.ntiles; ++ti) {
+    const int64_t clo = ti * tl.core, chi = min(clo + tl.core, n);
+    const int64_t wlo = clo - tl.halo;
+    const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
+    double u[K], Fr[K], a[K], cv[K / 2];
+    double tu[K], tf[K], ta[K], tc[K / 2];
+    issue<K>(tu, wlo, n, [&](int64_t g) { return Up[g]; });
+    issue<K / 2>(tc, wlo >> 1, nc, [&](int64_t J) { return Vc[J]; });
+    issue<K>(tf, wlo, n, [&](int64_t g) { return F[g]; });
+    if constexpr (OP != kOpPoisson) issue<K>(ta, wlo, n, [&](int64_t g) { return A[g]; });
+    stage<K>(st, tu, u, wlo, tl.wcount, n);
+    stage<K / 2>(st, tc, cv, wlo >> 1, (tl.wcount + 1) / 2, nc);
+    stage<K>(st, tf, Fr, wlo, tl.wcount, n);
+    if constexpr (OP != kOpPoisson) stage<K>(st, ta, a, wlo, tl.wcount, n);
+    else {
+#pragma unroll
+      for (int j = 0; j < K; ++j) a[j] = 0.0;
+    }
+    // coarse-grid correction (Eq. 4) with homogeneous reflections
+    double e[K / 2];
+#pragma unroll
+    for (int p = 0; p < K / 2; ++p) e[p] = cv[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
+    double el, er;
+    x.swap(e[0], e[K / 2 - 1], el, er);
+    const int64_t J0 = g0 >> 1;
+#pragma unroll
+    for (int p = 0; p < K / 2; ++p) {
+      const int64_t J = J0 + p;
+      double em = (p == 0) ? el : e[p - 1];
+      double ep = (p == K / 2 - 1) ? er : e[p + 1];
+      if (J == 0) em = -e[p];
+      if (J == nc - 1) ep = -e[p];
+      u[2 * p] = u[2 * p] + (3.0 * e[p] + em) * 0.25;
+      u[2 * p + 1] = u[2 * p + 1] + (3.0 * e[p] + ep) * 0.25;
+    }
+    const SweepGeom sg = sweep_geom(g0, K, max(wlo, (int64_t)0), min(wlo + tl.wcount, n), n,
+                                    c.gL, c.gR);
+    smooth<K, OP, PREC>(u, Fr, a, sg, ar.nu2, x);
+    store_run<K>(st, u, wlo, clo, chi, Vo);
+  }
+  __syncthreads();
+}
+
+// SR down pass (Fig. 3 at the finest level, per segment): ubar = Pi V^{M-1}
+// on the extended patch, nu1 sweeps with the exterior frozen, I^ of the core
+// to Uh and (reaction operators) the core's coarse rhs to Q^{M-1}.
+template <int K, int OP, int PREC>
+__device__ void sr_down(const Ctx& c, const Args& ar, double* st, Xch& x) {
+  const int64_t n = c.n, nc = n >> 1, s = c.seg, S = n / s;
+  const int64_t pad = (ar.buffer + 2) & ~1;
+  const int wcount = (int)(s + 2 * pad);
+  const double* Vc = c.V + c.off(c.M - 1);
+  double* Qo = (OP != kOpPoisson) ? c.Q + c.off(c.M - 1) : nullptr;
+  for (int64_t i = 0; i < S; ++i) {
+    const int64_t wlo = i * s - pad;
+    const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
+    double u[K], Fr[K], a[K], cr[K / 2];
+    double tf[K], ta[K], tc[K / 2];
+    issue<K / 2>(tc, wlo >> 1, nc, [&](int64_t J) { return Vc[J]; });
+    issue<K>(tf, wlo, n, [&](int64_t g) { return c.f[g]; });
+    if constexpr (OP != kOpPoisson) issue<K>(ta, wlo, n, [&](int64_t g) { return c.coef_fine(g); });
+    stage<K / 2>(st, tc, cr, wlo >> 1, (wcount + 1) / 2 + 2, nc);
+    stage<K>(st, tf, Fr, wlo, wcount, n);
+    if constexpr (OP != kOpPoisson) stage<K>(st, ta, a, wlo, wcount, n);
+    else {
+#pragma unroll
+      for (int j = 0; j < K; ++j) a[j] = 0.0;
+    }
+    interp_from_run<K>(u, cr, g0, n, Vc, c.gL, c.gR, x);
+    const int64_t lo = max(i * s - ar.buffer, (int64_t)0), hi = min((i + 1) * s + ar.buffer, n);
+    const SweepGeom sg = sweep_geom(g0, K, lo, hi, n, c.gL, c.gR);
+    smooth<K, OP, PREC>(u, Fr, a, sg, ar.nu1, x);
+    double uh[K / 2];
+#pragma unroll
+    for (int p = 0; p < K / 2; ++p) uh[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
+    store_run<K / 2>(st, uh, wlo >> 1, (i * s) >> 1, ((i + 1) * s) >> 1, c.Uh);
+    if constexpr (OP != kOpPoisson) {
+      double qc[K / 2];
+      coarse_rhs<K, OP>(u, Fr, a, qc, g0, n, x);
+      store_run<K / 2>(st, qc, wlo >> 1, (i * s) >> 1, ((i + 1) * s) >> 1, Qo);
+    }
+  }
+  __syncthreads();
+}
+
+// SR up pass (Eq. 5, Fig. 5, per segment): ubar = Pi V^{M-1}, nu2 x
+// [Kaczmarz projection of the patch's full pairs onto I^ ubar = V^{M-1}, one
+// sweep], core to the output.  For the adjoint the output is lambda
+// (grad_f) and grad_kappa = -u_fwd^3 lambda.
+template <int K, int OP, int PREC>
+__device__ void sr_up(const Ctx& c, const Args& ar, double* st, Xch& x) {
+  const int64_t n = c.n, nc = n >> 1, s = c.seg, S = n / s;
+  const int64_t pad = (ar.buffer + 2) & ~1;
+  const int wcount = (int)(s + 2 * pad);
+  const double* Vc = c.V + c.off(c.M - 1);
+  for (int64_t i = 0; i < S; ++i) {
+    const int64_t wlo = i * s - pad;
+    const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
+    double u[K], Fr[K], a[K], cr[K / 2];
+    double tf[K], ta[K], tc[K / 2];
+    issue<K / 2>(tc, wlo >> 1, nc, [&](int64_t J) { return Vc[J]; });
+    issue<K>(tf, wlo, n, [&](int64_t g) { return c.f[g]; });
+    if constexpr (OP != kOpPoisson) issue<K>(ta, wlo, n, [&](int64_t g) { return c.coef_fine(g); });
+    stage<K / 2>(st, tc, cr, wlo >> 1, (wcount + 1) / 2 + 2, nc);
+    stage<K>(st, tf, Fr, wlo, wcount, n);
+    if constexpr (OP != kOpPoisson) stage<K>(st, ta, a, wlo, wcount, n);
+    else {
+#pragma unroll
+      for (int j = 0; j < K; ++j) a[j] = 0.0;
+    }
+    interp_from_run<K>(u, cr, g0, n, Vc, c.gL, c.gR, x);
+    const int64_t lo = max(i * s - ar.buffer, (int64_t)0), hi = min((i + 1) * s + ar.buffer, n);
+    const SweepGeom sg = sweep_geom(g0, K, lo, hi, n, c.gL, c.gR);
+    for (int it = 0; it < ar.nu2; ++it) {
+#pragma unroll
+      for (int p = 0; p < K / 2; ++p) {
+        const int64_t g = g0 + 2 * p;
+        if (g >= lo && g + 1 < hi) {
+          const double r = cr[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
+          u[2 * p] = u[2 * p] + r;
+          u[2 * p + 1] = u[2 * p + 1] + r;
+        }
+      }
+      smooth<K, OP, PREC>(u, Fr, a, sg, 1, x);
+    }
+    if (c.uo) store_run<K>(st, u, wlo, i * s, (i + 1) * s, c.uo);
+    if (c.gk) {
+      double tw[K], w[K];
+      issue<K>(tw, wlo, n, [&](int64_t g) { return c.uf[g]; });
+      stage<K>(st, tw, w, wlo, wcount, n);
+#pragma unroll
+      for (int j = 0; j < K; ++j) w[j] = -(((w[j] * w[j]) * w[j]) * u[j]);
+      store_run<K>(st, w, wlo, i * s, (i + 1) * s, c.gk);
+    }
+  }
+  __syncthreads();
+}
+
+// Forcing hierarchy: R^l = I R^{l+1}, A^l = I^ A^{l+1}, l = M-1..0.
+template <int OP>
+__device__ void forcing(const Ctx& c) {
+  const int T = blockDim.x;
+  for (int l = c.M - 1; l >= 0; --l) {
+    const int64_t nf = c.nl(l + 1), ncl = c.nl(l);
+    const bool top = (l + 1 == c.M);
+    const double* Ff = top ? c.f : c.R + c.off(l + 1);
+    const double* Af = c.A + c.off(l + 1);
+    double* Rc = c.R + c.off(l);
+    double* Ac = c.A + c.off(l);
+    for (int64_t J = threadIdx.x; J < ncl; J += T) {
+      const double f0 = Ff[2 * J], f1 = Ff[2 * J + 1];
+      const double rm = (2 * J - 1 >= 0) ? Ff[2 * J - 1] : -f0;
+      const double rp = (2 * J + 2 < nf) ? Ff[2 * J + 2] : -f1;
+      Rc[J] = ((rm + rp) + 3.0 * (f0 + f1)) * 0.125;
+      if constexpr (OP != kOpPoisson) {
+        const double a0 = top ? c.coef_fine(2 * J) : Af[2 * J];
+        const double a1 = top ? c.coef_fine(2 * J + 1) : Af[2 * J + 1];
+        Ac[J] = (a0 + a1) * 0.5;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void wg_max2(double& a, double& b, double* red) {
+  for (int o = 32; o > 0; o >>= 1) {
+    a = fmax(a, __shfl_xor(a, o));
+    b = fmax(b, __shfl_xor(b, o));
+  }
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) { red[w] = a; red[16 + w] = b; }
+  __syncthreads();
+  a = red[0];
+  b = red[16];
+  for (int i = 1; i < nw; ++i) { a = fmax(a, red[i]); b = fmax(b, red[16 + i]); }
+  __syncthreads();
+}
+
+// Coarsest level: Newton's method, each step one PCR solve of the h^2-scaled
+// tridiagonal Jacobian in LDS.  Stop when max|d| <= 1e-14 max|u|, or when
+// max|d| <= 1e-8 max|u| and the step failed to halve max|d| (rounding
+// floor), or after 30 steps.  src: kZero (start of FMG), kRestrict (I^ of
+// U^1) or kDirect (Uh).  F and A: rhs and coefficient (fine arrays when the
+// problem has one level).
+template <int OP>
+__device__ void coarse_visit(const Ctx& c, int src_kind, const double* src, const double* F,
+                             const double* A, bool fine, double* out, double* lds, double* red) {
+  const int T = blockDim.x;
+  const int64_t n = c.n0;
+  const int nn = (int)n;
+  const double h2 = 1.0 / ((double)n * (double)n);
+  double* u = lds;
+  double* Fv = u + nn;
+  double* q = Fv + nn;
+  double* P0 = q + nn;          // a, b, c, d of buffer 0
+  double* P1 = P0 + 4 * nn;     // buffer 1
+  for (int i = threadIdx.x; i < nn; i += T) {
+    u[i] = (src_kind == kZero) ? 0.0
+         : (src_kind == kRestrict) ? (src[2 * i] + src[2 * i + 1]) * 0.5 : src[i];
+    Fv[i] = F[i];
+    q[i] = (OP == kOpPoisson) ? 0.0 : (fine ? c.coef_fine(i) : A[i]) * h2;
+  }
+  __syncthreads();
+  const double gL2 = 2.0 * c.gL, gR2 = 2.0 * c.gR;
+  double dprev = 0.0;
+  for (int it = 0; it < 30; ++it) {
+    for (int i = threadIdx.x; i < nn; i += T) {
+      const double l = (i > 0) ? u[i - 1] : gL2;
+      const double r = (i < nn - 1) ? u[i + 1] : gR2;
+      const double D = (nn == 1) ? 4.0 : ((i > 0 && i < nn - 1) ? 2.0 : 3.0);
+      double Ru = 0.0, dR = 0.0;
+      if constexpr (OP == kOpCubic) { Ru = q[i] * ((u[i] * u[i]) * u[i]); dR = 3.0 * q[i] * (u[i] * u[i]); }
+      else if constexpr (OP == kOpLinear) { Ru = q[i] * u[i]; dR = q[i]; }
+      P0[i] = (i > 0) ? -1.0 : 0.0;
+      P0[nn + i] = D + dR;
+      P0[2 * nn + i] = (i < nn - 1) ? -1.0 : 0.0;
+      P0[3 * nn + i] = (Fv[i] * h2 + (l + r)) - (D * u[i] + Ru);
+    }
+    __syncthreads();
+    double* cur = P0;
+    double* nxt = P1;
+    for (int sd = 1; sd < nn; sd <<= 1) {
+      for (int i = threadIdx.x; i < nn; i += T) {
+        const double ai = cur[i], bi = cur[nn + i], ci = cur[2 * nn + i], di = cur[3 * nn + i];
+        double na = 0.0, nb = bi, nc2 = 0.0, nd = di;
+        if (i - sd >= 0) {
+          const int k = i - sd;
+          const double al = -ai / cur[nn + k];
+          na = al * cur[k];
+          nb = nb + al * cur[2 * nn + k];
+          nd = nd + al * cur[3 * nn + k];
+        }
+        if (i + sd < nn) {
+          const int k = i + sd;
+          const double ga = -ci / cur[nn + k];
+          nc2 = ga * cur[2 * nn + k];
+          nb = nb + ga * cur[k];
+          nd = nd + ga * cur[3 * nn + k];
+        }
+        nxt[i] = na; nxt[nn + i] = nb; nxt[2 * nn + i] = nc2; nxt[3 * nn + i] = nd;
+      }
+      __syncthreads();
+      double* t = cur; cur = nxt; nxt = t;
+    }
+    double dmax = 0.0, umax = 0.0;
+    for (int i = threadIdx.x; i < nn; i += T) {
+      const double d = cur[3 * nn + i] / cur[nn + i];
+      u[i] = u[i] + d;
+      dmax = fmax(dmax, fabs(d));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nn; i += T) umax = fmax(umax, fabs(u[i]));
+    wg_max2(dmax, umax, red);
+    if (dmax <= 1e-14 * umax || (it >= 1 && dmax <= 1e-8 * umax && dmax > 0.5 * dprev)) break;
+    dprev = dmax;
+  }
+  for (int i = threadIdx.x; i < nn; i += T) out[i] = u[i];
+  __syncthreads();
+}
+
+// The whole FMG-FAS-SR iteration of one problem.
+template <int K, int OP, int PREC>
+__device__ void solve_problem(const Ctx& c, const Args& ar, double* st, Xch& x, double* red) {
+  const int M = c.M;
+  if (M == 0) {
+    // one level: the exact (Newton) solve on the fine grid
+    double* out = c.uo ? c.uo : c.U;
+    coarse_visit<OP>(c, kZero, nullptr, c.f, nullptr, true, out, st, red);
+    if (c.gk) {
+      for (int64_t i = threadIdx.x; i < c.n; i += blockDim.x) {
+        const double w = c.uf[i];
+        c.gk[i] = -(((w * w) * w) * out[i]);
+      }
+    }
+    __syncthreads();
+    return;
+  }
+  forcing<OP>(c);
+  const double* Fsrc = (OP == kOpPoisson) ? c.R : c.Q;   // rhs of inner levels
+  // FMG start: level 0 from zero with the original rhs
+  coarse_visit<OP>(c, kZero, nullptr, c.R, c.A, false, c.V, st, red);
+  for (int t = 1; t <= M; ++t) {
+    const bool sr = (t == M);
+    int top;
+    if (sr) {
+      sr_down<K, OP, PREC>(c, ar, st, x);
+      top = M - 1;
+    } else {
+      top = t;
+    }
+    for (int l = top; l >= 1; --l) {
+      int sk;
+      const double* src;
+      if (l == top && !sr) { sk = kInterp; src = c.V + c.off(l - 1); }
+      else if (l == top) { sk = kDirect; src = c.Uh; }
+      else { sk = kRestrict; src = c.U + c.off(l + 1); }
+      const double* F = (l == top && !sr) ? c.R + c.off(l) : Fsrc + c.off(l);
+      down_visit<K, OP, PREC>(c, ar, l, sk, src, F, st, x);
+    }
+    {
+      int sk;
+      const double* src;
+      if (top >= 1) { sk = kRestrict; src = c.U + c.off(1); }
+      else { sk = kDirect; src = c.Uh; }   // M == 1: level 0 is the top
+      const double* F = (top == 0 && !sr) ? c.R : Fsrc;
+      coarse_visit<OP>(c, sk, src, F, c.A, false, c.V, st, red);
+    }
+    for (int l = 1; l <= top; ++l) {
+      const double* F = (l == top && !sr) ? c.R + c.off(l) : Fsrc + c.off(l);
+      up_visit<K, OP, PREC>(c, ar, l, F, st, x);
+    }
+    if (sr) sr_up<K, OP, PREC>(c, ar, st, x);
+  }
+}
+
+template <int K, int OP, int PREC>
+__global__ __launch_bounds__(kMaxThreads) void k_batched(Args a) {
+  extern __shared__ double lds[];
+  double* st = lds;                                  // a.region >= T (K + 1) doubles
+  double* red = lds + a.region;                      // 32 doubles
+  Xch x{red + 32, 0};                                // 4 T doubles
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int p = next;
+    __syncthreads();
+    if (p >= a.batch) break;
+    const Prob pr = a.probs[a.order[p]];
+    const Ctx c = make_ctx(pr, a);
+    solve_problem<K, OP, PREC>(c, a, st, x, red);
+  }
+}
+
+__global__ void k_queue_reset(int32_t* q) { *q = 0; }
+
+}  // namespace bt
+}  // namespace fmgsr
+
+// ===========================================================================
+// Host side: plans, launch, autotuner, C ABI
+// ===========================================================================
+#include "fmgsr_host.hpp"
+
+using fmgsr::bt::Prob;
+
+struct fmgsr_batch_s {
+  int device = 0;
+  int32_t batch = 0;
+  int op = 0, prec = 0, nu1 = 2, nu2 = 1, buffer = 0, halo = 0;
+  int K = 8, T = 256, grid = 0;
+  int region = 0;                 // doubles of the LDS stage / coarse region
+  size_t lds = 0;
+  int n0max = 1;
+  bool auto_segments = true;
+  std::vector<int64_t> n, off, levels_v, segs;
+  std::vector<double> g;
+  std::vector<int32_t> order;
+  Prob* d_probs = nullptr;
+  int32_t* d_order = nullptr;
+  int32_t* d_queue = nullptr;
+  double* d_ws = nullptr;
+  int64_t ws_doubles = 0;
+  double algo_bytes = 0.0;        // algorithmic bytes of one solve (profiling)
+};
+
+namespace fmgsr {
+namespace bt {
+namespace {
+
+constexpr int kRunCells = 8;
+
+int64_t pad_of(int buffer) { return (buffer + 2) & ~1; }
+
+// Largest segment core n0 2^k (even, dividing n) whose extended patch fits a
+// window of W cells; `halve` > 0 halves it that many times (autotuner).
+int64_t auto_core(int64_t n, int M, int64_t n0, int buffer, int64_t W, int halve) {
+  int64_t best = 0;
+  for (int k = 0; k <= M; ++k) {
+    const int64_t s = n0 << k;
+    if (s % 2 != 0) continue;
+    if (s + 2 * pad_of(buffer) > W) break;
+    best = s;
+  }
+  for (int i = 0; i < halve && best > 2 && (best / 2) % 2 == 0 && n % (best / 2) == 0; ++i)
+    best /= 2;
+  return best;
+}
+
+template <int OP, int PREC>
+hipError_t launch_k(const Args& a, int grid, int T, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((k_batched<kRunCells, OP, PREC>), dim3(grid), dim3(T), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch(const Args& a, int op, int prec, int grid, int T, size_t lds, hipStream_t s) {
+  if (prec == kF64) {
+    if (op == kOpCubic) return launch_k<kOpCubic, kF64>(a, grid, T, lds, s);
+    if (op == kOpLinear) return launch_k<kOpLinear, kF64>(a, grid, T, lds, s);
+    return launch_k<kOpPoisson, kF64>(a, grid, T, lds, s);
+  }
+  if (op == kOpCubic) return launch_k<kOpCubic, kF32>(a, grid, T, lds, s);
+  if (op == kOpLinear) return launch_k<kOpLinear, kF32>(a, grid, T, lds, s);
+  return launch_k<kOpPoisson, kF32>(a, grid, T, lds, s);
+}
+
+const void* kernel_ptr(int op, int prec) {
+  if (prec == kF64) {
+    if (op == kOpCubic) return (const void*)k_batched<kRunCells, kOpCubic, kF64>;
+    if (op == kOpLinear) return (const void*)k_batched<kRunCells, kOpLinear, kF64>;
+    return (const void*)k_batched<kRunCells, kOpPoisson, kF64>;
+  }
+  if (op == kOpCubic) return (const void*)k_batched<kRunCells, kOpCubic, kF32>;
+  if (op == kOpLinear) return (const void*)k_batched<kRunCells, kOpLinear, kF32>;
+  return (const void*)k_batched<kRunCells, kOpPoisson, kF32>;
+}
+
+void free_plan_device(fmgsr_batch_s* b) {
+  if (b->d_probs) (void)hipFree(b->d_probs);
+  if (b->d_order) (void)hipFree(b->d_order);
+  if (b->d_queue) (void)hipFree(b->d_queue);
+  if (b->d_ws) (void)hipFree(b->d_ws);
+  b->d_probs = nullptr; b->d_order = nullptr; b->d_queue = nullptr; b->d_ws = nullptr;
+  (void)hipGetLastError();
+}
+
+// (Re)build the descriptors for the plan's shape and segment choice and
+// upload them; allocates on first use.
+fmgsr_status build_plan(fmgsr_batch_s* b, int T, int halve) {
+  const int64_t W = (int64_t)T * kRunCells;
+  const int64_t pad = pad_of(b->buffer);
+  std::vector<Prob> pr(b->batch);
+  int64_t ws = 0;
+  double bytes = 0.0;
+  for (int j = 0; j < b->batch; ++j) {
+    Prob& p = pr[j];
+    p.n = b->n[j];
+    p.off = b->off[j];
+    p.M = (int32_t)(b->levels_v[j] - 1);
+    p.n0 = (int32_t)(p.n >> p.M);
+    p.gL = b->g[2 * j];
+    p.gR = b->g[2 * j + 1];
+    if (p.M >= 1) {
+      int64_t s;
+      if (b->auto_segments) s = auto_core(p.n, p.M, p.n0, b->buffer, W, halve);
+      else s = p.n / b->segs[j];
+      if (s < 2 || s % 2 != 0 || p.n % s != 0 || s + 2 * pad > W) return FMGSR_EINVAL;
+      p.seg = s;
+    } else {
+      p.seg = 0;
+    }
+    p.ws = ws;
+    ws += std::max<int64_t>(slab_doubles(p.n0, p.M), lvl_size(p.n0, 0));
+    // algorithmic bytes: fine level f, kappa read twice (SR down/up) and u
+    // written once; stored levels as the visits read and write them
+    const double kap = (b->op == kOpPoisson) ? 0.0 : 1.0;
+    bytes += (double)p.n * 8.0 * (2.0 * (1.0 + kap) + 1.0);
+    if (p.M >= 1) bytes += (double)p.n * 8.0 * 6.0 * (1.0 + kap);  // about 6 n of level traffic
+  }
+  if (b->auto_segments)
+    for (int j = 0; j < b->batch; ++j) b->segs[j] = pr[j].M >= 1 ? pr[j].n / pr[j].seg : 1;
+
+  // launch shape
+  b->T = T;
+  b->region = std::max(T * (kRunCells + 1), 11 * b->n0max);
+  b->lds = sizeof(double) * ((size_t)b->region + 32 + 4 * (size_t)T);
+  if (b->lds > 160 * 1024) return FMGSR_EINVAL;
+  const void* kp = kernel_ptr(b->op, b->prec);
+  if (hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return FMGSR_EDEVICE;
+  }
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kp, T, b->lds) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return FMGSR_EDEVICE;
+  }
+  per_cu = std::max(per_cu, 1);
+  b->grid = (int)std::min<int64_t>(b->batch, (int64_t)per_cu * cus);
+  b->algo_bytes = bytes;
+
+  if (!b->d_probs) {
+    if (hipMalloc((void**)&b->d_probs, sizeof(Prob) * b->batch) != hipSuccess ||
+        hipMalloc((void**)&b->d_order, sizeof(int32_t) * b->batch) != hipSuccess ||
+        hipMalloc((void**)&b->d_queue, sizeof(int32_t)) != hipSuccess) {
+      free_plan_device(b);
+      return FMGSR_ENOMEM;
+    }
+  }
+  if (ws > b->ws_doubles) {
+    if (b->d_ws) (void)hipFree(b->d_ws);
+    b->d_ws = nullptr;
+    if (hipMalloc((void**)&b->d_ws, sizeof(double) * (size_t)std::max<int64_t>(ws, 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      b->ws_doubles = 0;
+      return FMGSR_ENOMEM;
+    }
+    b->ws_doubles = ws;
+  }
+  if (hipMemcpy(b->d_probs, pr.data(), sizeof(Prob) * b->batch, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_order, b->order.data(), sizeof(int32_t) * b->batch, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    return FMGSR_EDEVICE;
+  }
+  return FMGSR_OK;
+}
+
+fmgsr_status execute(fmgsr_batch_s* b, int op, bool adjoint, const double* f, const double* kappa,
+                     const double* ufwd, double* u, double* gk, hipStream_t s) {
+  Args a;
+  a.probs = b->d_probs;
+  a.order = b->d_order;
+  a.batch = b->batch;
+  a.queue = b->d_queue;
+  a.f = f;
+  a.kappa = kappa;
+  a.ufwd = ufwd;
+  a.u = u;
+  a.gk = gk;
+  a.ws = b->d_ws;
+  a.nu1 = b->nu1;
+  a.nu2 = b->nu2;
+  a.buffer = b->buffer;
+  a.halo = b->halo;
+  a.region = b->region;
+  a.adjoint = adjoint ? 1 : 0;
+  if (op != b->op) {
+    const void* kp = kernel_ptr(op, b->prec);
+    if (hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds) != hipSuccess) {
+      (void)hipGetLastError();
+      return FMGSR_EDEVICE;
+    }
+  }
+  ProfScope ps(adjoint ? "k_batched_adjoint" : "k_batched", b->algo_bytes, s);
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, s, b->d_queue);
+  if (hipGetLastError() != hipSuccess) return FMGSR_EDEVICE;
+  if (launch(a, op, b->prec, b->grid, b->T, b->lds, s) != hipSuccess) return FMGSR_EDEVICE;
+  return FMGSR_OK;
+}
+
+}  // namespace
+}  // namespace bt
+}  // namespace fmgsr
+
+using namespace fmgsr;
+
+extern "C" {
+
+fmgsr_status fmgsr_batch_create(int32_t batch, const int64_t* n_host, const int64_t* offset_host,
+                                const int32_t* levels_host, const int64_t* segments_host,
+                                int32_t buffer, const double* g_host, int32_t op_kind,
+                                const fmgsr_options* opt, fmgsr_batch* out) {
+  if (!out) return FMGSR_EINVAL;
+  *out = nullptr;
+  if (batch < 1 || batch > (1 << 24) || !n_host || !levels_host) return FMGSR_EINVAL;
+  if (buffer < 0 || buffer > 64) return FMGSR_EINVAL;
+  if (op_kind < FMGSR_OP_POISSON || op_kind > FMGSR_OP_LINEAR_REACTION) return FMGSR_EINVAL;
+  fmgsr_options o;
+  if (opt) o = *opt;
+  else fmgsr_default_options(&o);
+  if (o.nu1 < 0 || o.nu1 > 16 || o.nu2 < 0 || o.nu2 > 16) return FMGSR_EINVAL;
+  if (o.precision != FMGSR_FP64 && o.precision != FMGSR_FP32_RELAX) return FMGSR_EINVAL;
+  if (o.reserved != 0) return FMGSR_EINVAL;
+  if (o.tau_mode != FMGSR_TAU_SPLIT) return FMGSR_ENOTSUP;
+  auto* b = new (std::nothrow) fmgsr_batch_s;
+  if (!b) return FMGSR_ENOMEM;
+  b->batch = batch;
+  b->op = op_kind;
+  b->prec = o.precision;
+  b->nu1 = o.nu1;
+  b->nu2 = o.nu2;
+  b->buffer = buffer;
+  b->halo = ((2 * std::max(o.nu1, o.nu2) + 4) + 1) & ~1;
+  b->auto_segments = (segments_host == nullptr);
+  b->n.resize(batch); b->off.resize(batch); b->levels_v.resize(batch); b->segs.assign(batch, 1);
+  b->g.assign(2 * (size_t)batch, 0.0);
+  int64_t run = 0;
+  for (int j = 0; j < batch; ++j) {
+    const int64_t n = n_host[j];
+    const int32_t L = levels_host[j];
+    if (n < 1 || L < 1 || L > 31) { delete b; return FMGSR_EINVAL; }
+    const int M = L - 1;
+    if (n % ((int64_t)1 << M) != 0 || (n >> M) > bt::kMaxBatchN0) { delete b; return FMGSR_EINVAL; }
+    if (M >= 1 && o.sr_levels != 1) { delete b; return FMGSR_ENOTSUP; }
+    b->n[j] = n;
+    b->levels_v[j] = L;
+    b->off[j] = offset_host ? offset_host[j] : run;
+    if (b->off[j] < 0) { delete b; return FMGSR_EINVAL; }
+    run += n;
+    b->n0max = std::max<int>(b->n0max, (int)(n >> M));
+    if (segments_host && M >= 1) {
+      const int64_t sg = segments_host[j];
+      if (sg < 1 || n % sg != 0) { delete b; return FMGSR_EINVAL; }
+      const int64_t s = n / sg;
+      if (s % 2 != 0 || s + 2 * bt::pad_of(buffer) > (int64_t)bt::kMaxThreads * bt::kRunCells) {
+        delete b;
+        return FMGSR_EINVAL;
+      }
+      b->segs[j] = sg;
+    }
+    if (g_host) { b->g[2 * j] = g_host[2 * j]; b->g[2 * j + 1] = g_host[2 * j + 1]; }
+  }
+  // longest first
+  b->order.resize(batch);
+  std::iota(b->order.begin(), b->order.end(), 0);
+  std::stable_sort(b->order.begin(), b->order.end(),
+                   [&](int32_t x, int32_t y) { return b->n[x] > b->n[y]; });
+  if (hipGetDevice(&b->device) != hipSuccess) { (void)hipGetLastError(); delete b; return FMGSR_EDEVICE; }
+  const fmgsr_status st = bt::build_plan(b, 256, 0);
+  if (st != FMGSR_OK) { bt::free_plan_device(b); delete b; return st; }
+  *out = b;
+  return FMGSR_OK;
+}
+
+fmgsr_status fmgsr_batch_solve(fmgsr_batch b, const double* f_packed, const double* kappa_packed,
+                               double* u_packed, void* hip_stream) {
+  if (!b || !is_device_ptr(f_packed) || !is_device_ptr(u_packed)) return FMGSR_EINVAL;
+  if (b->op == FMGSR_OP_POISSON ? kappa_packed != nullptr : !is_device_ptr(kappa_packed))
+    return FMGSR_EINVAL;
+  if ((const void*)f_packed == (const void*)u_packed) return FMGSR_EINVAL;
+  return bt::execute(b, b->op, false, f_packed, kappa_packed, nullptr, u_packed, nullptr,
+                     (hipStream_t)hip_stream);
+}
+
+fmgsr_status fmgsr_batch_adjoint(fmgsr_batch b, const double* kappa_packed,
+                                 const double* u_fwd_packed, const double* dJdu_packed,
+                                 double* grad_f_packed, double* grad_kappa_packed,
+                                 void* hip_stream) {
+  if (!b) return FMGSR_EINVAL;
+  if (b->op != FMGSR_OP_CUBIC_REACTION) return FMGSR_ENOTSUP;
+  if (!is_device_ptr(kappa_packed) || !is_device_ptr(u_fwd_packed) || !is_device_ptr(dJdu_packed))
+    return FMGSR_EINVAL;
+  if (!grad_f_packed && !grad_kappa_packed) return FMGSR_EINVAL;
+  if ((grad_f_packed && !is_device_ptr(grad_f_packed)) ||
+      (grad_kappa_packed && !is_device_ptr(grad_kappa_packed)))
+    return FMGSR_EINVAL;
+  return bt::execute(b, bt::kOpLinear, true, dJdu_packed, kappa_packed, u_fwd_packed,
+                     grad_f_packed, grad_kappa_packed, (hipStream_t)hip_stream);
+}
+
+fmgsr_status fmgsr_batch_autotune(fmgsr_batch b, const double* f_packed, const double* kappa_packed,
+                                  double* u_scratch_packed, void* hip_stream, double* ms_out) {
+  if (!b) return FMGSR_EINVAL;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int shapes[2] = {256, 512};
+  const int halves = b->auto_segments ? 2 : 1;
+  double best = 1e300;
+  int bestT = b->T, bestH = 0;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    return FMGSR_EDEVICE;
+  }
+  fmgsr_status st = FMGSR_OK;
+  for (int T : shapes) {
+    for (int h = 0; h < halves && st == FMGSR_OK; ++h) {
+      fmgsr_status bs = bt::build_plan(b, T, h);
+      if (bs == FMGSR_EINVAL) continue;  // shape does not fit these problems
+      if (bs != FMGSR_OK) { st = bs; break; }
+      st = fmgsr_batch_solve(b, f_packed, kappa_packed, u_scratch_packed, hip_stream);  // warm
+      if (st != FMGSR_OK) break;
+      const int reps = 3;
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps && st == FMGSR_OK; ++r)
+        st = fmgsr_batch_solve(b, f_packed, kappa_packed, u_scratch_packed, hip_stream);
+      (void)hipEventRecord(e1, s);
+      float ms = 0.f;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        (void)hipGetLastError();
+        st = FMGSR_EDEVICE;
+        break;
+      }
+      if (ms / reps < best) { best = ms / reps; bestT = T; bestH = h; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != FMGSR_OK) return st;
+  st = bt::build_plan(b, bestT, bestH);
+  if (st == FMGSR_OK && ms_out) *ms_out = best;
+  return st;
+}
+
+fmgsr_status fmgsr_batch_query(fmgsr_batch b, fmgsr_batch_shape* shape, int64_t* segments_out) {
+  if (!b) return FMGSR_EINVAL;
+  if (shape) {
+    shape->threads = b->T;
+    shape->run = bt::kRunCells;
+    shape->grid = b->grid;
+    shape->halo = b->halo;
+    shape->lds_bytes = (int64_t)b->lds;
+    shape->workspace_bytes = b->ws_doubles * (int64_t)sizeof(double);
+  }
+  if (segments_out)
+    for (int j = 0; j < b->batch; ++j) segments_out[j] = b->segs[j];
+  return FMGSR_OK;
+}
+
+fmgsr_status fmgsr_batch_destroy(fmgsr_batch b) {
+  if (!b) return FMGSR_EINVAL;
+  (void)hipDeviceSynchronize();
+  bt::free_plan_device(b);
+  delete b;
+  return FMGSR_OK;
+}
+
+fmgsr_status fmgsr_solve_batched(int32_t batch, const int64_t* n_host, const int64_t* offset_host,
+                                 const int32_t* levels_host, const int64_t* segments_host,
+                                 int32_t buffer, const fmgsr_operator* op, const double* f_packed,
+                                 const double* g_host, const fmgsr_options* opt, double* u_packed,
+                                 void* hip_stream) {
+  const int32_t kind = op ? op->kind : FMGSR_OP_POISSON;
+  fmgsr_batch b = nullptr;
+  fmgsr_status st = fmgsr_batch_create(batch, n_host, offset_host, levels_host, segments_host,
+                                       buffer, g_host, kind, opt, &b);
+  if (st != FMGSR_OK) return st;
+  st = fmgsr_batch_solve(b, f_packed, op ? op->kappa : nullptr, u_packed, hip_stream);
+  if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) {
+    (void)hipGetLastError();
+    if (st == FMGSR_OK) st = FMGSR_EDEVICE;
+  }
+  fmgsr_batch_destroy(b);
+  return st;
+}
+
+fmgsr_status fmgsr_adjoint(const fmgsr_operator* op, const double* f, double g_left,
+                           double g_right, int64_t n, int32_t levels, int64_t n_segments,
+                           int32_t buffer, const fmgsr_options* opt, const double* u_fwd,
+                           const double* dJ_du, double* grad_f, double* grad_kappa,
+                           void* hip_stream) {
+  if (!op || op->kind != FMGSR_OP_CUBIC_REACTION) return FMGSR_ENOTSUP;
+  const int64_t nn = n;
+  const double g[2] = {g_left, g_right};
+  fmgsr_batch b = nullptr;
+  fmgsr_status st = fmgsr_batch_create(1, &nn, nullptr, &levels, n_segments > 0 ? &n_segments : nullptr,
+                                       buffer, g, FMGSR_OP_CUBIC_REACTION, opt, &b);
+  if (st != FMGSR_OK) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  double* tmp = nullptr;
+  if (!u_fwd) {
+    if (hipMalloc((void**)&tmp, sizeof(double) * (size_t)n) != hipSuccess) {
+      (void)hipGetLastError();
+      fmgsr_batch_destroy(b);
+      return FMGSR_ENOMEM;
+    }
+    st = fmgsr_batch_solve(b, f, op->kappa, tmp, hip_stream);
+    u_fwd = tmp;
+  }
+  if (st == FMGSR_OK) st = fmgsr_batch_adjoint(b, op->kappa, u_fwd, dJ_du, grad_f, grad_kappa, hip_stream);
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipGetLastError();
+    if (st == FMGSR_OK) st = FMGSR_EDEVICE;
+  }
+  if (tmp) (void)hipFree(tmp);
+  fmgsr_batch_destroy(b);
+  return st;
+}
+
+}  // extern "C"

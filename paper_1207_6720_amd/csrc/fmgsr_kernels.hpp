@@ -1,14 +1,7 @@
-// fmgsr_kernels.hpp -- gfx950 kernels of the FMG-FAS-SR solver (1D model
-// problem, FP64).  Included by fmgsr.hip only.
-//
-// Execution model.  A tile kernel gives each workgroup a contiguous window
-// of W*K cells of a level; thread t owns the run of K consecutive cells
-// [t K, t K + K) of the window in registers.  HBM is only touched through
-// coalesced lane-per-element loops (lane i handles window cells i + k W)
-// that go through a padded LDS stage; the smoothing itself runs on the
-// register runs, and LDS only carries one boundary value per thread per
-// half-sweep: red cells (even index) need the left neighbour's last cell,
-// black cells the right neighbour's first.
+// fmgsr_kernels.hpp -- gfx950 kernels of the single-problem FMG-FAS-SR
+// solver (1D Poisson, FP64).  Included by fmgsr.hip only; the device
+// helpers (stencils, exchange, register runs, staged loads) are in
+// fmgsr_device.hpp.
 //
 // Vertical processing (Sec. 1, Sec. 3: the multigrid cycle is walked
 // "vertically" through each patch).  A down kernel starts from the window
@@ -19,501 +12,14 @@
 // Windows overlap by a halo that absorbs the cells made stale by the window
 // edge (the host sizes it), so every core value equals what a sweep over
 // the whole level computes: same operations on the same operands.
-//
-// Stencils (Sec. 4; appendix operator assembly), level with n cells, h = 1/n,
-// Dirichlet values gL, gR entering through odd reflections about the faces:
-//   point update   u_i <- (F_i h^2 + (u_{i-1} + u_{i+1})) / 2, boundary cells
-//                  use 2 gL (2 gR) for the missing neighbour and divide by 3
-//   Pi (FMG)       child 2J: (105 c_J + 35 c_{J-1} - 7 c_{J+1} - 5 c_{J-2})/128
-//                  child 2J+1 mirrored (cubic interpolation, Sec. 2.3)
-//   I^ (solution)  (u_{2J} + u_{2J+1}) / 2
-//   I  (rhs, FW)   ((r_{2J-1} + r_{2J+2}) + 3 (r_{2J} + r_{2J+1})) / 8
-//   P  (correction) child 2J: (3 e_J + e_{J-1}) / 4, child 2J+1 mirrored
-// Each is one fixed expression tree; the library is built without FMA
-// contraction so that results are reproducible operation by operation.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fmgsr_device.hpp"
+
 namespace fmgsr {
-
-constexpr int kRun = 16;           // cells per thread at the top of a tile
-constexpr int kTileThreads = 256;  // threads per stored-level tile
-constexpr int kMaxFuse = 4;        // levels per vertical kernel
-constexpr int kTileHalo = 64;      // window halo (cells of the top level)
-constexpr int kSegRun = 8;         // cells per thread on the SR level
-constexpr int kSegMaxThreads = 1024;
-
-// ---------------------------------------------------------------------------
-// Small helpers
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ double ld(const double* __restrict__ p, int64_t i, int64_t n) {
-  return (i >= 0 && i < n) ? p[i] : 0.0;
-}
-
-// Coarse value at index J in [-2, nc+1], with the Dirichlet reflection
-// u_{-1-j} = 2 gL - u_j, u_{nc+j} = 2 gR - u_{nc-1-j} applied as often as
-// the (possibly one-cell) level requires.
-__device__ __forceinline__ double coarse_at(const double* __restrict__ c, int64_t nc, int64_t J,
-                                            double gL, double gR) {
-  if (J >= 0 && J < nc) return c[J];
-  if (J < 0) {
-    const int64_t m = -1 - J;
-    const double in = (m < nc) ? c[m] : 2.0 * gR - c[2 * nc - 1 - m];
-    return 2.0 * gL - in;
-  }
-  const int64_t m = 2 * nc - 1 - J;
-  const double in = (m >= 0) ? c[m] : 2.0 * gL - c[-1 - m];
-  return 2.0 * gR - in;
-}
-
-__device__ __forceinline__ double interp_even(double cm2, double cm1, double c0, double cp1) {
-  return (((105.0 * c0 + 35.0 * cm1) - 7.0 * cp1) - 5.0 * cm2) * 0.0078125;
-}
-__device__ __forceinline__ double interp_odd(double cm1, double c0, double cp1, double cp2) {
-  return (((105.0 * c0 + 35.0 * cp1) - 7.0 * cm1) - 5.0 * cp2) * 0.0078125;
-}
-
-// Point Gauss-Seidel update of cell g (omega = 1) from its neighbours.
-__device__ __forceinline__ double relax(double fj, double l, double r, int64_t g, int64_t n,
-                                        double h2, double gL2, double gR2) {
-  if (g > 0 && g < n - 1) return (fj * h2 + (l + r)) * 0.5;
-  if (g == 0) l = gL2;
-  if (g == n - 1) r = gR2;
-  const double num = fj * h2 + (l + r);
-  return (n == 1) ? num / 4.0 : num / 3.0;
-}
-
-// ---------------------------------------------------------------------------
-// Neighbour exchange: each thread publishes its first and last value and
-// reads its left neighbour's last and right neighbour's first.  Two LDS
-// buffers are used alternately, so one barrier per exchange suffices.
-// ---------------------------------------------------------------------------
-struct Xch {
-  double* buf;  // 4 * W doubles
-  int sel;
-  __device__ void swap(double first, double last, double& left_last, double& right_first) {
-    const int W = blockDim.x, t = threadIdx.x;
-    double* b = buf + (sel ? 2 * W : 0);
-    sel ^= 1;
-    b[t] = first;
-    b[W + t] = last;
-    __syncthreads();
-    left_last = (t > 0) ? b[W + t - 1] : 0.0;
-    right_first = (t + 1 < W) ? b[t + 1] : 0.0;
-  }
-  // one value only: the left neighbour's `mine` (0 for the first thread)
-  __device__ double from_left(double mine) {
-    const int W = blockDim.x, t = threadIdx.x;
-    double* b = buf + (sel ? 2 * W : 0);
-    sel ^= 1;
-    b[t] = mine;
-    __syncthreads();
-    return (t > 0) ? b[t - 1] : 0.0;
-  }
-  // the right neighbour's `mine` (0 for the last thread)
-  __device__ double from_right(double mine) {
-    const int W = blockDim.x, t = threadIdx.x;
-    double* b = buf + (sel ? 2 * W : 0);
-    sel ^= 1;
-    b[t] = mine;
-    __syncthreads();
-    return (t + 1 < W) ? b[t + 1] : 0.0;
-  }
-};
-
-// Per-run bounds in 32-bit local indices (0..K): updatable cells [jlo, jhi)
-// and the run positions of the first and last cell of the level (-1 if the
-// run does not hold them).
-struct RunBounds {
-  int jlo, jhi, jb0, jbn;
-};
-
-__device__ __forceinline__ RunBounds run_bounds(int64_t g0, int K, int64_t lo, int64_t hi,
-                                                int64_t n) {
-  RunBounds b;
-  const int64_t a = lo - g0, c = hi - g0, z = -g0, e = n - 1 - g0;
-  b.jlo = (int)(a < 0 ? 0 : (a > K ? K : a));
-  b.jhi = (int)(c < 0 ? 0 : (c > K ? K : c));
-  b.jb0 = (z >= 0 && z < K) ? (int)z : -1;
-  b.jbn = (e >= 0 && e < K) ? (int)e : -1;
-  return b;
-}
-
-// One half-sweep of colour C (0 = red = even index) over the run u[0..K)
-// (first cell even), updating the cells [jlo, jhi) of the run.
-template <int K, int C>
-__device__ __forceinline__ void rb_half(double (&u)[K], const double (&f)[K], const RunBounds& rb,
-                                        double h2, double gL2, double gR2, double bdiv, Xch& x) {
-  double ll, rf;
-  x.swap(u[0], u[K - 1], ll, rf);
-#pragma unroll
-  for (int j = C; j < K; j += 2) {
-    double l = (j == 0) ? ll : u[j - 1];
-    double r = (j == K - 1) ? rf : u[j + 1];
-    double v;
-    if (j != rb.jb0 && j != rb.jbn) {
-      v = (f[j] * h2 + (l + r)) * 0.5;
-    } else {
-      if (j == rb.jb0) l = gL2;
-      if (j == rb.jbn) r = gR2;
-      v = (f[j] * h2 + (l + r)) / bdiv;
-    }
-    if (j >= rb.jlo && j < rb.jhi) u[j] = v;
-  }
-}
-
-template <int K>
-__device__ __forceinline__ void rb_sweeps(double (&u)[K], const double (&f)[K], int64_t g0,
-                                          int nu, int64_t lo, int64_t hi, int64_t n,
-                                          double gL, double gR, Xch& x) {
-  const double h2 = 1.0 / ((double)n * (double)n);
-  const double gL2 = 2.0 * gL, gR2 = 2.0 * gR;
-  const double bdiv = (n == 1) ? 4.0 : 3.0;
-  const RunBounds rb = run_bounds(g0, K, lo, hi, n);
-  for (int s = 0; s < nu; ++s) {
-    rb_half<K, 0>(u, f, rb, h2, gL2, gR2, bdiv, x);
-    rb_half<K, 1>(u, f, rb, h2, gL2, gR2, bdiv, x);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// LDS stage: window cell e lives at e + e / K (one pad slot per run, so a
-// thread reading its run and lanes walking consecutive cells are both free
-// of bank conflicts).
-// ---------------------------------------------------------------------------
-template <int K>
-__device__ __forceinline__ int sidx(int e) { return e + e / K; }
-
-// stage -> registers: thread t takes cells [t K, t K + K)
-template <int K>
-__device__ __forceinline__ void stage_to_run(const double* st, double (&v)[K]) {
-  const int base = threadIdx.x * (K + 1);
-#pragma unroll
-  for (int j = 0; j < K; ++j) v[j] = st[base + j];
-}
-template <int K>
-__device__ __forceinline__ void run_to_stage(double* st, const double (&v)[K]) {
-  const int base = threadIdx.x * (K + 1);
-#pragma unroll
-  for (int j = 0; j < K; ++j) st[base + j] = v[j];
-}
-
-// Coalesced load of window cells [0, W K) (cell e = global wlo + e, valid
-// while e < wcount) into registers through the stage: v = val(global index)
-// for cells in [0, n), 0 elsewhere.  All K loads are issued unconditionally
-// (at a clamped, in-range index) before any is consumed, so their latencies
-// overlap; the validity test only selects the value.
-template <int K, class Fn>
-__device__ __forceinline__ void load_run(double* st, double (&v)[K], int64_t wlo, int wcount,
-                                         int64_t n, Fn val) {
-  const int W = blockDim.x;
-  double tmp[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int64_t g = wlo + threadIdx.x + k * W;
-    tmp[k] = val(g < 0 ? 0 : (g >= n ? n - 1 : g));
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int e = threadIdx.x + k * W;
-    const int64_t g = wlo + e;
-    st[sidx<K>(e)] = (e < wcount && g >= 0 && g < n) ? tmp[k] : 0.0;
-  }
-  __syncthreads();
-  stage_to_run<K>(st, v);
-  __syncthreads();
-}
-
-// Registers -> coalesced store of window cells whose global index lies in
-// [lo, hi).
-template <int K>
-__device__ __forceinline__ void store_run(double* st, const double (&v)[K], int64_t wlo,
-                                          int64_t lo, int64_t hi, double* __restrict__ out) {
-  const int W = blockDim.x;
-  run_to_stage<K>(st, v);
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int e = threadIdx.x + k * W;
-    const int64_t g = wlo + e;
-    if (g >= lo && g < hi) out[g] = st[sidx<K>(e)];
-  }
-  __syncthreads();
-}
-
-// Pi of the coarse level into the runs.  The coarse cells under the run,
-// c[0..K/2) = J0..J0+K/2-1, arrive as one coalesced load; the two coarse
-// values on each side come from the neighbouring threads (window-edge
-// threads read them from HBM), so Pi is exact on the whole window.  Cells
-// beyond the domain use the Dirichlet reflections (nested for a one-cell
-// level), cells outside [0, n) are set to 0.
-template <int K>
-__device__ __forceinline__ void interp_from_run(double (&u)[K], const double (&c)[K / 2],
-                                                int64_t g0, int64_t n,
-                                                const double* __restrict__ cg, double gL,
-                                                double gR, Xch& x) {
-  const int64_t nc = n >> 1;
-  const int64_t J0 = g0 >> 1;
-  double l1, r0, l2, r1;
-  x.swap(c[0], c[K / 2 - 1], l1, r0);
-  x.swap(c[1], c[K / 2 - 2], l2, r1);
-  auto at = [&](int64_t j) { return cg[j < 0 ? 0 : (j >= nc ? nc - 1 : j)]; };
-  if (threadIdx.x == 0) { l2 = at(J0 - 2); l1 = at(J0 - 1); }
-  if (threadIdx.x == blockDim.x - 1) { r0 = at(J0 + K / 2); r1 = at(J0 + K / 2 + 1); }
-  double e[K / 2 + 4];  // coarse J0-2 .. J0+K/2+1
-  e[0] = l2;
-  e[1] = l1;
-#pragma unroll
-  for (int p = 0; p < K / 2; ++p) e[p + 2] = c[p];
-  e[K / 2 + 2] = r0;
-  e[K / 2 + 3] = r1;
-#pragma unroll
-  for (int p = 0; p < K / 2; ++p) {
-    const int64_t J = J0 + p;
-    const double r0p = e[p + 2];
-    const double vm1 = (J >= 1) ? e[p + 1] : 2.0 * gL - r0p;
-    const double vp1 = (J + 1 < nc) ? e[p + 3] : 2.0 * gR - r0p;
-    const double vm2 = (J >= 2) ? e[p] : ((J == 1) ? 2.0 * gL - e[p + 1] : 2.0 * gL - vp1);
-    const double vp2 = (J + 2 < nc) ? e[p + 4] : ((J + 2 == nc) ? 2.0 * gR - e[p + 3] : 2.0 * gR - vm1);
-    const bool in = (J >= 0 && J < nc);
-    u[2 * p] = in ? interp_even(vm2, vm1, r0p, vp1) : 0.0;
-    u[2 * p + 1] = in ? interp_odd(vm1, r0p, vp1, vp2) : 0.0;
-  }
-}
-
-// Pi of the coarse level into the window (coarse run loaded here).
-template <int K>
-__device__ __forceinline__ void load_interp_run(double* st, double (&v)[K], int64_t wlo,
-                                                int wcount, int64_t n,
-                                                const double* __restrict__ c, double gL,
-                                                double gR, Xch& x) {
-  // coarse cells under the window plus the two the last valid pairs reach
-  double cr[K / 2];
-  load_run<K / 2>(st, cr, wlo >> 1, (wcount + 1) / 2 + 2, n >> 1, [&](int64_t J) { return c[J]; });
-  interp_from_run<K>(v, cr, wlo + (int64_t)threadIdx.x * K, n, c, gL, gR, x);
-}
-
-// I^ of the finer level (pairs read as one 16-byte load) into the window.
-template <int K>
-__device__ __forceinline__ void load_restrict_run(double* st, double (&v)[K], int64_t wlo,
-                                                  int wcount, int64_t n,
-                                                  const double* __restrict__ fine) {
-  const double2* __restrict__ f2 = reinterpret_cast<const double2*>(fine);
-  load_run<K>(st, v, wlo, wcount, n, [&](int64_t g) {
-    const double2 p = f2[g];
-    return (p.x + p.y) * 0.5;
-  });
-}
-
-// In-register restriction of a run to the next coarser level:
-// u1 = I^ u (local pairs), f1 = I f (full weighting; needs the neighbours'
-// edge values).  g0 is the global index of u[0] on the finer level (nf cells).
-template <int K>
-__device__ __forceinline__ void restrict_runs(const double (&u)[K], const double (&f)[K],
-                                              double (&u1)[K / 2], double (&f1)[K / 2],
-                                              int64_t g0, int64_t nf, Xch& x) {
-  double fl, fr;
-  x.swap(f[0], f[K - 1], fl, fr);
-  const RunBounds rb = run_bounds(g0, K, 0, nf, nf);
-#pragma unroll
-  for (int p = 0; p < K / 2; ++p) {
-    u1[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
-    double rm = (p == 0) ? fl : f[2 * p - 1];
-    double rp = (p == K / 2 - 1) ? fr : f[2 * p + 2];
-    if (2 * p == rb.jb0) rm = -f[2 * p];
-    if (2 * p + 1 == rb.jbn) rp = -f[2 * p + 1];
-    f1[p] = ((rm + rp) + 3.0 * (f[2 * p] + f[2 * p + 1])) * 0.125;
-  }
-}
-
-// Same full weighting for a right-hand side only.
-template <int K>
-__device__ __forceinline__ void restrict_rhs_run(const double (&f)[K], double (&f1)[K / 2],
-                                                 int64_t g0, int64_t nf, Xch& x) {
-  double fl, fr;
-  x.swap(f[0], f[K - 1], fl, fr);
-  const RunBounds rb = run_bounds(g0, K, 0, nf, nf);
-#pragma unroll
-  for (int p = 0; p < K / 2; ++p) {
-    double rm = (p == 0) ? fl : f[2 * p - 1];
-    double rp = (p == K / 2 - 1) ? fr : f[2 * p + 2];
-    if (2 * p == rb.jb0) rm = -f[2 * p];
-    if (2 * p + 1 == rb.jbn) rp = -f[2 * p + 1];
-    f1[p] = ((rm + rp) + 3.0 * (f[2 * p] + f[2 * p + 1])) * 0.125;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Interior fast paths.  A workgroup whose window lies inside the level with a
-// margin (no domain boundary, no reflection, no clipping) takes these: loads
-// and stores at plain offsets from one base pointer, Pi and full weighting
-// without boundary cases, and red-black updates without per-cell tests.  An
-// interior update is computed as fma(l + r, 1/2, F h^2 / 2): the product by
-// 1/2 is exact, so this rounds exactly like (F h^2 + (l + r)) / 2 (for normal
-// numbers; scaling by 2 commutes with rounding).  Cells at the window edge of
-// a tile are updated from a missing neighbour instead of being frozen; they
-// go stale at the same rate either way and the halo absorbs them.
-// ---------------------------------------------------------------------------
-
-// Coalesced load of window cells [0, W K) from base (all inside the level),
-// through the stage, into the runs.  Cells e >= count read base[0] and are
-// set to 0 (they lie past the part of the window in use).
-template <int K, bool kAll>
-__device__ __forceinline__ void load_run_fast(double* st, double (&v)[K],
-                                              const double* __restrict__ base, int count) {
-  const int W = blockDim.x;
-  double tmp[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int e = threadIdx.x + k * W;
-    tmp[k] = base[(kAll || e < count) ? e : 0];
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int e = threadIdx.x + k * W;
-    st[sidx<K>(e)] = (kAll || e < count) ? tmp[k] : 0.0;
-  }
-  __syncthreads();
-  stage_to_run<K>(st, v);
-  __syncthreads();
-}
-
-// The same in two halves, so that several loads can be in flight together:
-// issue_loads puts window cells [0, W K) from base into tmp (lane layout,
-// cell threadIdx.x + k W in tmp[k]); stage_tmp moves them into the runs.
-template <int K, bool kAll>
-__device__ __forceinline__ void issue_loads(double (&tmp)[K], const double* __restrict__ base,
-                                            int count) {
-  const int W = blockDim.x;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int e = threadIdx.x + k * W;
-    tmp[k] = base[(kAll || e < count) ? e : 0];
-  }
-}
-template <int K, bool kAll>
-__device__ __forceinline__ void stage_tmp(double* st, const double (&tmp)[K], double (&v)[K],
-                                          int count) {
-  const int W = blockDim.x;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int e = threadIdx.x + k * W;
-    st[sidx<K>(e)] = (kAll || e < count) ? tmp[k] : 0.0;
-  }
-  __syncthreads();
-  stage_to_run<K>(st, v);
-  __syncthreads();
-}
-
-// Registers -> coalesced store of window cells [clo, chi) to base.
-template <int K>
-__device__ __forceinline__ void store_run_fast(double* st, const double (&v)[K],
-                                               double* __restrict__ base, int clo, int chi) {
-  const int W = blockDim.x;
-  run_to_stage<K>(st, v);
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int e = threadIdx.x + k * W;
-    if (e >= clo && e < chi) base[e] = st[sidx<K>(e)];
-  }
-  __syncthreads();
-}
-
-// Pi from the coarse run c (cells J0..J0+K/2-1 of this thread, cbase =
-// address of J0 in HBM): two coarse cells on each side from the neighbours,
-// from HBM at the window edges.  No boundary cases.
-template <int K>
-__device__ __forceinline__ void interp_fast(double (&u)[K], const double (&c)[K / 2],
-                                            const double* __restrict__ cbase, Xch& x) {
-  double l1, r0, l2, r1;
-  x.swap(c[0], c[K / 2 - 1], l1, r0);
-  x.swap(c[1], c[K / 2 - 2], l2, r1);
-  if (threadIdx.x == 0) { l2 = cbase[-2]; l1 = cbase[-1]; }
-  if (threadIdx.x == blockDim.x - 1) { r0 = cbase[K / 2]; r1 = cbase[K / 2 + 1]; }
-  double e[K / 2 + 4];
-  e[0] = l2;
-  e[1] = l1;
-#pragma unroll
-  for (int p = 0; p < K / 2; ++p) e[p + 2] = c[p];
-  e[K / 2 + 2] = r0;
-  e[K / 2 + 3] = r1;
-#pragma unroll
-  for (int p = 0; p < K / 2; ++p) {
-    u[2 * p] = interp_even(e[p], e[p + 1], e[p + 2], e[p + 3]);
-    u[2 * p + 1] = interp_odd(e[p + 1], e[p + 2], e[p + 3], e[p + 4]);
-  }
-}
-
-// Full weighting of a run (no boundary cases).
-template <int K>
-__device__ __forceinline__ void fw_fast(const double (&f)[K], double (&f1)[K / 2], Xch& x) {
-  double fl, fr;
-  x.swap(f[0], f[K - 1], fl, fr);
-#pragma unroll
-  for (int p = 0; p < K / 2; ++p) {
-    const double rm = (p == 0) ? fl : f[2 * p - 1];
-    const double rp = (p == K / 2 - 1) ? fr : f[2 * p + 2];
-    f1[p] = ((rm + rp) + 3.0 * (f[2 * p] + f[2 * p + 1])) * 0.125;
-  }
-}
-
-// fh = F h^2 / 2 for the fused interior update.
-template <int K>
-__device__ __forceinline__ void half_scaled(const double (&f)[K], double (&fh)[K], int64_t n) {
-  const double h2 = 1.0 / ((double)n * (double)n);
-#pragma unroll
-  for (int j = 0; j < K; ++j) fh[j] = (f[j] * h2) * 0.5;
-}
-
-// nu red-black sweeps updating every cell of the run.
-template <int K>
-__device__ __forceinline__ void rb_sweeps_fast(double (&u)[K], const double (&fh)[K], int nu,
-                                               Xch& x) {
-  for (int s = 0; s < nu; ++s) {
-    const double ll = x.from_left(u[K - 1]);
-#pragma unroll
-    for (int j = 0; j < K; j += 2) u[j] = __builtin_fma((j == 0 ? ll : u[j - 1]) + u[j + 1], 0.5, fh[j]);
-    const double rf = x.from_right(u[0]);
-#pragma unroll
-    for (int j = 1; j < K; j += 2) u[j] = __builtin_fma(u[j - 1] + (j == K - 1 ? rf : u[j + 1]), 0.5, fh[j]);
-  }
-}
-
-// nu red-black sweeps updating the run cells [jlo, jhi) only (interior of
-// the level; used on SR segments, whose extended patch ends inside threads).
-template <int K>
-__device__ __forceinline__ void rb_sweeps_masked(double (&u)[K], const double (&fh)[K], int nu,
-                                                 int jlo, int jhi, Xch& x) {
-  const bool all = (jlo == 0 && jhi == K);
-  for (int s = 0; s < nu; ++s) {
-    const double ll = x.from_left(u[K - 1]);
-    if (all) {
-#pragma unroll
-      for (int j = 0; j < K; j += 2) u[j] = __builtin_fma((j == 0 ? ll : u[j - 1]) + u[j + 1], 0.5, fh[j]);
-    } else {
-#pragma unroll
-      for (int j = 0; j < K; j += 2) {
-        const double v = __builtin_fma((j == 0 ? ll : u[j - 1]) + u[j + 1], 0.5, fh[j]);
-        if (j >= jlo && j < jhi) u[j] = v;
-      }
-    }
-    const double rf = x.from_right(u[0]);
-    if (all) {
-#pragma unroll
-      for (int j = 1; j < K; j += 2) u[j] = __builtin_fma(u[j - 1] + (j == K - 1 ? rf : u[j + 1]), 0.5, fh[j]);
-    } else {
-#pragma unroll
-      for (int j = 1; j < K; j += 2) {
-        const double v = __builtin_fma(u[j - 1] + (j == K - 1 ? rf : u[j + 1]), 0.5, fh[j]);
-        if (j >= jlo && j < jhi) u[j] = v;
-      }
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Stored levels: vertical down / up kernels

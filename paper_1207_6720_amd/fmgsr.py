@@ -14,6 +14,8 @@ LIB_PATH = os.path.join(_HERE, "libfmgsr.so")
 
 FMGSR_OK, FMGSR_EINVAL, FMGSR_ENOMEM, FMGSR_EDEVICE, FMGSR_ENOTSUP = 0, -1, -2, -3, -4
 TAU_MODES = {"split": 0, "literal": 1}
+OPS = {"poisson": 0, "cubic": 1, "linear": 2}
+PRECISIONS = {"fp64": 0, "fp32relax": 1}
 
 _lib = None
 
@@ -22,12 +24,20 @@ class Options(ctypes.Structure):
     """Mirror of ``fmgsr_options`` (include/fmgsr.h)."""
     _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
                 ("sr_levels", ctypes.c_int32), ("tau_mode", ctypes.c_int32),
-                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Operator(ctypes.Structure):
     """Mirror of ``fmgsr_operator``."""
     _fields_ = [("kind", ctypes.c_int32), ("kappa", ctypes.c_void_p)]
+
+
+class BatchShape(ctypes.Structure):
+    """Mirror of ``fmgsr_batch_shape``."""
+    _fields_ = [("threads", ctypes.c_int32), ("run", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("halo", ctypes.c_int32), ("lds_bytes", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64)]
 
 
 class KernelStat(ctypes.Structure):
@@ -67,16 +77,34 @@ def lib():
         L.fmgsr_profile_collect.restype = ctypes.c_int32
         L.fmgsr_version.argtypes = []
         L.fmgsr_version.restype = ctypes.c_char_p
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.fmgsr_batch_create.argtypes = [i32, vp, vp, vp, vp, i32, vp, i32,
+                                         ctypes.POINTER(Options), ctypes.POINTER(vp)]
+        L.fmgsr_batch_solve.argtypes = [vp, vp, vp, vp, vp]
+        L.fmgsr_batch_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.fmgsr_batch_autotune.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
+        L.fmgsr_batch_query.argtypes = [vp, ctypes.POINTER(BatchShape), vp]
+        L.fmgsr_batch_destroy.argtypes = [vp]
+        L.fmgsr_solve_batched.argtypes = [i32, vp, vp, vp, vp, i32, ctypes.POINTER(Operator), vp,
+                                          vp, ctypes.POINTER(Options), vp, vp]
+        L.fmgsr_adjoint.argtypes = [ctypes.POINTER(Operator), vp, ctypes.c_double,
+                                    ctypes.c_double, i64, i32, i64, i32, ctypes.POINTER(Options),
+                                    vp, vp, vp, vp, vp]
+        for name in ("fmgsr_batch_create", "fmgsr_batch_solve", "fmgsr_batch_adjoint",
+                     "fmgsr_batch_autotune", "fmgsr_batch_query", "fmgsr_batch_destroy",
+                     "fmgsr_solve_batched", "fmgsr_adjoint"):
+            getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
 
 
-def make_options(nu=(2, 1), sr_levels=1, tau="split", workspace=None):
+def make_options(nu=(2, 1), sr_levels=1, tau="split", workspace=None, precision="fp64"):
     o = Options()
     lib().fmgsr_default_options(ctypes.byref(o))
     o.nu1, o.nu2 = int(nu[0]), int(nu[1])
     o.sr_levels = int(sr_levels)
     o.tau_mode = TAU_MODES[tau]
+    o.precision = PRECISIONS[precision]
     if workspace is not None:
         o.workspace = workspace.data_ptr()
         o.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -95,16 +123,25 @@ def alloc_workspace(n, levels, device, **kw):
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
+def _check_vec(t, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous() and t.dim() == 1):
+        raise ValueError(f"{name} must be a contiguous 1-D float64 tensor on the GPU")
+
+
 def solve(f, g=(0.0, 0.0), levels=None, segments=1, buffer=0, nu=(2, 1), sr_levels=1,
-          tau="split", out=None, workspace=None, stream=None):
-    """One FMG-FAS-SR iteration for -u'' = f on [0,1] (see include/fmgsr.h).
+          tau="split", out=None, workspace=None, stream=None, op="poisson", kappa=None):
+    """One FMG-FAS-SR iteration for -u'' (+ reaction) = f on [0,1] (see
+    include/fmgsr.h).
 
     f: contiguous float64 tensor on the GPU.  Returns u (same shape).  The
-    call is asynchronous on ``stream`` (default: torch's current stream).
+    call is asynchronous on ``stream`` (default: torch's current stream);
+    the reaction operators (``op`` = "cubic" or "linear" with ``kappa``) run
+    synchronously as a batch of one.
     """
-    if not (isinstance(f, torch.Tensor) and f.is_cuda and f.dtype == torch.float64
-            and f.is_contiguous() and f.dim() == 1):
-        raise ValueError("f must be a contiguous 1-D float64 tensor on the GPU")
+    _check_vec(f, "f")
+    if kappa is not None:
+        _check_vec(kappa, "kappa")
     n = f.numel()
     if levels is None:
         levels = n.bit_length()  # n a power of two -> N0 = 1
@@ -116,13 +153,121 @@ def solve(f, g=(0.0, 0.0), levels=None, segments=1, buffer=0, nu=(2, 1), sr_leve
     if stream is None:
         stream = torch.cuda.current_stream(f.device)
     o = make_options(nu, sr_levels, tau, workspace)
-    op = Operator(0, None)
+    op = Operator(OPS[op], kappa.data_ptr() if kappa is not None else None)
     st = lib().fmgsr_solve(ctypes.byref(op), f.data_ptr(), float(g[0]), float(g[1]), n,
                            int(levels), int(segments), int(buffer), ctypes.byref(o),
                            out.data_ptr(), ctypes.c_void_p(stream.cuda_stream))
     if st != FMGSR_OK:
         raise FmgsrError(st, "fmgsr_solve")
     return out
+
+
+class Batch:
+    """A batched-solve plan (``fmgsr_batch_create``): many independent
+    problems of uneven size solved in one persistent launch.
+
+    sizes, levels: per-problem fine cells and grids; segments: per-problem SR
+    segment counts or None (library choice); g: [batch, 2] Dirichlet values
+    or None.  Packed device arrays put problem j at ``offsets[j]``."""
+
+    def __init__(self, sizes, levels, buffer=8, segments=None, g=None, op="cubic", nu=(2, 1),
+                 precision="fp64", offsets=None):
+        import numpy as np
+        self.batch = len(sizes)
+        self.sizes = np.ascontiguousarray(sizes, dtype=np.int64)
+        self.levels = np.ascontiguousarray(levels, dtype=np.int32)
+        self.offsets = (np.concatenate([[0], np.cumsum(self.sizes)[:-1]]).astype(np.int64)
+                        if offsets is None else np.ascontiguousarray(offsets, dtype=np.int64))
+        self.total = int((self.offsets + self.sizes).max())
+        self.op = op
+        seg = None if segments is None else np.ascontiguousarray(segments, dtype=np.int64)
+        gh = None if g is None else np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
+        o = make_options(nu, 1, "split", None, precision)
+        h = ctypes.c_void_p()
+        ptr = lambda a: None if a is None else a.ctypes.data
+        st = lib().fmgsr_batch_create(self.batch, ptr(self.sizes), ptr(self.offsets),
+                                      ptr(self.levels), ptr(seg), int(buffer), ptr(gh), OPS[op],
+                                      ctypes.byref(o), ctypes.byref(h))
+        if st != FMGSR_OK:
+            raise FmgsrError(st, "fmgsr_batch_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.fmgsr_batch_destroy(h)
+            self._h = None
+
+    def _stream(self, stream, dev):
+        return (stream or torch.cuda.current_stream(dev)).cuda_stream
+
+    def solve(self, f, kappa=None, out=None, stream=None):
+        _check_vec(f, "f")
+        if out is None:
+            out = torch.empty_like(f)
+        st = lib().fmgsr_batch_solve(self._h, f.data_ptr(),
+                                     kappa.data_ptr() if kappa is not None else None,
+                                     out.data_ptr(), self._stream(stream, f.device))
+        if st != FMGSR_OK:
+            raise FmgsrError(st, "fmgsr_batch_solve")
+        return out
+
+    def adjoint(self, kappa, u_fwd, dJdu, grad_f=None, grad_kappa=None, stream=None):
+        """(grad_f, grad_kappa) of J with dJ/du = dJdu (fmgsr_batch_adjoint)."""
+        if grad_f is None:
+            grad_f = torch.empty_like(dJdu)
+        if grad_kappa is None:
+            grad_kappa = torch.empty_like(dJdu)
+        st = lib().fmgsr_batch_adjoint(self._h, kappa.data_ptr(), u_fwd.data_ptr(),
+                                       dJdu.data_ptr(), grad_f.data_ptr(), grad_kappa.data_ptr(),
+                                       self._stream(stream, dJdu.device))
+        if st != FMGSR_OK:
+            raise FmgsrError(st, "fmgsr_batch_adjoint")
+        return grad_f, grad_kappa
+
+    def autotune(self, f, kappa=None, scratch=None, stream=None):
+        if scratch is None:
+            scratch = torch.empty_like(f)
+        ms = ctypes.c_double(0.0)
+        st = lib().fmgsr_batch_autotune(self._h, f.data_ptr(),
+                                        kappa.data_ptr() if kappa is not None else None,
+                                        scratch.data_ptr(), self._stream(stream, f.device),
+                                        ctypes.byref(ms))
+        if st != FMGSR_OK:
+            raise FmgsrError(st, "fmgsr_batch_autotune")
+        return ms.value
+
+    def query(self):
+        import numpy as np
+        sh = BatchShape()
+        segs = np.zeros(self.batch, dtype=np.int64)
+        st = lib().fmgsr_batch_query(self._h, ctypes.byref(sh), segs.ctypes.data)
+        if st != FMGSR_OK:
+            raise FmgsrError(st, "fmgsr_batch_query")
+        return {"threads": sh.threads, "run": sh.run, "grid": sh.grid, "halo": sh.halo,
+                "lds_bytes": sh.lds_bytes, "workspace_bytes": sh.workspace_bytes,
+                "segments": segs}
+
+
+def adjoint(f, kappa, dJdu, g=(0.0, 0.0), levels=None, segments=0, buffer=8, nu=(2, 1),
+            u_fwd=None, precision="fp64", stream=None):
+    """(grad_f, grad_kappa) for one cubic problem (fmgsr_adjoint; synchronous)."""
+    for t, nm in ((f, "f"), (kappa, "kappa"), (dJdu, "dJdu")):
+        _check_vec(t, nm)
+    n = f.numel()
+    if levels is None:
+        levels = n.bit_length()
+    gf, gk = torch.empty_like(f), torch.empty_like(f)
+    o = make_options(nu, 1, "split", None, precision)
+    op = Operator(OPS["cubic"], kappa.data_ptr())
+    s = (stream or torch.cuda.current_stream(f.device)).cuda_stream
+    st = lib().fmgsr_adjoint(ctypes.byref(op), f.data_ptr(), float(g[0]), float(g[1]), n,
+                             int(levels), int(segments), int(buffer), ctypes.byref(o),
+                             u_fwd.data_ptr() if u_fwd is not None else None, dJdu.data_ptr(),
+                             gf.data_ptr(), gk.data_ptr(), s)
+    if st != FMGSR_OK:
+        raise FmgsrError(st, "fmgsr_adjoint")
+    return gf, gk
 
 
 def profile_enable(kernel_filter=None):

@@ -57,10 +57,48 @@ def test_invalid_arguments_rejected_on_host(args, kw):
 
 def test_unsupported_requests():
     assert _solve_raw(1024, 11, 4, 4, sr_levels=2) == F.FMGSR_ENOTSUP
-    op = F.Operator(1, None)
+    assert _solve_raw(1024, 11, 4, 4, precision="fp32relax") == F.FMGSR_ENOTSUP
     o = F.make_options()
-    assert F.lib().fmgsr_solve(ctypes.byref(op), None, 0.0, 0.0, 1024, 11, 4, 4, ctypes.byref(o),
-                               None, None) == F.FMGSR_ENOTSUP
+    for kind, expect in ((1, F.FMGSR_EINVAL), (2, F.FMGSR_EINVAL), (7, F.FMGSR_EINVAL)):
+        op = F.Operator(kind, None)  # reaction kinds need a device kappa
+        assert F.lib().fmgsr_solve(ctypes.byref(op), None, 0.0, 0.0, 1024, 11, 4, 4,
+                                   ctypes.byref(o), None, None) == expect
+
+
+def _create(sizes, levels, segs=None, buffer=8, op=1, **kw):
+    import numpy as np
+    n = np.asarray(sizes, dtype=np.int64)
+    L = np.asarray(levels, dtype=np.int32)
+    s = None if segs is None else np.asarray(segs, dtype=np.int64)
+    o = F.make_options(**kw)
+    h = ctypes.c_void_p()
+    st = F.lib().fmgsr_batch_create(len(n), n.ctypes.data, None, L.ctypes.data,
+                                    None if s is None else s.ctypes.data, buffer, None, op,
+                                    ctypes.byref(o), ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("sizes,levels,segs,buffer,kw", [
+    ([1000], [5], None, 8, {}),             # n not divisible by 2^(levels-1)
+    ([512 * 8], [4], None, 8, {}),          # coarsest grid of 512 cells (> 256)
+    ([4096], [0], None, 8, {}),             # no levels
+    ([4096], [13], [3], 8, {}),             # segments do not divide n
+    ([4096], [13], [4096], 8, {}),          # odd segment core
+    ([4096], [13], None, 65, {}),           # buffer too wide
+    ([4096], [13], None, -1, {}),           # negative buffer
+    ([4096], [13], None, 8, {"nu": (17, 1)}),
+    ([0], [1], None, 8, {}),                # empty problem
+])
+def test_batch_create_rejects_invalid_problems(sizes, levels, segs, buffer, kw):
+    st, h = _create(sizes, levels, segs, buffer, **kw)
+    assert st == F.FMGSR_EINVAL and not h.value
+
+
+def test_batch_create_unsupported_options():
+    assert _create([4096], [13], tau="literal")[0] == F.FMGSR_ENOTSUP
+    assert _create([4096], [13], sr_levels=0)[0] == F.FMGSR_ENOTSUP
+    assert F.lib().fmgsr_batch_solve(None, None, None, None, None) == F.FMGSR_EINVAL
+    assert F.lib().fmgsr_batch_destroy(None) == F.FMGSR_EINVAL
 
 
 def test_workspace_sizes():
