@@ -5,7 +5,7 @@ A step is one full solve: forcing hierarchy, FMG cycles on every level, the
 SR down and up passes over the finest level, result streamed to u_out.  All
 inputs are resident in HBM before the timed region.  Prints ONE JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload c5|c2|c1] [--gpus 1]
+  python bench.py [--steps K] [--warmup W] [--workload c5|c2|c1|c3|c4] [--gpus 1]
 
 Default workload: N = 2^28 fine cells, 29 levels, 2^16 segments of 4096
 cells + 8 buffer cells, V(2,1) red-black Gauss-Seidel, 32-mode seeded
@@ -14,6 +14,12 @@ back-to-back solves (K = 10 by default).  The dominant kernel (largest share
 of a profiled solve) is additionally bracketed by events inside the timed
 region to report its achieved algorithmic bandwidth against the 8 TB/s HBM
 peak.  The CPU baseline times the FP64 oracle on a bounded sample.
+
+Reaction workloads (batched solver, one persistent launch per step):
+  c3  4096 problems -u'' + kappa u^3 = f of 2^12..2^18 cells (--precision
+      fp64 | fp32relax); a step is one FMG-FAS-SR iteration of every problem.
+  c4  64 problems of 2^20 cells; a step is the forward iteration plus the
+      adjoint iteration (gradients w.r.t. f and kappa of h sum (u - u_t)^2).
 """
 import argparse
 import json
@@ -67,11 +73,15 @@ def traffic_for(kernel, kernel_source_hash):
 
 
 def kernel_source_hash():
+    """sha256 over every HIP source and header of the library."""
     import hashlib
     h = hashlib.sha256()
-    for p in ("paper_1207_6720_amd/csrc/fmgsr_kernels.hpp", "paper_1207_6720_amd/csrc/fmgsr.hip"):
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_1207_6720_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
     return h.hexdigest()
 
 
@@ -103,7 +113,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c5"])
+    ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c5", "c3", "c4"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32relax"])
     ap.add_argument("--tau", default="split", choices=["split", "literal"])
     ap.add_argument("--sr-levels", type=int, default=1, choices=[0, 1])
     ap.add_argument("--cpu-log2n", type=int, default=24)
@@ -127,6 +138,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.workload in ("c3", "c4"):
+        return run_batched(args, dev)
     wl = W.WORKLOADS[args.workload]
     n = wl.n
     k, c = W.modes(wl.law, wl.n_modes, 0)
@@ -222,6 +235,148 @@ def main():
         "kernels": {kname: {"launches": v["launches"], "ms": round(v["total_ms"], 4),
                             "GBps": round(v["algo_bytes"] / max(v["total_ms"], 1e-9) / 1e6, 1)}
                     for kname, v in sorted(prof_all.items(), key=lambda kv: -kv[1]["total_ms"])},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def oracle_sample(rb, f_host, k_host, segs, budget_unknowns):
+    """Indices of a bounded oracle sample: problems in batch order until the
+    sample holds about budget_unknowns cells."""
+    idx, tot = [], 0
+    for j in range(rb.batch):
+        if tot >= budget_unknowns:
+            break
+        idx.append(j)
+        tot += rb.sizes[j]
+    return idx, tot
+
+
+def run_batched(args, dev):
+    import torch
+    import oracle
+    from paper_1207_6720_amd import fmgsr, workloads as W
+    rb = W.reaction_batch(args.workload)
+    adjoint = args.workload == "c4"
+    log(f"{fmgsr.version()} workload {rb.name}: {rb.description}")
+    f, k, ue, ut = W.reaction_packed_torch(rb, dev)
+    u = torch.empty_like(f)
+    gf, gk, dJ = None, None, None
+    plan = fmgsr.Batch(rb.sizes, rb.levels, buffer=rb.buffer, op="cubic",
+                       precision=args.precision)
+    stream = torch.cuda.current_stream(dev)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 2^27 doubles copied")
+    if adjoint:
+        hvec = torch.cat([torch.full((n,), 1.0 / n, dtype=torch.float64, device=dev)
+                          for n in rb.sizes])
+        gf, gk, dJ = torch.empty_like(f), torch.empty_like(f), torch.empty_like(f)
+
+    def step():
+        plan.solve(f, k, out=u, stream=stream)
+        if adjoint:
+            torch.sub(u, ut, out=dJ)
+            dJ.mul_(hvec).mul_(2.0)
+            plan.adjoint(k, u, dJ, gf, gk, stream=stream)
+
+    torch.cuda.synchronize()
+    mem_inputs = torch.cuda.memory_allocated(dev)
+    fmgsr.profile_enable(None)
+    step()
+    torch.cuda.synchronize()
+    prof_all = fmgsr.profile_collect()
+    for _ in range(max(args.warmup - 1, 0)):
+        step()
+    torch.cuda.synchronize()
+    dominant = max(prof_all, key=lambda kname: prof_all[kname]["total_ms"])
+    log(f"warm-up done; dominant kernel {dominant}")
+    fmgsr.profile_enable(dominant)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    dom = fmgsr.profile_collect()[dominant]
+    ms = ev0.elapsed_time(ev1) / args.steps
+    log(f"timed {args.steps} steps: {ms:.3f} ms/step")
+    q = plan.query()
+    segs = q["segments"]
+
+    # accuracy on a sample of problems: discrete solution by Newton (oracle)
+    acc = {"alg_over_disc_max": 0.0, "vs_fp64_oracle_max": 0.0, "problems": []}
+    for j in sorted({0, rb.batch // 2, rb.batch - 1}):
+        o, n = int(rb.offsets[j]), int(rb.sizes[j])
+        fj, kj, uj, ej = (t[o:o + n].cpu().numpy() for t in (f, k, u, ue))
+        ustar, _ = oracle.rx_newton("cubic", kj, fj)
+        ref = oracle.rx_fmgsr_solve("cubic", fj, kj, levels=rb.levels[j], segments=int(segs[j]),
+                                    buffer=rb.buffer)
+        nrm = np.linalg.norm
+        alg, disc = nrm(uj - ustar) / nrm(ustar), nrm(ustar - ej) / nrm(ej)
+        par = nrm(uj - ref) / nrm(ref)
+        acc["problems"].append({"j": j, "n": n, "alg_rel": alg, "disc_rel": disc, "vs_oracle": par})
+        acc["alg_over_disc_max"] = max(acc["alg_over_disc_max"], alg / disc)
+        acc["vs_fp64_oracle_max"] = max(acc["vs_fp64_oracle_max"], par)
+
+    dom_launch_ms = dom["total_ms"] / dom["launches"]
+    dom_bytes = dom["algo_bytes"] / dom["launches"]
+    achieved = dom_bytes / (dom_launch_ms * 1e-3) / 1e9
+    traffic = traffic_for(dominant, kernel_source_hash())
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dominant, "algo_bytes_per_launch": dom_bytes,
+                "avg_launch_ms": round(dom_launch_ms, 4), "launches": dom["launches"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        # bounded sample: problems in batch order up to ~2^22 cells (c3), or
+        # one problem (c4), forward (+ adjoint) by the oracle, single thread
+        budget = (1 << 22) if not adjoint else rb.sizes[0]
+        idx, tot = oracle_sample(rb, None, None, segs, budget)
+        t0 = time.perf_counter()
+        for j in idx:
+            o, n = int(rb.offsets[j]), int(rb.sizes[j])
+            fj, kj = f[o:o + n].cpu().numpy(), k[o:o + n].cpu().numpy()
+            uj = oracle.rx_fmgsr_solve("cubic", fj, kj, levels=rb.levels[j],
+                                       segments=int(segs[j]), buffer=rb.buffer)
+            if adjoint:
+                utj = ut[o:o + n].cpu().numpy()
+                oracle.rx_fmgsr_adjoint(kj, uj, 2.0 / n * (uj - utj), levels=rb.levels[j],
+                                        segments=int(segs[j]), buffer=rb.buffer)
+        t = time.perf_counter() - t0
+        cpu = {"value": tot / t, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+               "sample": (f"{len(idx)} problem(s) of the {rb.name} batch ({tot} cells), "
+                          f"{'forward + adjoint' if adjoint else 'one FMG-FAS-SR iteration'} "
+                          f"by the single-threaded C oracle ({t:.2f} s)")}
+        log(f"oracle sample: {cpu['sample']}")
+
+    out = {
+        "metric": METRIC, "value": rb.total / (ms * 1e-3), "unit": "unknowns/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32relax", "data": "synthetic",
+        "config": {"workload": f"{rb.name}: {rb.description}"
+                               + (", forward + adjoint per step" if adjoint else ""),
+                   "batch": rb.batch, "total_unknowns": rb.total, "buffer": rb.buffer,
+                   "nu": [2, 1], "smoother": "red-black nonlinear GS", "precision": args.precision,
+                   "seed": rb.seed, "threads": q["threads"], "run": q["run"], "grid": q["grid"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "solve_model": {"algo_bytes_per_step": sum(v["algo_bytes"] for v in prof_all.values()),
+                        "algo_bytes_per_unknown": round(sum(v["algo_bytes"] for v in prof_all.values()) / rb.total, 2)},
+        "accuracy": acc,
+        "memory": {"inputs_and_workspace_bytes": mem_inputs,
+                   "workspace_bytes": q["workspace_bytes"],
+                   "peak_allocated_bytes": torch.cuda.max_memory_allocated(dev)},
+        "kernels": {kname: {"launches": v["launches"], "ms": round(v["total_ms"], 4),
+                            "GBps": round(v["algo_bytes"] / max(v["total_ms"], 1e-9) / 1e6, 1)}
+                    for kname, v in prof_all.items()},
     }
     print(json.dumps(out), flush=True)
 

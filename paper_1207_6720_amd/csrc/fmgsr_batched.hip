@@ -768,7 +768,8 @@ struct fmgsr_batch_s {
   int32_t* d_queue = nullptr;
   double* d_ws = nullptr;
   int64_t ws_doubles = 0;
-  double algo_bytes = 0.0;        // algorithmic bytes of one solve (profiling)
+  double algo_bytes = 0.0;          // algorithmic bytes of one solve (profiling)
+  double algo_bytes_adjoint = 0.0;  // ... of one adjoint solve
 };
 
 namespace fmgsr {
@@ -778,6 +779,40 @@ namespace {
 constexpr int kRunCells = 8;
 
 int64_t pad_of(int buffer) { return (buffer + 2) & ~1; }
+
+// Algorithmic bytes of one problem's FMG-FAS-SR iteration as the kernel
+// schedules it: every array a visit reads counted once per visit, every
+// array it writes once (8 bytes per cell).  `reaction`: coefficient arrays
+// and coarse right-hand sides exist; `adjoint`: the fine coefficient is
+// formed from kappa and u_fwd and grad_kappa is written too.
+double model_bytes(int64_t n, int64_t n0, int M, bool reaction, bool adjoint) {
+  const double r = reaction ? 1.0 : 0.0;
+  const double fine_coef = reaction ? (adjoint ? 2.0 : 1.0) : 0.0;  // kappa (+ u_fwd)
+  auto nl = [&](int l) { return (double)(n0 << l); };
+  double b = 0.0;
+  if (M == 0) return 8.0 * (double)n * (2.0 + fine_coef + (adjoint ? 1.0 : 0.0));
+  // forcing: level l from level l+1
+  for (int l = M - 1; l >= 0; --l) {
+    const double nf = nl(l + 1);
+    b += 8.0 * nf * (1.0 + (l + 1 == M ? fine_coef : r)) + 8.0 * nl(l) * (1.0 + r);
+  }
+  auto down = [&](int l, int src) {  // src: 0 interp, 1 restrict, 2 direct
+    const double m = nl(l);
+    const double sb = src == 0 ? 0.5 * m : (src == 1 ? 2.0 * m : m);
+    return 8.0 * (sb + m * (1.0 + r) + m + 0.5 * m * r);
+  };
+  auto up = [&](int l) { const double m = nl(l); return 8.0 * (m + 0.5 * m + m * (1.0 + r) + m); };
+  for (int t = 1; t < M; ++t) {
+    for (int l = t; l >= 1; --l) b += down(l, l == t ? 0 : 1);
+    for (int l = 1; l <= t; ++l) b += up(l);
+  }
+  const double N = (double)n;
+  b += 8.0 * (0.5 * N + N * (1.0 + fine_coef) + 0.5 * N + 0.5 * N * r);  // SR down
+  for (int l = M - 1; l >= 1; --l) b += down(l, l == M - 1 ? 2 : 1);
+  for (int l = 1; l <= M - 1; ++l) b += up(l);
+  b += 8.0 * (0.5 * N + N * (1.0 + fine_coef) + N + (adjoint ? N : 0.0));  // SR up
+  return b;
+}
 
 // Largest segment core n0 2^k (even, dividing n) whose extended patch fits a
 // window of W cells; `halve` > 0 halves it that many times (autotuner).
@@ -858,11 +893,7 @@ fmgsr_status build_plan(fmgsr_batch_s* b, int T, int halve) {
     }
     p.ws = ws;
     ws += std::max<int64_t>(slab_doubles(p.n0, p.M), lvl_size(p.n0, 0));
-    // algorithmic bytes: fine level f, kappa read twice (SR down/up) and u
-    // written once; stored levels as the visits read and write them
-    const double kap = (b->op == kOpPoisson) ? 0.0 : 1.0;
-    bytes += (double)p.n * 8.0 * (2.0 * (1.0 + kap) + 1.0);
-    if (p.M >= 1) bytes += (double)p.n * 8.0 * 6.0 * (1.0 + kap);  // about 6 n of level traffic
+    bytes += model_bytes(p.n, p.n0, p.M, b->op != kOpPoisson, false);
   }
   if (b->auto_segments)
     for (int j = 0; j < b->batch; ++j) b->segs[j] = pr[j].M >= 1 ? pr[j].n / pr[j].seg : 1;
@@ -886,6 +917,9 @@ fmgsr_status build_plan(fmgsr_batch_s* b, int T, int halve) {
   per_cu = std::max(per_cu, 1);
   b->grid = (int)std::min<int64_t>(b->batch, (int64_t)per_cu * cus);
   b->algo_bytes = bytes;
+  double adj = 0.0;
+  for (const Prob& p : pr) adj += model_bytes(p.n, p.n0, p.M, true, true);
+  b->algo_bytes_adjoint = adj;
 
   if (!b->d_probs) {
     if (hipMalloc((void**)&b->d_probs, sizeof(Prob) * b->batch) != hipSuccess ||
@@ -939,7 +973,8 @@ fmgsr_status execute(fmgsr_batch_s* b, int op, bool adjoint, const double* f, co
       return FMGSR_EDEVICE;
     }
   }
-  ProfScope ps(adjoint ? "k_batched_adjoint" : "k_batched", b->algo_bytes, s);
+  ProfScope ps(adjoint ? "k_batched_adjoint" : "k_batched",
+               adjoint ? b->algo_bytes_adjoint : b->algo_bytes, s);
   hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, s, b->d_queue);
   if (hipGetLastError() != hipSuccess) return FMGSR_EDEVICE;
   if (launch(a, op, b->prec, b->grid, b->T, b->lds, s) != hipSuccess) return FMGSR_EDEVICE;

@@ -270,6 +270,28 @@ def adjoint(f, kappa, dJdu, g=(0.0, 0.0), levels=None, segments=0, buffer=8, nu=
     return gf, gk
 
 
+class CubicSolve(torch.autograd.Function):
+    """u = FMG-FAS-SR solution of -u'' + kappa u^3 = f for every problem of a
+    batch plan, differentiable in f and kappa: the backward pass runs the
+    library's adjoint (fmgsr_batch_adjoint) on the saved u, i.e. the gradient
+    of the discrete solution map, with lambda from one FMG-SR iteration.
+
+        u = CubicSolve.apply(f, kappa, plan)"""
+
+    @staticmethod
+    def forward(ctx, f, kappa, plan):
+        u = plan.solve(f.detach(), kappa.detach())
+        ctx.save_for_backward(kappa, u)
+        ctx.plan = plan
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        kappa, u = ctx.saved_tensors
+        gf, gk = ctx.plan.adjoint(kappa, u, grad_u.contiguous())
+        return gf, gk, None
+
+
 def profile_enable(kernel_filter=None):
     """Bracket every library kernel launch (matching ``kernel_filter``) with
     HIP events on its stream until ``profile_collect``."""

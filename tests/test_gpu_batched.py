@@ -254,3 +254,84 @@ def test_c3_full_size_sampled_parity(dev):
         e = rel(uj, ref)
         print(f"c3 problem {j}: n={n} rel={e:.2e}", flush=True)
         assert e <= TOL
+
+
+def test_autograd_and_central_differences(dev):
+    """Gradients of J = h sum (u - u_t)^2 through torch.autograd (the library
+    adjoint) against central differences of the exact discrete solution map
+    (oracle Newton solves), eps = 1e-6 relative to each field, 32 random
+    directions per field.  The grids are small on purpose: a Newton solve is
+    exact only to about eps_mach times the condition number (~ 0.4 n^2), and
+    the differences must stay well above that floor (at n = 2^20 it exceeds
+    1e-6 itself)."""
+    n0, L = 32, 4
+    n = n0 << L
+    rb = W.ReactionBatch("fd", (n, n), (L + 1, L + 1), 8, 11)
+    f, k, _, ut = packed(rb, dev)
+    plan = fmgsr.Batch(rb.sizes, rb.levels, buffer=8, op="cubic")
+    fr = f.clone().requires_grad_(True)
+    kr = k.clone().requires_grad_(True)
+    u = fmgsr.CubicSolve.apply(fr, kr, plan)
+    h = 1.0 / n
+    loss = h * ((u - ut) ** 2).sum()
+    loss.backward()
+    gf_auto, gk_auto = fr.grad.detach(), kr.grad.detach()
+    # the library adjoint on the same u, directly
+    gf_dir, gk_dir = plan.adjoint(k, u.detach(), (2.0 * h * (u - ut)).detach())
+    torch.cuda.synchronize()
+    assert torch.equal(gf_auto, gf_dir) and torch.equal(gk_auto, gk_dir)
+    # FD on the exact discrete map, with the adjoint evaluated at the
+    # converged discrete solution
+    rng = np.random.default_rng(17)
+    eps = 1e-6
+    for j in range(rb.batch):
+        o = int(rb.offsets[j])
+        fj, kj, utj = (t[o:o + n].cpu().numpy() for t in (f, k, ut))
+        ustar, _ = oracle.rx_newton("cubic", kj, fj)
+        us_d = torch.from_numpy(ustar).to(dev)
+        one = fmgsr.Batch((n,), (L + 1,), buffer=8, op="cubic")
+        gfj, gkj = one.adjoint(k[o:o + n].contiguous(), us_d,
+                               torch.from_numpy(2.0 * h * (ustar - utj)).to(dev))
+        gfj, gkj = gfj.cpu().numpy(), gkj.cpu().numpy()
+
+        def J(ff, kk):
+            us, _ = oracle.rx_newton("cubic", kk, ff)
+            return h * np.sum((us - utj) ** 2)
+        fd_f, ad_f, fd_k, ad_k = [], [], [], []
+        for _ in range(32):
+            df = rng.normal(size=n) * np.abs(fj).max()
+            dk = rng.normal(size=n) * np.abs(kj).max()
+            fd_f.append((J(fj + eps * df, kj) - J(fj - eps * df, kj)) / (2 * eps))
+            fd_k.append((J(fj, kj + eps * dk) - J(fj, kj - eps * dk)) / (2 * eps))
+            ad_f.append(gfj @ df)
+            ad_k.append(gkj @ dk)
+        # agreement of the 32 directional derivatives as vectors (a single
+        # direction can make its derivative small by cancellation)
+        ef, ek = rel(np.array(ad_f), np.array(fd_f)), rel(np.array(ad_k), np.array(fd_k))
+        print(f"problem {j}: FD rel f {ef:.2e} kappa {ek:.2e}", flush=True)
+        assert ef <= 1e-4 and ek <= 1e-4
+
+
+def test_c4_full_size_sampled_parity(dev):
+    """64 problems of 2^20 cells: forward and adjoint in one launch each,
+    checked against the oracle on two problems."""
+    rb = W.reaction_batch("c4", seed=0)
+    f, k, _, ut = packed(rb, dev)
+    plan = fmgsr.Batch(rb.sizes, rb.levels, buffer=rb.buffer, op="cubic")
+    u = plan.solve(f, k)
+    n = rb.sizes[0]
+    dJ = 2.0 / n * (u - ut)
+    gf, gk = plan.adjoint(k, u, dJ)
+    torch.cuda.synchronize()
+    print("c4: GPU forward + adjoint done", flush=True)
+    segs = plan.query()["segments"]
+    for j in (0, 63):
+        o = int(rb.offsets[j])
+        fj, kj, uj, dj, gfj, gkj = (t[o:o + n].cpu().numpy() for t in (f, k, u, dJ, gf, gk))
+        ref = oracle.rx_fmgsr_solve("cubic", fj, kj, levels=rb.levels[j], segments=int(segs[j]),
+                                    buffer=rb.buffer)
+        rf, rk = oracle.rx_fmgsr_adjoint(kj, uj, dj, levels=rb.levels[j], segments=int(segs[j]),
+                                         buffer=rb.buffer)
+        print(f"c4 problem {j}: u {rel(uj, ref):.2e} grad_f {rel(gfj, rf):.2e} "
+              f"grad_kappa {rel(gkj, rk):.2e}", flush=True)
+        assert rel(uj, ref) <= TOL and rel(gfj, rf) <= TOL and rel(gkj, rk) <= TOL
