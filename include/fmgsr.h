@@ -153,7 +153,11 @@ fmgsr_status fmgsr_solve(const fmgsr_operator *op, const double *f, double g_lef
  * level cut into segments of core s_j = n_j / segments_j with `buffer` cells
  * on each side (0..64).  A plan holds the descriptors, the launch shape and
  * the workspace (every problem's stored levels, about 5.5 n_j doubles), so
- * that executing it needs no allocation and no host-to-device copy.
+ * that executing it needs no allocation and no host-to-device copy.  When the
+ * batch has fewer problems than resident workgroups, several workgroups
+ * share each problem; they must all be resident at once, so such a plan
+ * expects the device not to be shared with other long kernels (a bounded
+ * wait turns a stall into the `stalled` flag instead of a hang).
  * ------------------------------------------------------------------------ */
 typedef struct fmgsr_batch_s *fmgsr_batch;
 
@@ -164,6 +168,13 @@ typedef struct {
   int32_t halo;          /* stored-level tile halo (cells)                    */
   int64_t lds_bytes;     /* LDS per workgroup                                 */
   int64_t workspace_bytes;
+  int32_t group;         /* workgroups per problem (> 1 when the batch has
+                            fewer problems than resident workgroups: they
+                            split every large level's tiles and segments and
+                            meet at a barrier between phases)                 */
+  int32_t stalled;       /* 1 if a group barrier ever timed out (the results
+                            of that execution are invalid); reading it
+                            synchronises the device                           */
 } fmgsr_batch_shape;
 
 /*

@@ -82,6 +82,9 @@ struct Args {
   int nu1, nu2, buffer, halo;
   int region;            // doubles of the LDS stage / coarse-solve region
   int adjoint;           // 1: homogeneous boundary values (adjoint solve)
+  int group;             // workgroups cooperating on one problem (G)
+  int32_t* bars;         // [2 batch] per-problem barrier (count, generation)
+  int32_t* status;       // set to 1 if a group barrier timed out
 };
 
 __host__ __device__ inline int64_t lvl_size(int64_t n0, int l) {
@@ -110,6 +113,9 @@ struct Ctx {
   double* gk;
   double *R, *A, *U, *V, *Q, *Uh;
   int64_t hier;  // doubles per hierarchy array
+  int member, G; // this workgroup's rank in the problem's group, group size
+  int32_t* bar;  // the problem's barrier (count, generation)
+  int32_t* status;
   __device__ int64_t nl(int l) const { return n0 << l; }
   __device__ int64_t off(int l) const { return lvl_off(n0, l); }
   // fine-level coefficient: kappa, or 3 kappa u_fwd^2 for the adjoint
@@ -134,6 +140,10 @@ __device__ __forceinline__ Ctx make_ctx(const Prob& p, const Args& a) {
   double* s = a.ws + p.ws;
   c.R = s; c.A = s + c.hier; c.U = s + 2 * c.hier; c.V = s + 3 * c.hier; c.Q = s + 4 * c.hier;
   c.Uh = s + 5 * c.hier;
+  c.G = a.group;
+  c.member = 0;
+  c.bar = nullptr;
+  c.status = a.status;
   return c;
 }
 
@@ -352,7 +362,8 @@ __device__ void down_visit(const Ctx& c, const Args& ar, int l, int src_kind, co
   double* Uo = c.U + c.off(l);
   double* Qo = (OP != kOpPoisson) ? c.Q + c.off(l - 1) : nullptr;
   const Tiling tl = tiling(n, K, ar.halo);
-  for (int64_t ti = 0; ti < tl.ntiles; ++ti) {
+  const int64_t first = (tl.ntiles == 1) ? 0 : c.member, stride = (tl.ntiles == 1) ? 1 : c.G;
+  for (int64_t ti = first; ti < tl.ntiles; ti += stride) {
     const int64_t clo = ti * tl.core, chi = min(clo + tl.core, n);
     const int64_t wlo = clo - tl.halo;
     const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
@@ -405,7 +416,8 @@ __device__ void up_visit(const Ctx& c, const Args& ar, int l, const double* F, d
   const double* Vc = c.V + c.off(l - 1);
   double* Vo = c.V + c.off(l);
   const Tiling tl = tiling(n, K, ar.halo);
-  for (int64_t ti = 0; ti < tl.ntiles; ++ti) {
+  const int64_t first = (tl.ntiles == 1) ? 0 : c.member, stride = (tl.ntiles == 1) ? 1 : c.G;
+  for (int64_t ti = first; ti < tl.ntiles; ti += stride) {
     const int64_t clo = ti * tl.core, chi = min(clo + tl.core, n);
     const int64_t wlo = clo - tl.halo;
     const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
@@ -458,7 +470,7 @@ __device__ void sr_down(const Ctx& c, const Args& ar, double* st, Xch& x) {
   const int wcount = (int)(s + 2 * pad);
   const double* Vc = c.V + c.off(c.M - 1);
   double* Qo = (OP != kOpPoisson) ? c.Q + c.off(c.M - 1) : nullptr;
-  for (int64_t i = 0; i < S; ++i) {
+  for (int64_t i = c.member; i < S; i += c.G) {
     const int64_t wlo = i * s - pad;
     const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
     double u[K], Fr[K], a[K], cr[K / 2];
@@ -500,7 +512,7 @@ __device__ void sr_up(const Ctx& c, const Args& ar, double* st, Xch& x) {
   const int64_t pad = (ar.buffer + 2) & ~1;
   const int wcount = (int)(s + 2 * pad);
   const double* Vc = c.V + c.off(c.M - 1);
-  for (int64_t i = 0; i < S; ++i) {
+  for (int64_t i = c.member; i < S; i += c.G) {
     const int64_t wlo = i * s - pad;
     const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
     double u[K], Fr[K], a[K], cr[K / 2];
@@ -543,31 +555,90 @@ __device__ void sr_up(const Ctx& c, const Args& ar, double* st, Xch& x) {
   __syncthreads();
 }
 
-// Forcing hierarchy: R^l = I R^{l+1}, A^l = I^ A^{l+1}, l = M-1..0.
+// Forcing of level l: R^l = I R^{l+1}, A^l = I^ A^{l+1} (R^M = f, A^M = the
+// fine coefficient), cells J = first*T + tid, stepping by stride*T.
 template <int OP>
-__device__ void forcing(const Ctx& c) {
+__device__ void forcing_level(const Ctx& c, int l, int first, int stride) {
   const int T = blockDim.x;
-  for (int l = c.M - 1; l >= 0; --l) {
-    const int64_t nf = c.nl(l + 1), ncl = c.nl(l);
-    const bool top = (l + 1 == c.M);
-    const double* Ff = top ? c.f : c.R + c.off(l + 1);
-    const double* Af = c.A + c.off(l + 1);
-    double* Rc = c.R + c.off(l);
-    double* Ac = c.A + c.off(l);
-    for (int64_t J = threadIdx.x; J < ncl; J += T) {
-      const double f0 = Ff[2 * J], f1 = Ff[2 * J + 1];
-      const double rm = (2 * J - 1 >= 0) ? Ff[2 * J - 1] : -f0;
-      const double rp = (2 * J + 2 < nf) ? Ff[2 * J + 2] : -f1;
-      Rc[J] = ((rm + rp) + 3.0 * (f0 + f1)) * 0.125;
-      if constexpr (OP != kOpPoisson) {
-        const double a0 = top ? c.coef_fine(2 * J) : Af[2 * J];
-        const double a1 = top ? c.coef_fine(2 * J + 1) : Af[2 * J + 1];
-        Ac[J] = (a0 + a1) * 0.5;
+  const int64_t nf = c.nl(l + 1), ncl = c.nl(l);
+  const bool top = (l + 1 == c.M);
+  const double* Ff = top ? c.f : c.R + c.off(l + 1);
+  const double* Af = c.A + c.off(l + 1);
+  double* Rc = c.R + c.off(l);
+  double* Ac = c.A + c.off(l);
+  for (int64_t J = (int64_t)first * T + threadIdx.x; J < ncl; J += (int64_t)stride * T) {
+    const double f0 = Ff[2 * J], f1 = Ff[2 * J + 1];
+    const double rm = (2 * J - 1 >= 0) ? Ff[2 * J - 1] : -f0;
+    const double rp = (2 * J + 2 < nf) ? Ff[2 * J + 2] : -f1;
+    Rc[J] = ((rm + rp) + 3.0 * (f0 + f1)) * 0.125;
+    if constexpr (OP != kOpPoisson) {
+      const double a0 = top ? c.coef_fine(2 * J) : Af[2 * J];
+      const double a1 = top ? c.coef_fine(2 * J + 1) : Af[2 * J + 1];
+      Ac[J] = (a0 + a1) * 0.5;
+    }
+  }
+  __syncthreads();
+}
+
+// Barrier of the G workgroups solving one problem: arrive on the problem's
+// counter, the last arriver advances the generation.  Writes before the
+// barrier are released at agent scope and acquired after it.  The wait is
+// bounded; on expiry the status flag is set and false is returned (the
+// caller abandons the problem, so every wave still reaches its exit).
+__device__ bool group_sync(const Ctx& c) {
+  if (c.G == 1) {
+    __syncthreads();
+    return true;
+  }
+  // every wave waits for its own stores, so the release below covers the
+  // whole workgroup's writes
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    int32_t* cnt = c.bar;
+    int32_t* gen = c.bar + 1;
+    const int32_t g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const int32_t arrived = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    int good = 1;
+    if (arrived == c.G - 1) {
+      __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(gen, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      int64_t spins = 0;
+      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(4);
+        if (++spins > (int64_t)1 << 24) {
+          __hip_atomic_store(c.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          good = 0;
+          break;
+        }
       }
     }
-    __syncthreads();
+    __threadfence();
+    ok = good;
   }
+  __syncthreads();
+  const bool r = ok != 0;
+  __syncthreads();
+  return r;
 }
+
+// Phase sequencing for a group: a barrier separates phases, except between
+// two consecutive phases that member 0 runs alone.  Returns whether this
+// workgroup takes part in the phase; `alive` turns false after a barrier
+// timeout.
+struct Phases {
+  bool started = false, prev_solo = false, alive = true;
+  __device__ bool begin(const Ctx& c, bool solo) {
+    if (!alive) return false;
+    if (c.G > 1 && started && !(prev_solo && solo)) alive = group_sync(c);
+    started = true;
+    prev_solo = solo;
+    return alive && (!solo || c.member == 0);
+  }
+};
 
 __device__ __forceinline__ void wg_max2(double& a, double& b, double* red) {
   for (int o = 32; o > 0; o >>= 1) {
@@ -665,12 +736,16 @@ __device__ void coarse_visit(const Ctx& c, int src_kind, const double* src, cons
   __syncthreads();
 }
 
-// The whole FMG-FAS-SR iteration of one problem.
+// The whole FMG-FAS-SR iteration of one problem (by the group's member
+// c.member; levels of at most one window are run by member 0 alone).
 template <int K, int OP, int PREC>
 __device__ void solve_problem(const Ctx& c, const Args& ar, double* st, Xch& x, double* red) {
   const int M = c.M;
+  const int64_t W = (int64_t)blockDim.x * K;
+  Phases ph;
   if (M == 0) {
     // one level: the exact (Newton) solve on the fine grid
+    if (!ph.begin(c, true)) return;
     double* out = c.uo ? c.uo : c.U;
     coarse_visit<OP>(c, kZero, nullptr, c.f, nullptr, true, out, st, red);
     if (c.gk) {
@@ -682,15 +757,18 @@ __device__ void solve_problem(const Ctx& c, const Args& ar, double* st, Xch& x, 
     __syncthreads();
     return;
   }
-  forcing<OP>(c);
+  for (int l = M - 1; l >= 0; --l) {
+    const bool solo = c.nl(l) <= W;
+    if (ph.begin(c, solo)) forcing_level<OP>(c, l, solo ? 0 : c.member, solo ? 1 : c.G);
+  }
   const double* Fsrc = (OP == kOpPoisson) ? c.R : c.Q;   // rhs of inner levels
   // FMG start: level 0 from zero with the original rhs
-  coarse_visit<OP>(c, kZero, nullptr, c.R, c.A, false, c.V, st, red);
+  if (ph.begin(c, true)) coarse_visit<OP>(c, kZero, nullptr, c.R, c.A, false, c.V, st, red);
   for (int t = 1; t <= M; ++t) {
     const bool sr = (t == M);
     int top;
     if (sr) {
-      sr_down<K, OP, PREC>(c, ar, st, x);
+      if (ph.begin(c, false)) sr_down<K, OP, PREC>(c, ar, st, x);
       top = M - 1;
     } else {
       top = t;
@@ -702,7 +780,7 @@ __device__ void solve_problem(const Ctx& c, const Args& ar, double* st, Xch& x, 
       else if (l == top) { sk = kDirect; src = c.Uh; }
       else { sk = kRestrict; src = c.U + c.off(l + 1); }
       const double* F = (l == top && !sr) ? c.R + c.off(l) : Fsrc + c.off(l);
-      down_visit<K, OP, PREC>(c, ar, l, sk, src, F, st, x);
+      if (ph.begin(c, c.nl(l) <= W)) down_visit<K, OP, PREC>(c, ar, l, sk, src, F, st, x);
     }
     {
       int sk;
@@ -710,13 +788,13 @@ __device__ void solve_problem(const Ctx& c, const Args& ar, double* st, Xch& x, 
       if (top >= 1) { sk = kRestrict; src = c.U + c.off(1); }
       else { sk = kDirect; src = c.Uh; }   // M == 1: level 0 is the top
       const double* F = (top == 0 && !sr) ? c.R : Fsrc;
-      coarse_visit<OP>(c, sk, src, F, c.A, false, c.V, st, red);
+      if (ph.begin(c, true)) coarse_visit<OP>(c, sk, src, F, c.A, false, c.V, st, red);
     }
     for (int l = 1; l <= top; ++l) {
       const double* F = (l == top && !sr) ? c.R + c.off(l) : Fsrc + c.off(l);
-      up_visit<K, OP, PREC>(c, ar, l, F, st, x);
+      if (ph.begin(c, c.nl(l) <= W)) up_visit<K, OP, PREC>(c, ar, l, F, st, x);
     }
-    if (sr) sr_up<K, OP, PREC>(c, ar, st, x);
+    if (sr && ph.begin(c, false)) sr_up<K, OP, PREC>(c, ar, st, x);
   }
 }
 
@@ -728,18 +806,30 @@ __global__ __launch_bounds__(kMaxThreads) void k_batched(Args a) {
   Xch x{red + 32, 0};                                // 4 T doubles
   __shared__ int next;
   for (;;) {
+    // slot -> (queue position, member): the G members of a problem are
+    // consecutive slots, so all of them are taken by running workgroups
     if (threadIdx.x == 0) next = atomicAdd(a.queue, 1);
     __syncthreads();
-    const int p = next;
+    const int slot = next;
     __syncthreads();
+    const int p = slot / a.group;
     if (p >= a.batch) break;
-    const Prob pr = a.probs[a.order[p]];
-    const Ctx c = make_ctx(pr, a);
+    const int qp = a.order[p];
+    const Prob pr = a.probs[qp];
+    Ctx c = make_ctx(pr, a);
+    c.member = slot % a.group;
+    c.bar = a.bars + 2 * (int64_t)qp;
     solve_problem<K, OP, PREC>(c, a, st, x, red);
   }
 }
 
-__global__ void k_queue_reset(int32_t* q) { *q = 0; }
+// Zero the queue counter and the per-problem barriers (a kernel rather than
+// a memset, so that a captured graph replays it reliably).
+__global__ void k_queue_reset(int32_t* q, int32_t* bars, int64_t nbars) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *q = 0;
+  if (i < nbars) bars[i] = 0;
+}
 
 }  // namespace bt
 }  // namespace fmgsr
@@ -755,7 +845,7 @@ struct fmgsr_batch_s {
   int device = 0;
   int32_t batch = 0;
   int op = 0, prec = 0, nu1 = 2, nu2 = 1, buffer = 0, halo = 0;
-  int K = 8, T = 256, grid = 0;
+  int K = 8, T = 256, grid = 0, group = 1;
   int region = 0;                 // doubles of the LDS stage / coarse region
   size_t lds = 0;
   int n0max = 1;
@@ -765,7 +855,7 @@ struct fmgsr_batch_s {
   std::vector<int32_t> order;
   Prob* d_probs = nullptr;
   int32_t* d_order = nullptr;
-  int32_t* d_queue = nullptr;
+  int32_t* d_queue = nullptr;     // [0] queue, [1] status, [2..] barriers (2 per problem)
   double* d_ws = nullptr;
   int64_t ws_doubles = 0;
   double algo_bytes = 0.0;          // algorithmic bytes of one solve (profiling)
@@ -777,6 +867,7 @@ namespace bt {
 namespace {
 
 constexpr int kRunCells = 8;
+constexpr int kMaxGroup = 16;
 
 int64_t pad_of(int buffer) { return (buffer + 2) & ~1; }
 
@@ -915,7 +1006,10 @@ fmgsr_status build_plan(fmgsr_batch_s* b, int T, int halve) {
     return FMGSR_EDEVICE;
   }
   per_cu = std::max(per_cu, 1);
-  b->grid = (int)std::min<int64_t>(b->batch, (int64_t)per_cu * cus);
+  // fewer problems than resident workgroups: split each problem over a group
+  const int64_t cap = (int64_t)per_cu * cus;
+  b->group = (b->batch < cap) ? (int)std::min<int64_t>(kMaxGroup, cap / b->batch) : 1;
+  b->grid = (int)std::min<int64_t>((int64_t)b->batch * b->group, cap);
   b->algo_bytes = bytes;
   double adj = 0.0;
   for (const Prob& p : pr) adj += model_bytes(p.n, p.n0, p.M, true, true);
@@ -924,9 +1018,13 @@ fmgsr_status build_plan(fmgsr_batch_s* b, int T, int halve) {
   if (!b->d_probs) {
     if (hipMalloc((void**)&b->d_probs, sizeof(Prob) * b->batch) != hipSuccess ||
         hipMalloc((void**)&b->d_order, sizeof(int32_t) * b->batch) != hipSuccess ||
-        hipMalloc((void**)&b->d_queue, sizeof(int32_t)) != hipSuccess) {
+        hipMalloc((void**)&b->d_queue, sizeof(int32_t) * (2 + 2 * (size_t)b->batch)) != hipSuccess) {
       free_plan_device(b);
       return FMGSR_ENOMEM;
+    }
+    if (hipMemset(b->d_queue, 0, sizeof(int32_t) * (2 + 2 * (size_t)b->batch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return FMGSR_EDEVICE;
     }
   }
   if (ws > b->ws_doubles) {
@@ -966,6 +1064,9 @@ fmgsr_status execute(fmgsr_batch_s* b, int op, bool adjoint, const double* f, co
   a.halo = b->halo;
   a.region = b->region;
   a.adjoint = adjoint ? 1 : 0;
+  a.group = b->group;
+  a.status = b->d_queue + 1;
+  a.bars = b->d_queue + 2;
   if (op != b->op) {
     const void* kp = kernel_ptr(op, b->prec);
     if (hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds) != hipSuccess) {
@@ -975,7 +1076,9 @@ fmgsr_status execute(fmgsr_batch_s* b, int op, bool adjoint, const double* f, co
   }
   ProfScope ps(adjoint ? "k_batched_adjoint" : "k_batched",
                adjoint ? b->algo_bytes_adjoint : b->algo_bytes, s);
-  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, s, b->d_queue);
+  const int64_t nbars = 2 * (int64_t)b->batch;
+  hipLaunchKernelGGL(k_queue_reset, dim3((unsigned)((nbars + 255) / 256)), dim3(256), 0, s,
+                     b->d_queue, b->d_queue + 2, nbars);
   if (hipGetLastError() != hipSuccess) return FMGSR_EDEVICE;
   if (launch(a, op, b->prec, b->grid, b->T, b->lds, s) != hipSuccess) return FMGSR_EDEVICE;
   return FMGSR_OK;
@@ -1133,6 +1236,13 @@ fmgsr_status fmgsr_batch_query(fmgsr_batch b, fmgsr_batch_shape* shape, int64_t*
     shape->halo = b->halo;
     shape->lds_bytes = (int64_t)b->lds;
     shape->workspace_bytes = b->ws_doubles * (int64_t)sizeof(double);
+    shape->group = b->group;
+    int32_t stalled = 0;
+    if (hipMemcpy(&stalled, b->d_queue + 1, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) {
+      (void)hipGetLastError();
+      return FMGSR_EDEVICE;
+    }
+    shape->stalled = stalled;
   }
   if (segments_out)
     for (int j = 0; j < b->batch; ++j) segments_out[j] = b->segs[j];

@@ -37,7 +37,8 @@ class BatchShape(ctypes.Structure):
     """Mirror of ``fmgsr_batch_shape``."""
     _fields_ = [("threads", ctypes.c_int32), ("run", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("halo", ctypes.c_int32), ("lds_bytes", ctypes.c_int64),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("workspace_bytes", ctypes.c_int64), ("group", ctypes.c_int32),
+                ("stalled", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -246,7 +247,7 @@ class Batch:
             raise FmgsrError(st, "fmgsr_batch_query")
         return {"threads": sh.threads, "run": sh.run, "grid": sh.grid, "halo": sh.halo,
                 "lds_bytes": sh.lds_bytes, "workspace_bytes": sh.workspace_bytes,
-                "segments": segs}
+                "group": sh.group, "stalled": sh.stalled, "segments": segs}
 
 
 def adjoint(f, kappa, dJdu, g=(0.0, 0.0), levels=None, segments=0, buffer=8, nu=(2, 1),

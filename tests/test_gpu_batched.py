@@ -335,3 +335,27 @@ def test_c4_full_size_sampled_parity(dev):
         print(f"c4 problem {j}: u {rel(uj, ref):.2e} grad_f {rel(gfj, rf):.2e} "
               f"grad_kappa {rel(gkj, rk):.2e}", flush=True)
         assert rel(uj, ref) <= TOL and rel(gfj, rf) <= TOL and rel(gkj, rk) <= TOL
+
+
+def test_group_split_matches_single_workgroup_bitwise(dev):
+    """A problem solved alone (its levels split over a group of workgroups
+    meeting at barriers) equals the same problem inside a large batch (one
+    workgroup per problem) bit for bit, and neither run stalls."""
+    big = W.reaction_batch("small", seed=12, batch=600)
+    f, k, _, _ = packed(big, dev)
+    plan_big = fmgsr.Batch(big.sizes, big.levels, buffer=big.buffer, op="cubic")
+    u_big = plan_big.solve(f, k)
+    torch.cuda.synchronize()
+    qb = plan_big.query()
+    assert qb["group"] == 1
+    for j in (0, 17, 599):
+        o, n = int(big.offsets[j]), int(big.sizes[j])
+        one = fmgsr.Batch((n,), (big.levels[j],), buffer=big.buffer, op="cubic",
+                          segments=(int(qb["segments"][j]),))
+        u1 = one.solve(f[o:o + n].contiguous(), k[o:o + n].contiguous())
+        torch.cuda.synchronize()
+        q1 = one.query()
+        print(f"problem {j}: n={n} group={q1['group']} grid={q1['grid']}", flush=True)
+        assert q1["group"] > 1 and q1["stalled"] == 0
+        assert torch.equal(u1, u_big[o:o + n])
+    assert plan_big.query()["stalled"] == 0
