@@ -58,18 +58,19 @@ def closed_form(n, k, c, dev):
     return ustar, uex
 
 
-def traffic_for(kernel, kernel_source_hash):
-    """Measured HBM bytes per launch of `kernel` from the committed counter
-    summary, if it was taken on the current kernel source (else None)."""
+def traffic_for(workload, kernel, kernel_source_hash):
+    """Measured HBM bytes per launch of `kernel` in `workload` from the
+    committed counter summary, if it was taken on the current kernel sources
+    (else None)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    ent = t.get("kernels", {}).get(kernel)
-    if not ent or t.get("source_sha256") != kernel_source_hash:
+    if t.get("source_sha256") != kernel_source_hash:
         return None
-    return ent.get("hbm_bytes_per_launch")
+    ent = t.get("workloads", {}).get(workload, {}).get("kernels", {}).get(kernel)
+    return ent.get("hbm_bytes_per_launch") if ent else None
 
 
 def kernel_source_hash():
@@ -202,7 +203,7 @@ def main():
     dom_launch_ms = dom["total_ms"] / dom["launches"]
     dom_bytes = dom["algo_bytes"] / dom["launches"]
     achieved = dom_bytes / (dom_launch_ms * 1e-3) / 1e9
-    traffic = traffic_for(dominant, kernel_source_hash())
+    traffic = traffic_for(wl.name, dominant, kernel_source_hash())
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": dominant,
@@ -231,7 +232,11 @@ def main():
                         "frac_of_hbm_peak": round(model_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "accuracy": acc,
         "memory": {"inputs_and_workspace_bytes": mem_inputs, "peak_allocated_bytes": peak_mem,
-                   "workspace_bytes": ws.numel()},
+                   "workspace_bytes": ws.numel(),
+                   "workspace_bytes_full_grid_fmg": fmgsr.workspace_bytes(n, wl.levels, sr_levels=0,
+                                                                          tau=args.tau),
+                   "workspace_bytes_sr": fmgsr.workspace_bytes(n, wl.levels, sr_levels=1,
+                                                               tau=args.tau)},
         "kernels": {kname: {"launches": v["launches"], "ms": round(v["total_ms"], 4),
                             "GBps": round(v["algo_bytes"] / max(v["total_ms"], 1e-9) / 1e6, 1)}
                     for kname, v in sorted(prof_all.items(), key=lambda kv: -kv[1]["total_ms"])},
@@ -276,6 +281,10 @@ def run_batched(args, dev):
         hvec = torch.cat([torch.full((n,), 1.0 / n, dtype=torch.float64, device=dev)
                           for n in rb.sizes])
         gf, gk, dJ = torch.empty_like(f), torch.empty_like(f), torch.empty_like(f)
+
+    tuned_ms = plan.autotune(f, k, u, stream=stream)
+    log(f"autotuned: {tuned_ms:.3f} ms per solve, {plan.query()['threads']} threads, "
+        f"group {plan.query()['group']}")
 
     def step():
         plan.solve(f, k, out=u, stream=stream)
@@ -327,7 +336,8 @@ def run_batched(args, dev):
     dom_launch_ms = dom["total_ms"] / dom["launches"]
     dom_bytes = dom["algo_bytes"] / dom["launches"]
     achieved = dom_bytes / (dom_launch_ms * 1e-3) / 1e9
-    traffic = traffic_for(dominant, kernel_source_hash())
+    traffic = traffic_for(rb.name + ("" if args.precision == "fp64" else "_" + args.precision),
+                          dominant, kernel_source_hash())
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dominant, "algo_bytes_per_launch": dom_bytes,
@@ -365,7 +375,8 @@ def run_batched(args, dev):
                                + (", forward + adjoint per step" if adjoint else ""),
                    "batch": rb.batch, "total_unknowns": rb.total, "buffer": rb.buffer,
                    "nu": [2, 1], "smoother": "red-black nonlinear GS", "precision": args.precision,
-                   "seed": rb.seed, "threads": q["threads"], "run": q["run"], "grid": q["grid"]},
+                   "seed": rb.seed, "threads": q["threads"], "run": q["run"], "grid": q["grid"],
+                   "group": q["group"], "autotuned": True},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "solve_model": {"algo_bytes_per_step": sum(v["algo_bytes"] for v in prof_all.values()),

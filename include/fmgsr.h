@@ -226,9 +226,11 @@ fmgsr_status fmgsr_batch_adjoint(fmgsr_batch plan, const double *kappa_packed,
                                  void *hip_stream);
 
 /* Project autotuner: times the plan's candidate launch shapes (workgroup
- * size) and segment sizes (the largest fitting core and half of it, unless
+ * size 256 or 512, workgroups per problem 1..16 when the batch is small)
+ * and segment sizes (the largest fitting core and half of it, unless
  * segments were given) on these inputs, keeps the fastest and returns its
- * time per solve in *ms_out (may be NULL).  Synchronises hip_stream;
+ * time per solve in *ms_out (may be NULL).  With the environment variable
+ * FMGSR_AUTOTUNE_LOG=1 every candidate's time is printed to stderr.  Synchronises hip_stream;
  * u_scratch_packed is overwritten.  Segment sizes change the SR iterate
  * (within the method's accuracy); fmgsr_batch_query reports the choice. */
 fmgsr_status fmgsr_batch_autotune(fmgsr_batch plan, const double *f_packed,

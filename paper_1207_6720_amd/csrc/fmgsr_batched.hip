@@ -39,6 +39,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -959,7 +961,7 @@ void free_plan_device(fmgsr_batch_s* b) {
 
 // (Re)build the descriptors for the plan's shape and segment choice and
 // upload them; allocates on first use.
-fmgsr_status build_plan(fmgsr_batch_s* b, int T, int halve) {
+fmgsr_status build_plan(fmgsr_batch_s* b, int T, int halve, int group_cap = kMaxGroup) {
   const int64_t W = (int64_t)T * kRunCells;
   const int64_t pad = pad_of(b->buffer);
   std::vector<Prob> pr(b->batch);
@@ -1008,7 +1010,7 @@ fmgsr_status build_plan(fmgsr_batch_s* b, int T, int halve) {
   per_cu = std::max(per_cu, 1);
   // fewer problems than resident workgroups: split each problem over a group
   const int64_t cap = (int64_t)per_cu * cus;
-  b->group = (b->batch < cap) ? (int)std::min<int64_t>(kMaxGroup, cap / b->batch) : 1;
+  b->group = (b->batch < cap) ? (int)std::min<int64_t>(group_cap, cap / b->batch) : 1;
   b->grid = (int)std::min<int64_t>((int64_t)b->batch * b->group, cap);
   b->algo_bytes = bytes;
   double adj = 0.0;
@@ -1152,7 +1154,17 @@ fmgsr_status fmgsr_batch_create(int32_t batch, const int64_t* n_host, const int6
   std::stable_sort(b->order.begin(), b->order.end(),
                    [&](int32_t x, int32_t y) { return b->n[x] > b->n[y]; });
   if (hipGetDevice(&b->device) != hipSuccess) { (void)hipGetLastError(); delete b; return FMGSR_EDEVICE; }
-  const fmgsr_status st = bt::build_plan(b, 256, 0);
+  // default shape: small batches (fewer problems than CUs) get the wide
+  // window and groups of workgroups; large batches one 256-thread workgroup
+  // per problem (the autotuner refines both)
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete b;
+    return FMGSR_EDEVICE;
+  }
+  fmgsr_status st = bt::build_plan(b, batch < cus ? 512 : 256, 0, 4);
+  if (st == FMGSR_EINVAL && batch < cus) st = bt::build_plan(b, 256, 0, 4);
   if (st != FMGSR_OK) { bt::free_plan_device(b); delete b; return st; }
   *out = b;
   return FMGSR_OK;
@@ -1190,8 +1202,11 @@ fmgsr_status fmgsr_batch_autotune(fmgsr_batch b, const double* f_packed, const d
   hipStream_t s = (hipStream_t)hip_stream;
   const int shapes[2] = {256, 512};
   const int halves = b->auto_segments ? 2 : 1;
+  const int gcaps[5] = {1, 2, 4, 8, 16};
+  const char* env = std::getenv("FMGSR_AUTOTUNE_LOG");
+  const bool log = env && env[0] && env[0] != '0';
   double best = 1e300;
-  int bestT = b->T, bestH = 0;
+  int bestT = b->T, bestH = 0, bestG = bt::kMaxGroup;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     (void)hipGetLastError();
@@ -1200,7 +1215,12 @@ fmgsr_status fmgsr_batch_autotune(fmgsr_batch b, const double* f_packed, const d
   fmgsr_status st = FMGSR_OK;
   for (int T : shapes) {
     for (int h = 0; h < halves && st == FMGSR_OK; ++h) {
-      fmgsr_status bs = bt::build_plan(b, T, h);
+     int last_group = -1;
+     for (int gc : gcaps) {
+      if (st != FMGSR_OK) break;
+      fmgsr_status bs = bt::build_plan(b, T, h, gc);
+      if (bs == FMGSR_OK && b->group == last_group) continue;  // same group size as before
+      last_group = b->group;
       if (bs == FMGSR_EINVAL) continue;  // shape does not fit these problems
       if (bs != FMGSR_OK) { st = bs; break; }
       st = fmgsr_batch_solve(b, f_packed, kappa_packed, u_scratch_packed, hip_stream);  // warm
@@ -1216,13 +1236,16 @@ fmgsr_status fmgsr_batch_autotune(fmgsr_batch b, const double* f_packed, const d
         st = FMGSR_EDEVICE;
         break;
       }
-      if (ms / reps < best) { best = ms / reps; bestT = T; bestH = h; }
+      if (log) std::fprintf(stderr, "fmgsr autotune: threads %d segment-halving %d group %d: %.3f ms\n",
+                            T, h, b->group, ms / reps);
+      if (ms / reps < best) { best = ms / reps; bestT = T; bestH = h; bestG = gc; }
+     }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != FMGSR_OK) return st;
-  st = bt::build_plan(b, bestT, bestH);
+  st = bt::build_plan(b, bestT, bestH, bestG);
   if (st == FMGSR_OK && ms_out) *ms_out = best;
   return st;
 }

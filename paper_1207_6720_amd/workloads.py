@@ -212,14 +212,37 @@ def reaction_problem_numpy(n: int, seed: int, j: int):
 
 def reaction_packed_torch(rb: ReactionBatch, device):
     """Packed (f, kappa, u_exact, u_target) of a whole batch, generated in
-    device memory problem by problem."""
+    device memory for all problems at once (a few dozen whole-batch kernels):
+    every cell gathers its problem's parameters."""
     import torch
-    tot = rb.total
-    out = [torch.empty(tot, dtype=torch.float64, device=device) for _ in range(4)]
-    for j, (n, off) in enumerate(zip(rb.sizes, rb.offsets)):
-        a, cm, phi, target = reaction_params(rb.seed, j)
-        x = (torch.arange(n, dtype=torch.float64, device=device) + 0.5) / n
-        fields = _reaction_fields(torch, x, a, cm, phi, target, np.pi)
-        for o, v in zip(out, (fields[2], fields[0], fields[1], fields[3])):
-            o[off:off + n] = v
-    return tuple(out)
+    B = rb.batch
+    params = [reaction_params(rb.seed, j) for j in range(B)]
+    tens = lambda rows: torch.tensor(np.array(rows), dtype=torch.float64, device=device)
+    a = tens([p[0] for p in params])            # [B, 8]
+    cm = tens([p[1] for p in params])           # [B, 4]
+    phi = tens([p[2] for p in params])          # [B, 4]
+    tg = tens([p[3] for p in params])           # [B, 8]
+    csum = cm.abs().sum(dim=1)                  # [B]
+    sizes = torch.tensor(rb.sizes, dtype=torch.int64, device=device)
+    offs = torch.tensor(rb.offsets, dtype=torch.int64, device=device)
+    pid = torch.repeat_interleave(torch.arange(B, device=device), sizes)
+    local = torch.arange(rb.total, dtype=torch.int64, device=device) - offs[pid]
+    x = (local.to(torch.float64) + 0.5) / sizes[pid].to(torch.float64)
+    del local
+    pi = np.pi
+    g = torch.zeros_like(x)
+    for m in range(4):
+        g = g + cm[pid, m] * torch.cos(x * (float(m + 1) * pi) + phi[pid, m])
+    kappa = 1.0 + 0.5 * g / csum[pid]
+    del g
+    u = torch.zeros_like(x)
+    lap = torch.zeros_like(x)
+    ut = torch.zeros_like(x)
+    for k in range(8):
+        s = torch.sin(x * (float(k + 1) * pi))
+        u = u + a[pid, k] * s
+        lap = lap + (a[pid, k] * float(((k + 1) * pi) ** 2)) * s
+        ut = ut + tg[pid, k] * s
+        del s
+    f = lap + kappa * (u * u * u)
+    return f, kappa, u, ut
