@@ -148,7 +148,7 @@ def main():
     f = W.rhs_torch(n, k, c, dev)
     u = torch.empty_like(f)
     kw = dict(levels=wl.levels, segments=wl.segments, buffer=wl.buffer, nu=(2, 1),
-              sr_levels=args.sr_levels, tau=args.tau)
+              sr_levels=args.sr_levels, tau=args.tau, precision=args.precision)
     ws = fmgsr.alloc_workspace(n, wl.levels, dev, nu=(2, 1), sr_levels=args.sr_levels,
                                tau=args.tau)
     stream = torch.cuda.current_stream(dev)
@@ -203,7 +203,8 @@ def main():
     dom_launch_ms = dom["total_ms"] / dom["launches"]
     dom_bytes = dom["algo_bytes"] / dom["launches"]
     achieved = dom_bytes / (dom_launch_ms * 1e-3) / 1e9
-    traffic = traffic_for(wl.name, dominant, kernel_source_hash())
+    traffic = traffic_for(wl.name + ("" if args.precision == "fp64" else "_" + args.precision),
+                          dominant, kernel_source_hash())
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": dominant,
@@ -219,8 +220,10 @@ def main():
         "metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {wl.description}", "n": n, "levels": wl.levels,
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32relax", "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.description}"
+                               + ("" if args.precision == "fp64" else ", FP32 relaxation"),
+                   "n": n, "levels": wl.levels, "precision": args.precision,
                    "segments": wl.segments, "buffer": wl.buffer, "nu": [2, 1],
                    "smoother": "red-black GS", "tau": args.tau, "sr_levels": args.sr_levels,
                    "seed": 0, "modes": wl.n_modes},

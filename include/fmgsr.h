@@ -74,7 +74,12 @@ enum { FMGSR_OP_POISSON = 0, FMGSR_OP_CUBIC_REACTION = 1, FMGSR_OP_LINEAR_REACTI
  * smoother call forms the FP64 residual once, runs its sweeps on an FP32
  * correction (exterior correction 0; the same iteration in exact
  * arithmetic) and adds it to the FP64 iterate; residuals, tau, transfers and
- * the coarsest solve stay FP64.  Batched entry points only. */
+ * the coarsest solve stay FP64.  In fmgsr_solve the levels handled by the
+ * single-workgroup coarse core (at most 2048 cells) also relax in FP64, and
+ * FP32_RELAX with FMGSR_TAU_LITERAL returns FMGSR_ENOTSUP: literal tau applies
+ * L_h to the iterate, which amplifies the FP32 rounding by ~n^2 into every
+ * coarse right-hand side (at n = 2^16 the result misses a tenth of the
+ * discretisation error by 2.4x). */
 enum { FMGSR_FP64 = 0, FMGSR_FP32_RELAX = 1 };
 
 typedef struct {

@@ -123,6 +123,7 @@ struct Plan {
   int64_t n = 0, n0 = 0;
   int M = 0, C = 0;
   int nu1 = 2, nu2 = 1, nsr = 1, literal = 0;
+  bool f32 = false;  // FP32 relaxation (correction form) on stored and SR levels
   int d_down = 1, d_up = 1;
   int64_t S = 1, s = 0, b = 0, pad = 0;
   int seg_threads = 0;
@@ -142,6 +143,12 @@ fmgsr_status make_plan(int64_t n, int32_t levels, const fmgsr_options& o, Plan* 
   if (o.sr_levels > 1) return FMGSR_ENOTSUP;
   if (o.sr_levels == 1 && M < 1) return FMGSR_EINVAL;
   if (o.tau_mode != FMGSR_TAU_SPLIT && o.tau_mode != FMGSR_TAU_LITERAL) return FMGSR_EINVAL;
+  if (o.precision != FMGSR_FP64 && o.precision != FMGSR_FP32_RELAX) return FMGSR_EINVAL;
+  if (o.reserved != 0) return FMGSR_EINVAL;
+  p->f32 = (o.precision == FMGSR_FP32_RELAX);
+  // literal tau differentiates the iterate (L_h u), amplifying the FP32
+  // rounding of the relaxation by ~n^2 into every coarse right-hand side
+  if (p->f32 && o.tau_mode == FMGSR_TAU_LITERAL) return FMGSR_ENOTSUP;
   p->n = n;
   p->n0 = n0;
   p->M = M;
@@ -237,7 +244,8 @@ struct Ctx {
     bytes += nb + (src_kind == kSrcInterp ? nb * 0.5 : src_kind == kSrcRestrict ? nb * 2.0 : nb);
     const int64_t blocks = (a.n + a.core - 1) / a.core;
     ProfScope ps("k_down", bytes, st);
-    hipLaunchKernelGGL(k_down<kRun>, dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+    if (p->f32) hipLaunchKernelGGL((k_down<kRun, true>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+    else hipLaunchKernelGGL((k_down<kRun, false>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
     check();
   }
 
@@ -256,7 +264,8 @@ struct Ctx {
     a.out[0] = out;
     const int64_t blocks = (a.n + a.core - 1) / a.core;
     ProfScope ps("k_up", bytes, st);
-    hipLaunchKernelGGL(k_up<kRun>, dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+    if (p->f32) hipLaunchKernelGGL((k_up<kRun, true>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+    else hipLaunchKernelGGL((k_up<kRun, false>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
     check();
   }
 
@@ -331,11 +340,11 @@ struct Ctx {
     const double bytes = up ? nb * 2.5 : nb * 2.0 + (q_out ? nb * 0.5 : 0.0);
     const size_t lds = (size_t)p->seg_threads * (kSegRun + 1 + 4) * sizeof(double);
     ProfScope ps(up ? "k_sr_up" : "k_sr_down", bytes, st);
-    if (up)
-      hipLaunchKernelGGL(k_sr_up<kSegRun>, dim3((unsigned)p->S), dim3(p->seg_threads), lds, st, a);
-    else
-      hipLaunchKernelGGL(k_sr_down<kSegRun>, dim3((unsigned)p->S), dim3(p->seg_threads), lds, st,
-                         a);
+    const dim3 g((unsigned)p->S), b(p->seg_threads);
+    if (up && p->f32) hipLaunchKernelGGL((k_sr_up<kSegRun, true>), g, b, lds, st, a);
+    else if (up) hipLaunchKernelGGL((k_sr_up<kSegRun, false>), g, b, lds, st, a);
+    else if (p->f32) hipLaunchKernelGGL((k_sr_down<kSegRun, true>), g, b, lds, st, a);
+    else hipLaunchKernelGGL((k_sr_down<kSegRun, false>), g, b, lds, st, a);
     check();
   }
 
@@ -438,8 +447,6 @@ fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_lef
   fmgsr_options o;
   if (opt) o = *opt;
   else fmgsr_default_options(&o);
-  if (o.precision != FMGSR_FP64) return o.precision == FMGSR_FP32_RELAX ? FMGSR_ENOTSUP : FMGSR_EINVAL;
-  if (o.reserved != 0) return FMGSR_EINVAL;
   Plan p;
   fmgsr_status st = make_plan(n, levels, o, &p);
   if (st == FMGSR_OK) st = plan_segments(n_segments, buffer, &p);
@@ -462,10 +469,9 @@ fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_lef
   std::call_once(attr_once, [] {
     (void)hipFuncSetAttribute((const void*)k_coarse_core, hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024);
-    (void)hipFuncSetAttribute((const void*)k_sr_down<kSegRun>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute((const void*)k_sr_up<kSegRun>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    for (const void* k : {(const void*)k_sr_down<kSegRun, false>, (const void*)k_sr_up<kSegRun, false>,
+                          (const void*)k_sr_down<kSegRun, true>, (const void*)k_sr_up<kSegRun, true>})
+      (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     (void)hipGetLastError();
   });
   Ctx c;

@@ -178,6 +178,84 @@ __device__ __forceinline__ void stage(double* st, const double (&tmp)[K], double
   __syncthreads();
 }
 
+// A window of a level: cells wlo .. wlo + cnt - 1 of a level with n cells;
+// local cell e is inside the level when lo <= e <= hi.  Loads and stores go
+// through a uniform base pointer (base + wlo) with 32-bit lane offsets.
+struct Win {
+  int64_t wlo;
+  int lo, hi, cnt;
+};
+__device__ __forceinline__ Win make_win(int64_t wlo, int cnt, int64_t n) {
+  Win w;
+  w.wlo = wlo;
+  w.cnt = cnt;
+  w.lo = wlo < 0 ? (int)(-wlo) : 0;
+  const int64_t h = n - 1 - wlo;
+  w.hi = h > 0x3fffffff ? 0x3fffffff : (int)h;
+  return w;
+}
+__device__ __forceinline__ int clampe(int e, const Win& w) { return min(max(e, w.lo), w.hi); }
+
+// threadIdx.x through an empty asm statement: per-lane offsets are then
+// recomputed at each use instead of being hoisted out of the tile loops and
+// kept live (which costs dozens of VGPRs across the smoothing).
+__device__ __forceinline__ int lane_id() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+__device__ __forceinline__ bool inside(int e, const Win& w) { return e < w.cnt && e >= w.lo && e <= w.hi; }
+
+template <int K>
+__device__ __forceinline__ void ld_win(double (&tmp)[K], const double* __restrict__ base,
+                                       const Win& w) {
+  const double* __restrict__ p = base + w.wlo;
+  const int t = lane_id();
+#pragma unroll
+  for (int k = 0; k < K; ++k) tmp[k] = p[clampe(t + k * blockDim.x, w)];
+}
+// cell pairs 2g, 2g+1 of the finer level (one 16-byte load each)
+template <int K>
+__device__ __forceinline__ void ld_win_pairs(double2 (&tmp)[K], const double* __restrict__ fine,
+                                             const Win& w) {
+  const double2* __restrict__ p = reinterpret_cast<const double2*>(fine + 2 * w.wlo);
+  const int t = lane_id();
+#pragma unroll
+  for (int k = 0; k < K; ++k) tmp[k] = p[clampe(t + k * blockDim.x, w)];
+}
+// loaded lane values -> stage -> runs; cells outside the level become 0
+template <int K>
+__device__ __forceinline__ void stage_win(double* st, const double (&tmp)[K], double (&v)[K],
+                                          const Win& w) {
+  const int t = lane_id();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = t + k * blockDim.x;
+    st[sidx<K>(e)] = inside(e, w) ? tmp[k] : 0.0;
+  }
+  __syncthreads();
+  stage_to_run<K>(st, v);
+  __syncthreads();
+}
+// runs -> stage -> coalesced store of the window cells whose level index is
+// in [clo, chi)
+template <int K>
+__device__ __forceinline__ void store_win(double* st, const double (&v)[K],
+                                          double* __restrict__ base, int64_t wlo, int64_t clo,
+                                          int64_t chi) {
+  run_to_stage<K>(st, v);
+  __syncthreads();
+  double* __restrict__ q = base + wlo;
+  const int a = (int)(clo - wlo), b = (int)(chi - wlo);
+  const int t = lane_id();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = t + k * blockDim.x;
+    if (e >= a && e < b) q[e] = st[sidx<K>(e)];
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Smoothing on register runs
 // ---------------------------------------------------------------------------
@@ -371,26 +449,28 @@ __device__ void down_visit(const Ctx& c, const Args& ar, int l, int src_kind, co
     const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
     double u[K], Fr[K], a[K];
     double tu[K], tf[K], ta[K];
+    double2 tp[K];
     double tc[K / 2];
-    if (src_kind == kInterp) {
-      const int64_t nc = n >> 1;
-      issue<K / 2>(tc, wlo >> 1, nc, [&](int64_t J) { return src[J]; });
-    } else if (src_kind == kRestrict) {
-      issue<K>(tu, wlo, n, [&](int64_t g) { return (src[2 * g] + src[2 * g + 1]) * 0.5; });
-    } else {
-      issue<K>(tu, wlo, n, [&](int64_t g) { return src[g]; });
-    }
-    issue<K>(tf, wlo, n, [&](int64_t g) { return F[g]; });
-    if constexpr (OP != kOpPoisson) issue<K>(ta, wlo, n, [&](int64_t g) { return A[g]; });
+    const Win wf = make_win(wlo, tl.wcount, n);
+    const Win wc = make_win(wlo >> 1, (tl.wcount + 1) / 2 + 2, n >> 1);
+    if (src_kind == kInterp) ld_win<K / 2>(tc, src, wc);
+    else if (src_kind == kRestrict) ld_win_pairs<K>(tp, src, wf);
+    else ld_win<K>(tu, src, wf);
+    ld_win<K>(tf, F, wf);
+    if constexpr (OP != kOpPoisson) ld_win<K>(ta, A, wf);
     if (src_kind == kInterp) {
       double cr[K / 2];
-      stage<K / 2>(st, tc, cr, wlo >> 1, (tl.wcount + 1) / 2 + 2, n >> 1);
+      stage_win<K / 2>(st, tc, cr, wc);
       interp_from_run<K>(u, cr, g0, n, src, c.gL, c.gR, x);
     } else {
-      stage<K>(st, tu, u, wlo, tl.wcount, n);
+      if (src_kind == kRestrict) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) tu[k] = (tp[k].x + tp[k].y) * 0.5;
+      }
+      stage_win<K>(st, tu, u, wf);
     }
-    stage<K>(st, tf, Fr, wlo, tl.wcount, n);
-    if constexpr (OP != kOpPoisson) stage<K>(st, ta, a, wlo, tl.wcount, n);
+    stage_win<K>(st, tf, Fr, wf);
+    if constexpr (OP != kOpPoisson) stage_win<K>(st, ta, a, wf);
     else {
 #pragma unroll
       for (int j = 0; j < K; ++j) a[j] = 0.0;
@@ -398,11 +478,11 @@ __device__ void down_visit(const Ctx& c, const Args& ar, int l, int src_kind, co
     const SweepGeom sg = sweep_geom(g0, K, max(wlo, (int64_t)0), min(wlo + tl.wcount, n), n,
                                     c.gL, c.gR);
     smooth<K, OP, PREC>(u, Fr, a, sg, ar.nu1, x);
-    store_run<K>(st, u, wlo, clo, chi, Uo);
+    store_win<K>(st, u, Uo, wlo, clo, chi);
     if constexpr (OP != kOpPoisson) {
       double qc[K / 2];
       coarse_rhs<K, OP>(u, Fr, a, qc, g0, n, x);
-      store_run<K / 2>(st, qc, wlo >> 1, clo >> 1, chi >> 1, Qo);
+      store_win<K / 2>(st, qc, Qo, wlo >> 1, clo >> 1, chi >> 1);
     }
   }
   __syncthreads();
@@ -425,14 +505,16 @@ __device__ void up_visit(const Ctx& c, const Args& ar, int l, const double* F, d
     const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
     double u[K], Fr[K], a[K], cv[K / 2];
     double tu[K], tf[K], ta[K], tc[K / 2];
-    issue<K>(tu, wlo, n, [&](int64_t g) { return Up[g]; });
-    issue<K / 2>(tc, wlo >> 1, nc, [&](int64_t J) { return Vc[J]; });
-    issue<K>(tf, wlo, n, [&](int64_t g) { return F[g]; });
-    if constexpr (OP != kOpPoisson) issue<K>(ta, wlo, n, [&](int64_t g) { return A[g]; });
-    stage<K>(st, tu, u, wlo, tl.wcount, n);
-    stage<K / 2>(st, tc, cv, wlo >> 1, (tl.wcount + 1) / 2, nc);
-    stage<K>(st, tf, Fr, wlo, tl.wcount, n);
-    if constexpr (OP != kOpPoisson) stage<K>(st, ta, a, wlo, tl.wcount, n);
+    const Win wf = make_win(wlo, tl.wcount, n);
+    const Win wc = make_win(wlo >> 1, (tl.wcount + 1) / 2, nc);
+    ld_win<K>(tu, Up, wf);
+    ld_win<K / 2>(tc, Vc, wc);
+    ld_win<K>(tf, F, wf);
+    if constexpr (OP != kOpPoisson) ld_win<K>(ta, A, wf);
+    stage_win<K>(st, tu, u, wf);
+    stage_win<K / 2>(st, tc, cv, wc);
+    stage_win<K>(st, tf, Fr, wf);
+    if constexpr (OP != kOpPoisson) stage_win<K>(st, ta, a, wf);
     else {
 #pragma unroll
       for (int j = 0; j < K; ++j) a[j] = 0.0;
@@ -457,7 +539,7 @@ __device__ void up_visit(const Ctx& c, const Args& ar, int l, const double* F, d
     const SweepGeom sg = sweep_geom(g0, K, max(wlo, (int64_t)0), min(wlo + tl.wcount, n), n,
                                     c.gL, c.gR);
     smooth<K, OP, PREC>(u, Fr, a, sg, ar.nu2, x);
-    store_run<K>(st, u, wlo, clo, chi, Vo);
+    store_win<K>(st, u, Vo, wlo, clo, chi);
   }
   __syncthreads();
 }
@@ -476,13 +558,24 @@ __device__ void sr_down(const Ctx& c, const Args& ar, double* st, Xch& x) {
     const int64_t wlo = i * s - pad;
     const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
     double u[K], Fr[K], a[K], cr[K / 2];
-    double tf[K], ta[K], tc[K / 2];
-    issue<K / 2>(tc, wlo >> 1, nc, [&](int64_t J) { return Vc[J]; });
-    issue<K>(tf, wlo, n, [&](int64_t g) { return c.f[g]; });
-    if constexpr (OP != kOpPoisson) issue<K>(ta, wlo, n, [&](int64_t g) { return c.coef_fine(g); });
-    stage<K / 2>(st, tc, cr, wlo >> 1, (wcount + 1) / 2 + 2, nc);
-    stage<K>(st, tf, Fr, wlo, wcount, n);
-    if constexpr (OP != kOpPoisson) stage<K>(st, ta, a, wlo, wcount, n);
+    double tf[K], ta[K], tw[K], tc[K / 2];
+    const Win wf = make_win(wlo, wcount, n);
+    const Win wc = make_win(wlo >> 1, (wcount + 1) / 2 + 2, nc);
+    ld_win<K / 2>(tc, Vc, wc);
+    ld_win<K>(tf, c.f, wf);
+    if constexpr (OP != kOpPoisson) {
+      ld_win<K>(ta, c.kap, wf);
+      if (c.uf) ld_win<K>(tw, c.uf, wf);
+    }
+    stage_win<K / 2>(st, tc, cr, wc);
+    stage_win<K>(st, tf, Fr, wf);
+    if constexpr (OP != kOpPoisson) {
+      if (c.uf) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) ta[k] = (3.0 * ta[k]) * (tw[k] * tw[k]);
+      }
+      stage_win<K>(st, ta, a, wf);
+    }
     else {
 #pragma unroll
       for (int j = 0; j < K; ++j) a[j] = 0.0;
@@ -494,11 +587,11 @@ __device__ void sr_down(const Ctx& c, const Args& ar, double* st, Xch& x) {
     double uh[K / 2];
 #pragma unroll
     for (int p = 0; p < K / 2; ++p) uh[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
-    store_run<K / 2>(st, uh, wlo >> 1, (i * s) >> 1, ((i + 1) * s) >> 1, c.Uh);
+    store_win<K / 2>(st, uh, c.Uh, wlo >> 1, (i * s) >> 1, ((i + 1) * s) >> 1);
     if constexpr (OP != kOpPoisson) {
       double qc[K / 2];
       coarse_rhs<K, OP>(u, Fr, a, qc, g0, n, x);
-      store_run<K / 2>(st, qc, wlo >> 1, (i * s) >> 1, ((i + 1) * s) >> 1, Qo);
+      store_win<K / 2>(st, qc, Qo, wlo >> 1, (i * s) >> 1, ((i + 1) * s) >> 1);
     }
   }
   __syncthreads();
@@ -518,13 +611,24 @@ __device__ void sr_up(const Ctx& c, const Args& ar, double* st, Xch& x) {
     const int64_t wlo = i * s - pad;
     const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
     double u[K], Fr[K], a[K], cr[K / 2];
-    double tf[K], ta[K], tc[K / 2];
-    issue<K / 2>(tc, wlo >> 1, nc, [&](int64_t J) { return Vc[J]; });
-    issue<K>(tf, wlo, n, [&](int64_t g) { return c.f[g]; });
-    if constexpr (OP != kOpPoisson) issue<K>(ta, wlo, n, [&](int64_t g) { return c.coef_fine(g); });
-    stage<K / 2>(st, tc, cr, wlo >> 1, (wcount + 1) / 2 + 2, nc);
-    stage<K>(st, tf, Fr, wlo, wcount, n);
-    if constexpr (OP != kOpPoisson) stage<K>(st, ta, a, wlo, wcount, n);
+    double tf[K], ta[K], tw[K], tc[K / 2];
+    const Win wf = make_win(wlo, wcount, n);
+    const Win wc = make_win(wlo >> 1, (wcount + 1) / 2 + 2, nc);
+    ld_win<K / 2>(tc, Vc, wc);
+    ld_win<K>(tf, c.f, wf);
+    if constexpr (OP != kOpPoisson) {
+      ld_win<K>(ta, c.kap, wf);
+      if (c.uf) ld_win<K>(tw, c.uf, wf);
+    }
+    stage_win<K / 2>(st, tc, cr, wc);
+    stage_win<K>(st, tf, Fr, wf);
+    if constexpr (OP != kOpPoisson) {
+      if (c.uf) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) ta[k] = (3.0 * ta[k]) * (tw[k] * tw[k]);
+      }
+      stage_win<K>(st, ta, a, wf);
+    }
     else {
 #pragma unroll
       for (int j = 0; j < K; ++j) a[j] = 0.0;
@@ -544,14 +648,14 @@ __device__ void sr_up(const Ctx& c, const Args& ar, double* st, Xch& x) {
       }
       smooth<K, OP, PREC>(u, Fr, a, sg, 1, x);
     }
-    if (c.uo) store_run<K>(st, u, wlo, i * s, (i + 1) * s, c.uo);
+    if (c.uo) store_win<K>(st, u, c.uo, wlo, i * s, (i + 1) * s);
     if (c.gk) {
-      double tw[K], w[K];
-      issue<K>(tw, wlo, n, [&](int64_t g) { return c.uf[g]; });
-      stage<K>(st, tw, w, wlo, wcount, n);
+      double tw2[K], w[K];
+      ld_win<K>(tw2, c.uf, wf);
+      stage_win<K>(st, tw2, w, wf);
 #pragma unroll
       for (int j = 0; j < K; ++j) w[j] = -(((w[j] * w[j]) * w[j]) * u[j]);
-      store_run<K>(st, w, wlo, i * s, (i + 1) * s, c.gk);
+      store_win<K>(st, w, c.gk, wlo, i * s, (i + 1) * s);
     }
   }
   __syncthreads();

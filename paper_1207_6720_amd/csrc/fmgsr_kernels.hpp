@@ -22,6 +22,123 @@
 namespace fmgsr {
 
 // ---------------------------------------------------------------------------
+// FP32 relaxation (correction form).  One smoother call forms the FP64
+// residual once, runs its sweeps on an FP32 correction d (d = 0 on cells
+// that are not updated) and adds d to the FP64 iterate.  In exact arithmetic
+// this is the same Gauss-Seidel iteration: with u = u0 + d the point update
+// becomes d_i <- (d_{i-1} + d_{i+1} + res_i) / D, res = F h^2 + (l + r) - D u0
+// (boundary ghosts in res, homogeneous ghosts for d).
+// ---------------------------------------------------------------------------
+
+// Interior runs (no domain boundary in the window): fh = F h^2 / 2, cells
+// [jlo, jhi) of the run updated.
+template <int K>
+__device__ __forceinline__ void cf_sweeps_fast(double (&u)[K], const double (&fh)[K], int nu,
+                                               int jlo, int jhi, Xch& x) {
+  if (nu <= 0) return;
+  double ll, rf;
+  x.swap(u[0], u[K - 1], ll, rf);
+  float rh[K], d[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const double l = (j == 0) ? ll : u[j - 1];
+    const double r = (j == K - 1) ? rf : u[j + 1];
+    rh[j] = (float)(__builtin_fma(l + r, 0.5, fh[j]) - u[j]);  // res / 2
+    d[j] = 0.0f;
+  }
+  for (int s = 0; s < nu; ++s) {
+    const float dl0 = (float)x.from_left((double)d[K - 1]);
+#pragma unroll
+    for (int j = 0; j < K; j += 2) {
+      const float v = __builtin_fmaf((j == 0 ? dl0 : d[j - 1]) + d[j + 1], 0.5f, rh[j]);
+      if (j >= jlo && j < jhi) d[j] = v;
+    }
+    const float dr0 = (float)x.from_right((double)d[0]);
+#pragma unroll
+    for (int j = 1; j < K; j += 2) {
+      const float v = __builtin_fmaf(d[j - 1] + (j == K - 1 ? dr0 : d[j + 1]), 0.5f, rh[j]);
+      if (j >= jlo && j < jhi) d[j] = v;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+    if (j >= jlo && j < jhi) u[j] = u[j] + (double)d[j];
+}
+
+// General runs (domain boundaries, clipped windows): f = F, cells [lo, hi)
+// of the level updated.
+template <int K>
+__device__ __forceinline__ void cf_sweeps(double (&u)[K], const double (&f)[K], int64_t g0,
+                                          int nu, int64_t lo, int64_t hi, int64_t n, double gL,
+                                          double gR, Xch& x) {
+  if (nu <= 0) return;
+  const double h2 = 1.0 / ((double)n * (double)n);
+  const double gL2 = 2.0 * gL, gR2 = 2.0 * gR;
+  const double bdiv = (n == 1) ? 4.0 : 3.0;
+  const RunBounds rb = run_bounds(g0, K, lo, hi, n);
+  double ll, rf;
+  x.swap(u[0], u[K - 1], ll, rf);
+  float rq[K], w[K], d[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    double l = (j == 0) ? ll : u[j - 1];
+    double r = (j == K - 1) ? rf : u[j + 1];
+    double D = 2.0;
+    if (j == rb.jb0) { l = gL2; D = bdiv; }
+    if (j == rb.jbn) { r = gR2; D = bdiv; }
+    const double res = (f[j] * h2 + (l + r)) - D * u[j];
+    rq[j] = (float)(res / D);
+    w[j] = (float)(1.0 / D);
+    d[j] = 0.0f;
+  }
+  for (int s = 0; s < nu; ++s) {
+    const float dl0 = (float)x.from_left((double)d[K - 1]);
+#pragma unroll
+    for (int j = 0; j < K; j += 2) {
+      float dl = (j == 0) ? dl0 : d[j - 1];
+      float dr = d[j + 1];
+      if (j == rb.jb0) dl = 0.0f;
+      if (j == rb.jbn) dr = 0.0f;
+      const float v = __builtin_fmaf(dl + dr, w[j], rq[j]);
+      if (j >= rb.jlo && j < rb.jhi) d[j] = v;
+    }
+    const float dr0 = (float)x.from_right((double)d[0]);
+#pragma unroll
+    for (int j = 1; j < K; j += 2) {
+      float dl = d[j - 1];
+      float dr = (j == K - 1) ? dr0 : d[j + 1];
+      if (j == rb.jb0) dl = 0.0f;
+      if (j == rb.jbn) dr = 0.0f;
+      const float v = __builtin_fmaf(dl + dr, w[j], rq[j]);
+      if (j >= rb.jlo && j < rb.jhi) d[j] = v;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+    if (j >= rb.jlo && j < rb.jhi) u[j] = u[j] + (double)d[j];
+}
+
+// Smoother dispatch on the arithmetic of the relaxation.
+template <int K, bool F32>
+__device__ __forceinline__ void smooth_fast(double (&u)[K], const double (&fh)[K], int nu, Xch& x) {
+  if constexpr (F32) cf_sweeps_fast<K>(u, fh, nu, 0, K, x);
+  else rb_sweeps_fast<K>(u, fh, nu, x);
+}
+template <int K, bool F32>
+__device__ __forceinline__ void smooth_masked(double (&u)[K], const double (&fh)[K], int nu,
+                                              int jlo, int jhi, Xch& x) {
+  if constexpr (F32) cf_sweeps_fast<K>(u, fh, nu, jlo, jhi, x);
+  else rb_sweeps_masked<K>(u, fh, nu, jlo, jhi, x);
+}
+template <int K, bool F32>
+__device__ __forceinline__ void smooth_general(double (&u)[K], const double (&f)[K], int64_t g0,
+                                               int nu, int64_t lo, int64_t hi, int64_t n,
+                                               double gL, double gR, Xch& x) {
+  if constexpr (F32) cf_sweeps<K>(u, f, g0, nu, lo, hi, n, gL, gR, x);
+  else rb_sweeps<K>(u, f, g0, nu, lo, hi, n, gL, gR, x);
+}
+
+// ---------------------------------------------------------------------------
 // Stored levels: vertical down / up kernels
 // ---------------------------------------------------------------------------
 
@@ -65,17 +182,17 @@ __device__ __forceinline__ TileGeom tile_geom(const VertArgs& a, int i, int K) {
   return g;
 }
 
-template <int K, int I>
+template <int K, int I, bool F32>
 __device__ void down_level(const VertArgs& a, double* st, Xch& x, double (&u)[K],
                            const double (&f)[K]) {
   const TileGeom G = tile_geom(a, I, K);
-  rb_sweeps<K>(u, f, G.g0, a.nu, G.lo, G.hi, G.n, a.gL, a.gR, x);
+  smooth_general<K, F32>(u, f, G.g0, a.nu, G.lo, G.hi, G.n, a.gL, a.gR, x);
   store_run<K>(st, u, G.wlo, G.clo, G.chi, a.out[I]);
   if constexpr (I + 1 < kMaxFuse && K >= 4) {
     if (I + 1 < a.levels) {
       double u1[K / 2], f1[K / 2];
       restrict_runs<K>(u, f, u1, f1, G.g0, G.n, x);
-      down_level<K / 2, I + 1>(a, st, x, u1, f1);
+      down_level<K / 2, I + 1, F32>(a, st, x, u1, f1);
     }
   }
 }
@@ -90,7 +207,7 @@ __device__ __forceinline__ bool window_interior(int64_t wlo, int64_t cells, int6
   return wlo >= kInteriorMargin && wlo + cells + kInteriorMargin <= n;
 }
 
-template <int K, int I>
+template <int K, int I, bool F32>
 __device__ void down_level_fast(const VertArgs& a, double* st, Xch& x, double (&u)[K],
                                 double (&f)[K], int64_t wlo0) {
   const int64_t wlo = wlo0 >> I;
@@ -99,14 +216,14 @@ __device__ void down_level_fast(const VertArgs& a, double* st, Xch& x, double (&
   if constexpr (I + 1 < kMaxFuse && K >= 4)
     if (more) fw_fast<K>(f, f1, x);
   half_scaled<K>(f, f, a.n >> I);
-  rb_sweeps_fast<K>(u, f, a.nu, x);
+  smooth_fast<K, F32>(u, f, a.nu, x);
   store_run_fast<K>(st, u, a.out[I] + wlo, (int)(a.halo >> I), (int)((a.halo + a.core) >> I));
   if constexpr (I + 1 < kMaxFuse && K >= 4) {
     if (more) {
       double u1[K / 2];
 #pragma unroll
       for (int p = 0; p < K / 2; ++p) u1[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
-      down_level_fast<K / 2, I + 1>(a, st, x, u1, f1, wlo0);
+      down_level_fast<K / 2, I + 1, F32>(a, st, x, u1, f1, wlo0);
     }
   }
 }
@@ -115,7 +232,7 @@ __device__ void down_level_fast(const VertArgs& a, double* st, Xch& x, double (&
 // then restrict + smooth of the pre-smoothing leg), split tau: the coarse
 // right-hand side is the full weighting of the finer one (the Laplacian
 // part of tau is identically zero with I^ = average, I = full weighting).
-template <int K>
+template <int K, bool F32>
 __global__ __launch_bounds__(kTileThreads) void k_down(VertArgs a) {
   __shared__ double st[kTileThreads * (K + 1)];
   __shared__ double xb[4 * kTileThreads];
@@ -149,7 +266,7 @@ __global__ __launch_bounds__(kTileThreads) void k_down(VertArgs a) {
       stage_tmp<K, true>(st, tf, f, 0);
       stage_tmp<K, true>(st, tu, u, 0);
     }
-    down_level_fast<K, 0>(a, st, x, u, f, wlo0);
+    down_level_fast<K, 0, F32>(a, st, x, u, f, wlo0);
     return;
   }
   const TileGeom G = tile_geom(a, 0, K);
@@ -160,12 +277,12 @@ __global__ __launch_bounds__(kTileThreads) void k_down(VertArgs a) {
     load_restrict_run<K>(st, u, G.wlo, wcount, G.n, a.src);
   else
     load_run<K>(st, u, G.wlo, wcount, G.n, [&](int64_t g) { return a.src[g]; });
-  down_level<K, 0>(a, st, x, u, f);
+  down_level<K, 0, F32>(a, st, x, u, f);
 }
 
 // Up leg, level I of the kernel (I = 0 is the top).  On entry f holds this
 // level's right-hand side; on return u holds its post-smoothed iterate.
-template <int K, int I>
+template <int K, int I, bool F32>
 __device__ void up_level(const VertArgs& a, double* st, Xch& x, const double (&f)[K],
                          double (&u)[K]) {
   const TileGeom G = tile_geom(a, I, K);
@@ -177,7 +294,7 @@ __device__ void up_level(const VertArgs& a, double* st, Xch& x, const double (&f
     if (I + 1 < a.levels) {
       double f1[K / 2];
       restrict_rhs_run<K>(f, f1, G.g0, G.n, x);
-      up_level<K / 2, I + 1>(a, st, x, f1, c);
+      up_level<K / 2, I + 1, F32>(a, st, x, f1, c);
       done = true;
     }
   }
@@ -205,13 +322,13 @@ __device__ void up_level(const VertArgs& a, double* st, Xch& x, const double (&f
       u[2 * p + 1] = u[2 * p + 1] + (3.0 * eJ + ep) * 0.25;
     }
   }
-  rb_sweeps<K>(u, f, G.g0, a.nu, G.lo, G.hi, G.n, a.gL, a.gR, x);
+  smooth_general<K, F32>(u, f, G.g0, a.nu, G.lo, G.hi, G.n, a.gL, a.gR, x);
 }
 
 // tp holds this level's pre-smoothed iterate in flight (lane layout); the
 // coarser levels' loads are issued before descending, so every HBM read of
 // the kernel is outstanding at once.
-template <int K, int I>
+template <int K, int I, bool F32>
 __device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, double (&f)[K],
                               double (&u)[K], const double (&tp)[K], int64_t wlo0) {
   const int64_t wlo = wlo0 >> I;
@@ -223,7 +340,7 @@ __device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, double (&f)
       issue_loads<K / 2, true>(tp1, a.pre[I + 1] + (wlo >> 1), 0);
       double f1[K / 2];
       fw_fast<K>(f, f1, x);
-      up_level_fast<K / 2, I + 1>(a, st, x, f1, c, tp1, wlo0);
+      up_level_fast<K / 2, I + 1, F32>(a, st, x, f1, c, tp1, wlo0);
       done = true;
     }
   }
@@ -246,13 +363,13 @@ __device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, double (&f)
     u[2 * p] = u[2 * p] + (3.0 * e[p] + em) * 0.25;
     u[2 * p + 1] = u[2 * p + 1] + (3.0 * e[p] + ep) * 0.25;
   }
-  rb_sweeps_fast<K>(u, f, a.nu, x);
+  smooth_fast<K, F32>(u, f, a.nu, x);
 }
 
 // Up leg over `levels` stored levels, bottom-up (Fig. 3 post-smoothing leg,
 // Eq. 4); only the top level's core is written.  Lower right-hand sides are
 // the full weighting of the top one (split tau).
-template <int K>
+template <int K, bool F32>
 __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
   __shared__ double st[kTileThreads * (K + 1)];
   __shared__ double xb[4 * kTileThreads];
@@ -265,13 +382,13 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
     issue_loads<K, true>(tf, a.rhs + wlo0, 0);
     issue_loads<K, true>(tp, a.pre[0] + wlo0, 0);
     stage_tmp<K, true>(st, tf, f, 0);
-    up_level_fast<K, 0>(a, st, x, f, u, tp, wlo0);
+    up_level_fast<K, 0, F32>(a, st, x, f, u, tp, wlo0);
     store_run_fast<K>(st, u, a.out[0] + wlo0, (int)a.halo, (int)(a.halo + a.core));
     return;
   }
   const TileGeom G = tile_geom(a, 0, K);
   load_run<K>(st, f, G.wlo, wcount, G.n, [&](int64_t g) { return a.rhs[g]; });
-  up_level<K, 0>(a, st, x, f, u);
+  up_level<K, 0, F32>(a, st, x, f, u);
   store_run<K>(st, u, G.wlo, G.clo, G.chi, a.out[0]);
 }
 
@@ -380,7 +497,7 @@ struct SegArgs {
 // Down pass (Fig. 3 steps 1-5 fused): Pi, nu sweeps on the extended patch,
 // then I^ (and literal tau) on the core's coarse cells.  The fine iterate
 // never leaves the chip.
-template <int K>
+template <int K, bool F32>
 __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
   extern __shared__ double sm[];
   const int W = blockDim.x;
@@ -404,7 +521,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
     interp_fast<K>(u, c, cb + threadIdx.x * (K / 2), x);
     half_scaled<K>(f, f, n);
     const RunBounds rb = run_bounds(g0, K, lo, hi, n);
-    rb_sweeps_masked<K>(u, f, a.nu, rb.jlo, rb.jhi, x);
+    smooth_masked<K, F32>(u, f, a.nu, rb.jlo, rb.jhi, x);
     double uc[K / 2];
 #pragma unroll
     for (int p = 0; p < K / 2; ++p) uc[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
@@ -413,7 +530,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
   }
   load_run<K>(st, f, wlo, a.win, n, [&](int64_t g) { return a.f[g]; });
   load_interp_run<K>(st, u, wlo, a.win, n, a.coarse, a.gL, a.gR, x);
-  rb_sweeps<K>(u, f, g0, a.nu, lo, hi, n, a.gL, a.gR, x);
+  smooth_general<K, F32>(u, f, g0, a.nu, lo, hi, n, a.gL, a.gR, x);
   double uc[K / 2];
 #pragma unroll
   for (int p = 0; p < K / 2; ++p) uc[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
@@ -463,7 +580,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
 // Up pass (Fig. 3 SR branch): full update u = Pi c (Eq. 5), then nu times
 // [Kaczmarz projection onto I^ u = c (Eq. 8, Fig. 5), red-black sweep] on
 // the extended patch; the core streams to u_out.
-template <int K>
+template <int K, bool F32>
 __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
   extern __shared__ double sm[];
   const int W = blockDim.x;
@@ -506,7 +623,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
           }
         }
       }
-      rb_sweeps_masked<K>(u, f, 1, rb.jlo, rb.jhi, x);
+      smooth_masked<K, F32>(u, f, 1, rb.jlo, rb.jhi, x);
     }
     store_run_fast<K>(st, u, a.out + wlo, (int)a.pad, (int)(a.pad + a.s));
     return;
@@ -527,8 +644,12 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
         u[2 * p + 1] = u[2 * p + 1] + r;
       }
     }
-    rb_half<K, 0>(u, f, rb, h2, gL2, gR2, bdiv, x);
-    rb_half<K, 1>(u, f, rb, h2, gL2, gR2, bdiv, x);
+    if constexpr (F32) {
+      cf_sweeps<K>(u, f, g0, 1, lo, hi, n, a.gL, a.gR, x);
+    } else {
+      rb_half<K, 0>(u, f, rb, h2, gL2, gR2, bdiv, x);
+      rb_half<K, 1>(u, f, rb, h2, gL2, gR2, bdiv, x);
+    }
   }
   store_run<K>(st, u, wlo, core_lo, core_hi < n ? core_hi : n, a.out);
 }

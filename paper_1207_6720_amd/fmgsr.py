@@ -131,7 +131,8 @@ def _check_vec(t, name):
 
 
 def solve(f, g=(0.0, 0.0), levels=None, segments=1, buffer=0, nu=(2, 1), sr_levels=1,
-          tau="split", out=None, workspace=None, stream=None, op="poisson", kappa=None):
+          tau="split", out=None, workspace=None, stream=None, op="poisson", kappa=None,
+          precision="fp64"):
     """One FMG-FAS-SR iteration for -u'' (+ reaction) = f on [0,1] (see
     include/fmgsr.h).
 
@@ -153,7 +154,7 @@ def solve(f, g=(0.0, 0.0), levels=None, segments=1, buffer=0, nu=(2, 1), sr_leve
         raise ValueError("out must be a contiguous float64 GPU tensor of f's size")
     if stream is None:
         stream = torch.cuda.current_stream(f.device)
-    o = make_options(nu, sr_levels, tau, workspace)
+    o = make_options(nu, sr_levels, tau, workspace, precision)
     op = Operator(OPS[op], kappa.data_ptr() if kappa is not None else None)
     st = lib().fmgsr_solve(ctypes.byref(op), f.data_ptr(), float(g[0]), float(g[1]), n,
                            int(levels), int(segments), int(buffer), ctypes.byref(o),

@@ -156,3 +156,55 @@ def test_workload_c2_full_size_parity(dev):
     u_ref = oracle_solve(f_host, levels=wl.levels, segments=wl.segments, buffer=wl.buffer)
     err = compare(u.cpu().numpy(), u_ref, bitwise=True)
     print(f"c2 parity rel = {err:.3e}", flush=True)
+
+
+def closed_form_pair(n, k, c):
+    """Discrete solution (sines are eigenvectors of the cell-centred
+    Laplacian, eigenvalue 4 n^2 sin^2(k pi / 2n)) and the continuous one."""
+    x = (np.arange(n) + 0.5) / n
+    ustar = np.zeros(n)
+    uex = np.zeros(n)
+    for kk, cc in zip(k, c):
+        s_ = np.sin(kk * np.pi * x)
+        ustar += cc * (kk * np.pi) ** 2 / (4.0 * n * n * np.sin(kk * np.pi / (2 * n)) ** 2) * s_
+        uex += cc * s_
+    return ustar, uex
+
+
+FP32_CASES = [
+    (1 << 10, 11, 4, 4, "split", 0),
+    (5 << 12, 13, 5, 8, "split", 1),      # N0 = 5
+    (1 << 16, 17, 16, 8, "split", 2),
+    (1 << 14, 15, 1, 0, "split", 3),      # plain FMG-FAS (sr_levels = 0 below)
+]
+
+
+@pytest.mark.parametrize("case", FP32_CASES, ids=lambda c: f"n{c[0]}_L{c[1]}_S{c[2]}_{c[4]}")
+def test_fp32_relaxation_poisson_below_discretisation_error(dev, case):
+    n, levels, S, b, tau, seed = case
+    sr = 0 if S == 1 else 1
+    k, c = W.modes("inv_k2", 16, seed)
+    f = W.rhs_numpy(n, k, c)
+    kw = dict(levels=levels, segments=S, buffer=b, sr_levels=sr, tau=tau)
+    u32 = gpu_solve(dev, f, precision="fp32relax", **kw)
+    u64 = gpu_solve(dev, f, **kw)
+    ref = oracle_solve(f, **kw)
+    ustar, uex = closed_form_pair(n, k, c)
+    disc = np.linalg.norm(ustar - uex) / np.linalg.norm(uex)
+    d32 = np.linalg.norm(u32 - ref) / np.linalg.norm(ref)
+    print(f"n={n} disc={disc:.2e} fp32-vs-oracle={d32:.2e}", flush=True)
+    compare(u64, ref, bitwise=(n >> (levels - 1)) == 1)
+    assert d32 <= 0.1 * disc
+
+
+def test_fp32_relaxation_c2_full_size(dev):
+    wl = W.WORKLOADS["c2"]
+    k, c = W.modes(wl.law, wl.n_modes, 0)
+    f = W.rhs_torch(wl.n, k, c, dev)
+    kw = dict(levels=wl.levels, segments=wl.segments, buffer=wl.buffer)
+    u32 = fmgsr.solve(f, precision="fp32relax", **kw)
+    u64 = fmgsr.solve(f, **kw)
+    torch.cuda.synchronize()
+    d = float(torch.linalg.vector_norm(u32 - u64) / torch.linalg.vector_norm(u64))
+    print(f"c2 fp32 vs fp64 relaxation: {d:.2e}", flush=True)
+    assert d <= 7e-15   # a tenth of this workload's discretisation error (6.9e-14)

@@ -57,7 +57,7 @@ def test_invalid_arguments_rejected_on_host(args, kw):
 
 def test_unsupported_requests():
     assert _solve_raw(1024, 11, 4, 4, sr_levels=2) == F.FMGSR_ENOTSUP
-    assert _solve_raw(1024, 11, 4, 4, precision="fp32relax") == F.FMGSR_ENOTSUP
+    assert _solve_raw(1024, 11, 4, 4, tau="literal", precision="fp32relax") == F.FMGSR_ENOTSUP
     o = F.make_options()
     for kind, expect in ((1, F.FMGSR_EINVAL), (2, F.FMGSR_EINVAL), (7, F.FMGSR_EINVAL)):
         op = F.Operator(kind, None)  # reaction kinds need a device kappa
