@@ -101,6 +101,15 @@ typedef struct {
   size_t workspace_bytes;
   int32_t precision;     /* FMGSR_FP64 or FMGSR_FP32_RELAX                    */
   int32_t reserved;      /* must be 0                                         */
+  double *functionals;   /* fmgsr_solve with sr_levels = 1: NULL, or a device
+                            array [2] that receives h sum u and h sum u^2 of
+                            the finest-level result, accumulated segment by
+                            segment while the SR up pass rebuilds u (Sec. 3.2:
+                            the fine solution is only needed for functionals;
+                            summation order fixed, so results repeat bit for
+                            bit).  With functionals set, u_out may be NULL and
+                            the fine solution is never written.  Needs a
+                            segment core of at least 4 cells.                 */
 } fmgsr_options;
 
 /* Defaults: V(2,1), sr_levels = 1, split tau, FP64, library-managed
@@ -134,7 +143,8 @@ size_t fmgsr_workspace_bytes(int64_t n, int32_t levels, const fmgsr_options *opt
  *   opt         options (NULL = defaults); nu1, nu2 in 0..16; sr_levels 0 or
  *               1 (1 needs levels >= 2).
  *   u_out       [n] result: the finest-level solution after the cycle,
- *               written once as it is produced (Sec. 3.2, streaming).
+ *               written once as it is produced (Sec. 3.2, streaming); may be
+ *               NULL when opt->functionals is set.
  *   hip_stream  stream to enqueue on.
  *
  * Smoother: red-black Gauss-Seidel (red = even cell index first, omega = 1).
@@ -199,8 +209,9 @@ typedef struct {
  *   g_host         [2 batch] Dirichlet values (g_left, g_right) per problem,
  *                  or NULL for homogeneous data.
  *   op_kind        FMGSR_OP_*; kappa is passed at execution.
- *   opt            nu1, nu2 (0..16), precision; sr_levels must be 1 and
- *                  tau_mode split (others: ENOTSUP); workspace ignored.
+ *   opt            nu1, nu2 (0..16), precision; sr_levels must be 1,
+ *                  tau_mode split and functionals NULL (others: ENOTSUP);
+ *                  workspace ignored.
  *   out            receives the plan.
  */
 fmgsr_status fmgsr_batch_create(int32_t batch, const int64_t *n_host, const int64_t *offset_host,

@@ -202,6 +202,7 @@ struct Ctx {
   double gL, gR;
   const double* f;
   double* u_out;
+  double* functionals = nullptr;  // [2] device: h sum u, h sum u^2 of the result
   double *F, *U, *V, *Uh, *Q, *Utop;
   fmgsr_status err = FMGSR_OK;
 
@@ -323,6 +324,7 @@ struct Ctx {
   void seg_launch(bool up, const double* coarse, double* out, double* q_out) {
     SegArgs a;
     std::memset(&a, 0, sizeof(a));
+    if (up && functionals) a.part = Uh;  // Uh is dead once the down pass has been consumed
     a.n = p->n;
     a.gL = gL;
     a.gR = gR;
@@ -401,7 +403,15 @@ struct Ctx {
         up_launch(hi, d, rhs_of(hi), lv(V, lo - 1), U_of(hi), out);
         lo += d;
       }
-      if (sr) seg_launch(true, lv(V, M - 1), u_out, nullptr);
+      if (sr) {
+        seg_launch(true, lv(V, M - 1), u_out, nullptr);
+        if (functionals) {
+          ProfScope ps("k_functionals", (double)P.S * 16.0 + 16.0, st);
+          hipLaunchKernelGGL(k_functionals, dim3(1), dim3(1024), 0, st, Uh, (int64_t)P.S,
+                             1.0 / (double)P.n, functionals);
+          check();
+        }
+      }
     }
   }
 };
@@ -439,6 +449,7 @@ fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_lef
   if (op && op->kind != FMGSR_OP_POISSON) {
     // reaction operators: a batch of one problem (synchronous)
     if (!is_device_ptr(op->kappa)) return FMGSR_EINVAL;
+    if (opt && opt->functionals) return FMGSR_ENOTSUP;
     const double g[2] = {g_left, g_right};
     return fmgsr_solve_batched(1, &n, nullptr, &levels, n_segments > 0 ? &n_segments : nullptr,
                                buffer, op, f, g, opt, u_out, hip_stream);
@@ -451,7 +462,12 @@ fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_lef
   fmgsr_status st = make_plan(n, levels, o, &p);
   if (st == FMGSR_OK) st = plan_segments(n_segments, buffer, &p);
   if (st != FMGSR_OK) return st;
-  if (!is_device_ptr(f) || !is_device_ptr(u_out)) return FMGSR_EINVAL;
+  // on-the-fly functionals (SR level only); u_out may then be NULL: the fine
+  // solution never reaches HBM
+  if (o.functionals) {
+    if (p.nsr != 1 || p.s < 4 || !is_device_ptr(o.functionals)) return FMGSR_EINVAL;
+  }
+  if (!is_device_ptr(f) || (u_out ? !is_device_ptr(u_out) : !o.functionals)) return FMGSR_EINVAL;
   if ((const void*)f == (const void*)u_out) return FMGSR_EINVAL;
   hipStream_t stream = (hipStream_t)hip_stream;
   char* ws = (char*)o.workspace;
@@ -481,6 +497,7 @@ fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_lef
   c.gR = g_right;
   c.f = f;
   c.u_out = u_out;
+  c.functionals = o.functionals;
   c.F = (double*)(ws + p.off_F);
   c.U = (double*)(ws + p.off_U);
   c.V = (double*)(ws + p.off_V);

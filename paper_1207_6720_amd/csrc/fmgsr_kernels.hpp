@@ -490,9 +490,41 @@ struct SegArgs {
   int win;               // window cells actually used (s + 2 pad)
   const double* coarse;  // level n/2 iterate (Pi source; Kaczmarz target)
   const double* f;       // fine right-hand side
-  double* out;           // down: I^ of the smoothed cores [n/2]; up: u_out [n]
+  double* out;           // down: I^ of the smoothed cores [n/2]; up: u_out [n] or nullptr
   double* q_out;         // down, literal tau: coarse rhs [n/2] (else nullptr)
+  double* part;          // up: per-segment (sum u, sum u^2) of the core, or nullptr
 };
+
+// Sums of the core cells [a, b) of this thread's run (run-local indices),
+// in cell order, then over each wavefront by a fixed shuffle tree, then over
+// the wavefronts in order; thread 0 writes (sum u, sum u^2) of the segment
+// to part[2 seg].  The order never depends on scheduling.
+__device__ __forceinline__ void wave_sum2(double& s1, double& s2) {
+  for (int o = 32; o > 0; o >>= 1) {
+    s1 = s1 + __shfl_down(s1, o);
+    s2 = s2 + __shfl_down(s2, o);
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void segment_sums(const double (&u)[K], int a, int b, double* st,
+                                             double* __restrict__ part) {
+  double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+    if (j >= a && j < b) { s1 = s1 + u[j]; s2 = s2 + u[j] * u[j]; }
+  wave_sum2(s1, s2);
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) { st[w] = s1; st[32 + w] = s2; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t1 = st[0], t2 = st[32];
+    for (int i = 1; i < nw; ++i) { t1 = t1 + st[i]; t2 = t2 + st[32 + i]; }
+    part[2 * (int64_t)blockIdx.x] = t1;
+    part[2 * (int64_t)blockIdx.x + 1] = t2;
+  }
+}
 
 // Down pass (Fig. 3 steps 1-5 fused): Pi, nu sweeps on the extended patch,
 // then I^ (and literal tau) on the core's coarse cells.  The fine iterate
@@ -625,7 +657,11 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
       }
       smooth_masked<K, F32>(u, f, 1, rb.jlo, rb.jhi, x);
     }
-    store_run_fast<K>(st, u, a.out + wlo, (int)a.pad, (int)(a.pad + a.s));
+    if (a.out) store_run_fast<K>(st, u, a.out + wlo, (int)a.pad, (int)(a.pad + a.s));
+    if (a.part) {
+      const int e0 = (int)threadIdx.x * K;
+      segment_sums<K>(u, (int)a.pad - e0, (int)(a.pad + a.s) - e0, st, a.part);
+    }
     return;
   }
   load_run<K>(st, f, wlo, a.win, n, [&](int64_t g) { return a.f[g]; });
@@ -651,7 +687,37 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
       rb_half<K, 1>(u, f, rb, h2, gL2, gR2, bdiv, x);
     }
   }
-  store_run<K>(st, u, wlo, core_lo, core_hi < n ? core_hi : n, a.out);
+  if (a.out) store_run<K>(st, u, wlo, core_lo, core_hi < n ? core_hi : n, a.out);
+  if (a.part) {
+    const int64_t c0 = core_lo - g0, c1 = (core_hi < n ? core_hi : n) - g0;
+    segment_sums<K>(u, (int)(c0 < 0 ? 0 : (c0 > K ? K : c0)), (int)(c1 < 0 ? 0 : (c1 > K ? K : c1)),
+                    st, a.part);
+  }
+}
+
+// Functionals of the fine solution from the per-segment sums (fixed order:
+// each thread walks a strided set of segments in order, then the shuffle
+// tree and the wavefronts in order): out[0] = h sum u, out[1] = h sum u^2.
+__global__ __launch_bounds__(1024) void k_functionals(const double* __restrict__ part,
+                                                      int64_t S, double h,
+                                                      double* __restrict__ out) {
+  __shared__ double r[64];
+  const int t = threadIdx.x;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = t; i < S; i += 1024) {
+    const double2 p = reinterpret_cast<const double2*>(part)[i];
+    s1 = s1 + p.x;
+    s2 = s2 + p.y;
+  }
+  wave_sum2(s1, s2);
+  if ((t & 63) == 0) { r[t >> 6] = s1; r[32 + (t >> 6)] = s2; }
+  __syncthreads();
+  if (t == 0) {
+    double t1 = r[0], t2 = r[32];
+    for (int i = 1; i < 16; ++i) { t1 = t1 + r[i]; t2 = t2 + r[32 + i]; }
+    out[0] = h * t1;
+    out[1] = h * t2;
+  }
 }
 
 // ---------------------------------------------------------------------------

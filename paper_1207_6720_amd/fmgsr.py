@@ -25,7 +25,8 @@ class Options(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
                 ("sr_levels", ctypes.c_int32), ("tau_mode", ctypes.c_int32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("functionals", ctypes.c_void_p)]
 
 
 class Operator(ctypes.Structure):
@@ -132,7 +133,7 @@ def _check_vec(t, name):
 
 def solve(f, g=(0.0, 0.0), levels=None, segments=1, buffer=0, nu=(2, 1), sr_levels=1,
           tau="split", out=None, workspace=None, stream=None, op="poisson", kappa=None,
-          precision="fp64"):
+          precision="fp64", functionals=None, write_u=True):
     """One FMG-FAS-SR iteration for -u'' (+ reaction) = f on [0,1] (see
     include/fmgsr.h).
 
@@ -147,18 +148,28 @@ def solve(f, g=(0.0, 0.0), levels=None, segments=1, buffer=0, nu=(2, 1), sr_leve
     n = f.numel()
     if levels is None:
         levels = n.bit_length()  # n a power of two -> N0 = 1
-    if out is None:
+    if not write_u:
+        if functionals is None:
+            raise ValueError("write_u=False needs a functionals tensor")
+        out = None
+    elif out is None:
         out = torch.empty_like(f)
     elif not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
               and out.numel() == n):
         raise ValueError("out must be a contiguous float64 GPU tensor of f's size")
+    if functionals is not None and not (functionals.is_cuda and functionals.dtype == torch.float64
+                                        and functionals.numel() >= 2):
+        raise ValueError("functionals must be a float64 GPU tensor with 2 elements")
     if stream is None:
         stream = torch.cuda.current_stream(f.device)
     o = make_options(nu, sr_levels, tau, workspace, precision)
+    if functionals is not None:
+        o.functionals = functionals.data_ptr()
     op = Operator(OPS[op], kappa.data_ptr() if kappa is not None else None)
     st = lib().fmgsr_solve(ctypes.byref(op), f.data_ptr(), float(g[0]), float(g[1]), n,
                            int(levels), int(segments), int(buffer), ctypes.byref(o),
-                           out.data_ptr(), ctypes.c_void_p(stream.cuda_stream))
+                           out.data_ptr() if out is not None else None,
+                           ctypes.c_void_p(stream.cuda_stream))
     if st != FMGSR_OK:
         raise FmgsrError(st, "fmgsr_solve")
     return out

@@ -208,3 +208,61 @@ def test_fp32_relaxation_c2_full_size(dev):
     d = float(torch.linalg.vector_norm(u32 - u64) / torch.linalg.vector_norm(u64))
     print(f"c2 fp32 vs fp64 relaxation: {d:.2e}", flush=True)
     assert d <= 7e-15   # a tenth of this workload's discretisation error (6.9e-14)
+
+
+def fsum_functionals(u):
+    import math
+    n = u.size
+    return np.array([math.fsum(u) / n, math.fsum(u * u) / n])
+
+
+FUNC_CASES = [
+    (1 << 10, 11, 4, 4, (0.0, 0.0), 0),
+    (5 << 12, 13, 5, 8, (0.3, -0.4), 1),
+    (1 << 14, 15, 4096, 2, (0.0, 0.0), 2),   # 4-cell segment cores
+]
+
+
+@pytest.mark.parametrize("case", FUNC_CASES, ids=lambda c: f"n{c[0]}_S{c[2]}")
+def test_functionals_on_the_fly(dev, case):
+    """h sum u and h sum u^2 accumulated by the SR up pass (fixed order)
+    against the oracle's solution summed exactly; the functional-only solve
+    (u_out = NULL) gives the same bits."""
+    n, levels, S, b, g, seed = case
+    f_host = rhs(n, seed)
+    f = torch.from_numpy(f_host).to(dev)
+    fun = torch.zeros(2, dtype=torch.float64, device=dev)
+    u = fmgsr.solve(f, g=g, levels=levels, segments=S, buffer=b, functionals=fun)
+    fun_only = torch.zeros(2, dtype=torch.float64, device=dev)
+    fmgsr.solve(f, g=g, levels=levels, segments=S, buffer=b, functionals=fun_only, write_u=False)
+    torch.cuda.synchronize()
+    ref = fsum_functionals(oracle_solve(f_host, g=g, levels=levels, segments=S, buffer=b))
+    got = fun.cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 1e-13 * np.abs(ref)), (got, ref)
+    assert torch.equal(fun, fun_only)
+    assert np.allclose(fsum_functionals(u.cpu().numpy()), got, rtol=1e-14, atol=0)
+
+
+def test_functionals_rejections(dev):
+    f = torch.zeros(1 << 10, dtype=torch.float64, device=dev)
+    fun = torch.zeros(2, dtype=torch.float64, device=dev)
+    with pytest.raises(fmgsr.FmgsrError):      # no SR level
+        fmgsr.solve(f, levels=11, sr_levels=0, functionals=fun)
+    with pytest.raises(fmgsr.FmgsrError):      # 2-cell segment cores
+        fmgsr.solve(f, levels=11, segments=512, buffer=2, functionals=fun)
+
+
+def test_functionals_c2_functional_only(dev):
+    """N = 2^24 with the fine solution never written."""
+    wl = W.WORKLOADS["c2"]
+    k, c = W.modes(wl.law, wl.n_modes, 0)
+    f = W.rhs_torch(wl.n, k, c, dev)
+    fun = torch.zeros(2, dtype=torch.float64, device=dev)
+    fmgsr.solve(f, levels=wl.levels, segments=wl.segments, buffer=wl.buffer, functionals=fun,
+                write_u=False)
+    torch.cuda.synchronize()
+    ref = fsum_functionals(oracle_solve(f.cpu().numpy(), levels=wl.levels, segments=wl.segments,
+                                        buffer=wl.buffer))
+    got = fun.cpu().numpy()
+    print("c2 functionals", got, ref, flush=True)
+    assert np.all(np.abs(got - ref) <= 1e-13 * np.abs(ref))

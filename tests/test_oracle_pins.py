@@ -463,3 +463,55 @@ def test_invalid_arguments():
         oracle.fmgsr_solve(f, segments=3, buffer=1, nsr=1)
     with pytest.raises(ValueError):
         oracle.fmgsr_solve(f, rhs_restrict="avg", tau="split")
+
+
+def _paper_study(halo, block, nu, nsr, exps=range(5, 13)):
+    """Relative error of one FMG-SR cycle against the continuous solution in
+    the paper's convergence-study setting (lexicographic GS, average
+    restrictions, literal assembled tau, coarsest grid of 4 cells, blocks of
+    two cells with `halo` cells on each side; halo = 0: point-wise GS)."""
+    errs = []
+    for e in exps:
+        n = 1 << e
+        k, c = W.modes("paper", 0, 0, n)
+        f = W.rhs_numpy(n, k, c)
+        u = oracle.fmgsr_solve(f, levels=e - 1, segments=1, buffer=halo, nsr=nsr,
+                               tau="literal", rhs_restrict="avg", smoother="lex",
+                               tau_assembled=True, block_all=block, nu1=nu, nu2=nu)
+        errs.append(rel(u, W.exact_numpy(n, k, c)))
+    return np.array(errs)
+
+
+def test_paper_figures_6_to_8_claims():
+    """The qualitative findings of the paper's three convergence studies
+    (Sec. 4; the plotted data is not in the source, so the curves are
+    recomputed here): (Fig. 6) with two halo cells, truncation accuracy is
+    lost to some extent with three SR levels and V(1,1) cycles, otherwise
+    second order; (Fig. 7) with four halo cells every configuration is very
+    accurate; (Fig. 8) the point-wise smoother gives cleaner curves."""
+    studies = {}
+    for halo, block in ((2, 2), (4, 2), (0, 0)):
+        for nu in (1, 2):
+            for nsr in (0, 1, 2, 3):
+                studies[(halo, nu, nsr)] = _paper_study(halo, block, nu, nsr)
+    # second order everywhere: error ratios per doubling near 4
+    for key, errs in studies.items():
+        ratios = errs[:-1] / errs[1:]
+        assert np.all((ratios > 2.9) & (ratios < 5.6)), (key, ratios)
+    # Fig. 6: the finest-grid error relative to no SR is worst for
+    # (2 halo, V(1,1), 3 SR levels), and clearly above 1
+    loss = {(nu, nsr): studies[(2, nu, nsr)][-1] / studies[(2, nu, 0)][-1]
+            for nu in (1, 2) for nsr in (1, 2, 3)}
+    assert max(loss, key=loss.get) == (1, 3) and loss[(1, 3)] > 1.5, loss
+    # Fig. 7: with four halo cells every configuration stays close to no SR
+    for nu in (1, 2):
+        for nsr in (1, 2, 3):
+            q = studies[(4, nu, nsr)][-4:] / studies[(4, nu, 0)][-4:]
+            assert np.all((q > 0.6) & (q < 1.3)), (nu, nsr, q)
+    # Fig. 8: the point-wise smoother's convergence ratios vary least
+    def spread(halo):
+        r = [studies[(halo, nu, nsr)][1:-1] / studies[(halo, nu, nsr)][2:]
+             for nu in (1, 2) for nsr in (0, 1, 2, 3)]
+        r = np.concatenate(r)
+        return r.max() - r.min()
+    assert spread(0) < spread(2), (spread(0), spread(2))
