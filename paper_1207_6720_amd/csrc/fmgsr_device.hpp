@@ -114,6 +114,32 @@ struct Xch {
   }
 };
 
+// Exchange of four values per thread, for sweeps with one exchange each:
+// every thread publishes (first, second, last, extra) and reads its left
+// neighbour's last and its right neighbour's first, second and extra (0 at
+// the workgroup edges).  Two halves of 4 W doubles alternate, so one barrier
+// per exchange suffices.
+struct Xch4 {
+  double* buf;  // 8 * W doubles
+  int sel;
+  __device__ void swap(double first, double second, double last, double extra, double& l_last,
+                       double& r_first, double& r_second, double& r_extra) {
+    const int W = blockDim.x, t = threadIdx.x;
+    double* b = buf + (sel ? 4 * W : 0);
+    sel ^= 1;
+    b[t] = first;
+    b[W + t] = second;
+    b[2 * W + t] = last;
+    b[3 * W + t] = extra;
+    __syncthreads();
+    l_last = (t > 0) ? b[2 * W + t - 1] : 0.0;
+    const bool r = (t + 1 < W);
+    r_first = r ? b[t + 1] : 0.0;
+    r_second = r ? b[W + t + 1] : 0.0;
+    r_extra = r ? b[3 * W + t + 1] : 0.0;
+  }
+};
+
 // Per-run bounds in 32-bit local indices (0..K): updatable cells [jlo, jhi)
 // and the run positions of the first and last cell of the level (-1 if the
 // run does not hold them).
@@ -501,6 +527,35 @@ __device__ __forceinline__ void rb_sweeps_masked(double (&u)[K], const double (&
         const double v = __builtin_fma(u[j - 1] + (j == K - 1 ? rf : u[j + 1]), 0.5, fh[j]);
         if (j >= jlo && j < jhi) u[j] = v;
       }
+    }
+  }
+}
+
+// nu red-black sweeps over the run cells [jlo, jhi) with ONE exchange per
+// sweep (interior of the level; fh = F h^2 / 2).  The black update of the
+// run's last cell needs the right neighbour's first (red) cell after its
+// red update; that value is recomputed here from the same operands the
+// neighbour uses (its left value is this run's last cell, its right value
+// its own second cell, its fh its first), so the result is bitwise the same
+// as with an exchange between the two half-sweeps.  nb_upd: whether the
+// neighbour's first cell is updated at all (inside the patch).
+template <int K>
+__device__ __forceinline__ void rb_sweeps_x1(double (&u)[K], const double (&fh)[K], int nu,
+                                             int jlo, int jhi, bool nb_upd, Xch4& x) {
+  const bool all = (jlo == 0 && jhi == K);
+  for (int s = 0; s < nu; ++s) {
+    double ll, r0, r1, fK;
+    x.swap(u[0], u[1], u[K - 1], fh[0], ll, r0, r1, fK);
+#pragma unroll
+    for (int j = 0; j < K; j += 2) {
+      const double v = __builtin_fma((j == 0 ? ll : u[j - 1]) + u[j + 1], 0.5, fh[j]);
+      if (all || (j >= jlo && j < jhi)) u[j] = v;
+    }
+    const double uK = nb_upd ? __builtin_fma(u[K - 1] + r1, 0.5, fK) : r0;
+#pragma unroll
+    for (int j = 1; j < K; j += 2) {
+      const double v = __builtin_fma(u[j - 1] + (j == K - 1 ? uK : u[j + 1]), 0.5, fh[j]);
+      if (all || (j >= jlo && j < jhi)) u[j] = v;
     }
   }
 }

@@ -34,7 +34,7 @@ namespace fmgsr {
 // [jlo, jhi) of the run updated.
 template <int K>
 __device__ __forceinline__ void cf_sweeps_fast(double (&u)[K], const double (&fh)[K], int nu,
-                                               int jlo, int jhi, Xch& x) {
+                                               int jlo, int jhi, bool nb_upd, Xch& x, Xch4& x4) {
   if (nu <= 0) return;
   double ll, rf;
   x.swap(u[0], u[K - 1], ll, rf);
@@ -46,17 +46,21 @@ __device__ __forceinline__ void cf_sweeps_fast(double (&u)[K], const double (&fh
     rh[j] = (float)(__builtin_fma(l + r, 0.5, fh[j]) - u[j]);  // res / 2
     d[j] = 0.0f;
   }
+  // one exchange per sweep: the right neighbour's first (red) correction is
+  // recomputed from the same operands (see rb_sweeps_x1)
   for (int s = 0; s < nu; ++s) {
-    const float dl0 = (float)x.from_left((double)d[K - 1]);
+    double dl0d, d0, d1, rK;
+    x4.swap((double)d[0], (double)d[1], (double)d[K - 1], (double)rh[0], dl0d, d0, d1, rK);
+    const float dl0 = (float)dl0d;
 #pragma unroll
     for (int j = 0; j < K; j += 2) {
       const float v = __builtin_fmaf((j == 0 ? dl0 : d[j - 1]) + d[j + 1], 0.5f, rh[j]);
       if (j >= jlo && j < jhi) d[j] = v;
     }
-    const float dr0 = (float)x.from_right((double)d[0]);
+    const float dK = nb_upd ? __builtin_fmaf(d[K - 1] + (float)d1, 0.5f, (float)rK) : (float)d0;
 #pragma unroll
     for (int j = 1; j < K; j += 2) {
-      const float v = __builtin_fmaf(d[j - 1] + (j == K - 1 ? dr0 : d[j + 1]), 0.5f, rh[j]);
+      const float v = __builtin_fmaf(d[j - 1] + (j == K - 1 ? dK : d[j + 1]), 0.5f, rh[j]);
       if (j >= jlo && j < jhi) d[j] = v;
     }
   }
@@ -118,17 +122,19 @@ __device__ __forceinline__ void cf_sweeps(double (&u)[K], const double (&f)[K], 
     if (j >= rb.jlo && j < rb.jhi) u[j] = u[j] + (double)d[j];
 }
 
-// Smoother dispatch on the arithmetic of the relaxation.
+// Smoother dispatch on the arithmetic of the relaxation (interior runs:
+// one exchange per sweep).
 template <int K, bool F32>
-__device__ __forceinline__ void smooth_fast(double (&u)[K], const double (&fh)[K], int nu, Xch& x) {
-  if constexpr (F32) cf_sweeps_fast<K>(u, fh, nu, 0, K, x);
-  else rb_sweeps_fast<K>(u, fh, nu, x);
+__device__ __forceinline__ void smooth_fast(double (&u)[K], const double (&fh)[K], int nu, Xch& x,
+                                            Xch4& x4) {
+  if constexpr (F32) cf_sweeps_fast<K>(u, fh, nu, 0, K, true, x, x4);
+  else rb_sweeps_x1<K>(u, fh, nu, 0, K, true, x4);
 }
 template <int K, bool F32>
 __device__ __forceinline__ void smooth_masked(double (&u)[K], const double (&fh)[K], int nu,
-                                              int jlo, int jhi, Xch& x) {
-  if constexpr (F32) cf_sweeps_fast<K>(u, fh, nu, jlo, jhi, x);
-  else rb_sweeps_masked<K>(u, fh, nu, jlo, jhi, x);
+                                              int jlo, int jhi, bool nb_upd, Xch& x, Xch4& x4) {
+  if constexpr (F32) cf_sweeps_fast<K>(u, fh, nu, jlo, jhi, nb_upd, x, x4);
+  else rb_sweeps_x1<K>(u, fh, nu, jlo, jhi, nb_upd, x4);
 }
 template <int K, bool F32>
 __device__ __forceinline__ void smooth_general(double (&u)[K], const double (&f)[K], int64_t g0,
@@ -208,7 +214,7 @@ __device__ __forceinline__ bool window_interior(int64_t wlo, int64_t cells, int6
 }
 
 template <int K, int I, bool F32>
-__device__ void down_level_fast(const VertArgs& a, double* st, Xch& x, double (&u)[K],
+__device__ void down_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4, double (&u)[K],
                                 double (&f)[K], int64_t wlo0) {
   const int64_t wlo = wlo0 >> I;
   double f1[K / 2];
@@ -216,14 +222,14 @@ __device__ void down_level_fast(const VertArgs& a, double* st, Xch& x, double (&
   if constexpr (I + 1 < kMaxFuse && K >= 4)
     if (more) fw_fast<K>(f, f1, x);
   half_scaled<K>(f, f, a.n >> I);
-  smooth_fast<K, F32>(u, f, a.nu, x);
+  smooth_fast<K, F32>(u, f, a.nu, x, x4);
   store_run_fast<K>(st, u, a.out[I] + wlo, (int)(a.halo >> I), (int)((a.halo + a.core) >> I));
   if constexpr (I + 1 < kMaxFuse && K >= 4) {
     if (more) {
       double u1[K / 2];
 #pragma unroll
       for (int p = 0; p < K / 2; ++p) u1[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
-      down_level_fast<K / 2, I + 1, F32>(a, st, x, u1, f1, wlo0);
+      down_level_fast<K / 2, I + 1, F32>(a, st, x, x4, u1, f1, wlo0);
     }
   }
 }
@@ -236,7 +242,9 @@ template <int K, bool F32>
 __global__ __launch_bounds__(kTileThreads) void k_down(VertArgs a) {
   __shared__ double st[kTileThreads * (K + 1)];
   __shared__ double xb[4 * kTileThreads];
+  __shared__ double xb4[8 * kTileThreads];
   Xch x{xb, 0};
+  Xch4 x4{xb4, 0};
   const int wcount = kTileThreads * K;
   const int64_t wlo0 = top_wlo(a);
   double u[K], f[K];
@@ -266,7 +274,7 @@ __global__ __launch_bounds__(kTileThreads) void k_down(VertArgs a) {
       stage_tmp<K, true>(st, tf, f, 0);
       stage_tmp<K, true>(st, tu, u, 0);
     }
-    down_level_fast<K, 0, F32>(a, st, x, u, f, wlo0);
+    down_level_fast<K, 0, F32>(a, st, x, x4, u, f, wlo0);
     return;
   }
   const TileGeom G = tile_geom(a, 0, K);
@@ -329,7 +337,7 @@ __device__ void up_level(const VertArgs& a, double* st, Xch& x, const double (&f
 // coarser levels' loads are issued before descending, so every HBM read of
 // the kernel is outstanding at once.
 template <int K, int I, bool F32>
-__device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, double (&f)[K],
+__device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4, double (&f)[K],
                               double (&u)[K], const double (&tp)[K], int64_t wlo0) {
   const int64_t wlo = wlo0 >> I;
   double c[K / 2];
@@ -340,7 +348,7 @@ __device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, double (&f)
       issue_loads<K / 2, true>(tp1, a.pre[I + 1] + (wlo >> 1), 0);
       double f1[K / 2];
       fw_fast<K>(f, f1, x);
-      up_level_fast<K / 2, I + 1, F32>(a, st, x, f1, c, tp1, wlo0);
+      up_level_fast<K / 2, I + 1, F32>(a, st, x, x4, f1, c, tp1, wlo0);
       done = true;
     }
   }
@@ -363,7 +371,7 @@ __device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, double (&f)
     u[2 * p] = u[2 * p] + (3.0 * e[p] + em) * 0.25;
     u[2 * p + 1] = u[2 * p + 1] + (3.0 * e[p] + ep) * 0.25;
   }
-  smooth_fast<K, F32>(u, f, a.nu, x);
+  smooth_fast<K, F32>(u, f, a.nu, x, x4);
 }
 
 // Up leg over `levels` stored levels, bottom-up (Fig. 3 post-smoothing leg,
@@ -373,7 +381,9 @@ template <int K, bool F32>
 __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
   __shared__ double st[kTileThreads * (K + 1)];
   __shared__ double xb[4 * kTileThreads];
+  __shared__ double xb4[8 * kTileThreads];
   Xch x{xb, 0};
+  Xch4 x4{xb4, 0};
   const int wcount = kTileThreads * K;
   const int64_t wlo0 = top_wlo(a);
   double u[K], f[K];
@@ -382,7 +392,7 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
     issue_loads<K, true>(tf, a.rhs + wlo0, 0);
     issue_loads<K, true>(tp, a.pre[0] + wlo0, 0);
     stage_tmp<K, true>(st, tf, f, 0);
-    up_level_fast<K, 0, F32>(a, st, x, f, u, tp, wlo0);
+    up_level_fast<K, 0, F32>(a, st, x, x4, f, u, tp, wlo0);
     store_run_fast<K>(st, u, a.out[0] + wlo0, (int)a.halo, (int)(a.halo + a.core));
     return;
   }
@@ -553,7 +563,9 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
     interp_fast<K>(u, c, cb + threadIdx.x * (K / 2), x);
     half_scaled<K>(f, f, n);
     const RunBounds rb = run_bounds(g0, K, lo, hi, n);
-    smooth_masked<K, F32>(u, f, a.nu, rb.jlo, rb.jhi, x);
+    Xch4 x4{st, 0};  // the stage is idle during the sweeps (8 W <= W (K + 1) doubles)
+    smooth_masked<K, F32>(u, f, a.nu, rb.jlo, rb.jhi, g0 + K >= lo && g0 + K < hi, x, x4);
+    __syncthreads();  // last exchange read before the stage is reused
     double uc[K / 2];
 #pragma unroll
     for (int p = 0; p < K / 2; ++p) uc[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
@@ -637,6 +649,8 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
     half_scaled<K>(f, f, n);
     const RunBounds rb = run_bounds(g0, K, lo, hi, n);
     const bool all = (rb.jlo == 0 && rb.jhi == K);
+    const bool nb_upd = g0 + K >= lo && g0 + K < hi;
+    Xch4 x4{st, 0};  // the stage is idle during the sweeps (8 W <= W (K + 1) doubles)
     for (int it = 0; it < a.nu; ++it) {
       if (all) {
 #pragma unroll
@@ -655,8 +669,9 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
           }
         }
       }
-      smooth_masked<K, F32>(u, f, 1, rb.jlo, rb.jhi, x);
+      smooth_masked<K, F32>(u, f, 1, rb.jlo, rb.jhi, nb_upd, x, x4);
     }
+    __syncthreads();  // last exchange read before the stage is reused
     if (a.out) store_run_fast<K>(st, u, a.out + wlo, (int)a.pad, (int)(a.pad + a.s));
     if (a.part) {
       const int e0 = (int)threadIdx.x * K;
