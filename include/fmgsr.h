@@ -203,8 +203,11 @@ typedef struct {
  *   levels_host    [batch] grids per problem (1..31).
  *   segments_host  [batch] SR segments per problem, or NULL: the library
  *                  picks the largest segment core N0 2^k whose extended patch
- *                  fits one workgroup window.  A given count must divide n_j,
- *                  give an even core and fit the window (EINVAL otherwise).
+ *                  fits one workgroup window (threads x run cells: 256 x 4
+ *                  when the batch has at least as many problems as CUs, else
+ *                  512 x 8).  A given count must divide n_j, give an even
+ *                  core and fit the largest window, 4096 cells (EINVAL
+ *                  otherwise); the plan then takes a window it fits.
  *   buffer         SR buffer cells per side, 0..64.
  *   g_host         [2 batch] Dirichlet values (g_left, g_right) per problem,
  *                  or NULL for homogeneous data.
@@ -242,11 +245,12 @@ fmgsr_status fmgsr_batch_adjoint(fmgsr_batch plan, const double *kappa_packed,
                                  void *hip_stream);
 
 /* Project autotuner: times the plan's candidate launch shapes (workgroup
- * size 256 or 512, workgroups per problem 1..16 when the batch is small)
- * and segment sizes (the largest fitting core and half of it, unless
- * segments were given) on these inputs, keeps the fastest and returns its
- * time per solve in *ms_out (may be NULL).  With the environment variable
- * FMGSR_AUTOTUNE_LOG=1 every candidate's time is printed to stderr.  Synchronises hip_stream;
+ * size 256 or 512, 4 or 8 cells per thread, workgroups per problem 1..16
+ * when the batch is small) and segment sizes (the largest fitting core and
+ * half of it, unless segments were given) on these inputs, keeps the fastest
+ * and returns its time per solve in *ms_out (may be NULL).  With the
+ * environment variable FMGSR_AUTOTUNE_LOG=1 every candidate's time is
+ * printed to stderr.  Synchronises hip_stream;
  * u_scratch_packed is overwritten.  Segment sizes change the SR iterate
  * (within the method's accuracy); fmgsr_batch_query reports the choice. */
 fmgsr_status fmgsr_batch_autotune(fmgsr_batch plan, const double *f_packed,

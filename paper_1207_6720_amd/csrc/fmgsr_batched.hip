@@ -972,7 +972,11 @@ namespace fmgsr {
 namespace bt {
 namespace {
 
-constexpr int kRunCells = 8;
+// Cells per thread: 4 (fewer registers, three resident workgroups per CU;
+// best for many small problems) or 8 (wider windows, fewer tiles; best for
+// few large problems split over groups).  The window of a segment patch is
+// at most kMaxThreads * kMaxRun cells.
+constexpr int kMaxRun = 8;
 constexpr int kMaxGroup = 16;
 
 int64_t pad_of(int buffer) { return (buffer + 2) & ~1; }
@@ -1026,32 +1030,28 @@ int64_t auto_core(int64_t n, int M, int64_t n0, int buffer, int64_t W, int halve
   return best;
 }
 
-template <int OP, int PREC>
-hipError_t launch_k(const Args& a, int grid, int T, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((k_batched<kRunCells, OP, PREC>), dim3(grid), dim3(T), lds, s, a);
+template <int K>
+const void* kernel_ptr_k(int op, int prec) {
+  if (prec == kF64) {
+    if (op == kOpCubic) return (const void*)k_batched<K, kOpCubic, kF64>;
+    if (op == kOpLinear) return (const void*)k_batched<K, kOpLinear, kF64>;
+    return (const void*)k_batched<K, kOpPoisson, kF64>;
+  }
+  if (op == kOpCubic) return (const void*)k_batched<K, kOpCubic, kF32>;
+  if (op == kOpLinear) return (const void*)k_batched<K, kOpLinear, kF32>;
+  return (const void*)k_batched<K, kOpPoisson, kF32>;
+}
+
+const void* kernel_ptr(int op, int prec, int K) {
+  return K == 4 ? kernel_ptr_k<4>(op, prec) : kernel_ptr_k<8>(op, prec);
+}
+
+hipError_t launch(const Args& a, int op, int prec, int K, int grid, int T, size_t lds,
+                  hipStream_t s) {
+  void* args[] = {const_cast<Args*>(&a)};
+  if (hipLaunchKernel(kernel_ptr(op, prec, K), dim3(grid), dim3(T), args, lds, s) != hipSuccess)
+    return hipGetLastError();
   return hipGetLastError();
-}
-
-hipError_t launch(const Args& a, int op, int prec, int grid, int T, size_t lds, hipStream_t s) {
-  if (prec == kF64) {
-    if (op == kOpCubic) return launch_k<kOpCubic, kF64>(a, grid, T, lds, s);
-    if (op == kOpLinear) return launch_k<kOpLinear, kF64>(a, grid, T, lds, s);
-    return launch_k<kOpPoisson, kF64>(a, grid, T, lds, s);
-  }
-  if (op == kOpCubic) return launch_k<kOpCubic, kF32>(a, grid, T, lds, s);
-  if (op == kOpLinear) return launch_k<kOpLinear, kF32>(a, grid, T, lds, s);
-  return launch_k<kOpPoisson, kF32>(a, grid, T, lds, s);
-}
-
-const void* kernel_ptr(int op, int prec) {
-  if (prec == kF64) {
-    if (op == kOpCubic) return (const void*)k_batched<kRunCells, kOpCubic, kF64>;
-    if (op == kOpLinear) return (const void*)k_batched<kRunCells, kOpLinear, kF64>;
-    return (const void*)k_batched<kRunCells, kOpPoisson, kF64>;
-  }
-  if (op == kOpCubic) return (const void*)k_batched<kRunCells, kOpCubic, kF32>;
-  if (op == kOpLinear) return (const void*)k_batched<kRunCells, kOpLinear, kF32>;
-  return (const void*)k_batched<kRunCells, kOpPoisson, kF32>;
 }
 
 void free_plan_device(fmgsr_batch_s* b) {
@@ -1065,8 +1065,8 @@ void free_plan_device(fmgsr_batch_s* b) {
 
 // (Re)build the descriptors for the plan's shape and segment choice and
 // upload them; allocates on first use.
-fmgsr_status build_plan(fmgsr_batch_s* b, int T, int halve, int group_cap = kMaxGroup) {
-  const int64_t W = (int64_t)T * kRunCells;
+fmgsr_status build_plan(fmgsr_batch_s* b, int T, int K, int halve, int group_cap = kMaxGroup) {
+  const int64_t W = (int64_t)T * K;
   const int64_t pad = pad_of(b->buffer);
   std::vector<Prob> pr(b->batch);
   int64_t ws = 0;
@@ -1097,10 +1097,11 @@ fmgsr_status build_plan(fmgsr_batch_s* b, int T, int halve, int group_cap = kMax
 
   // launch shape
   b->T = T;
-  b->region = std::max(T * (kRunCells + 1), 11 * b->n0max);
+  b->K = K;
+  b->region = std::max(T * (K + 1), 11 * b->n0max);
   b->lds = sizeof(double) * ((size_t)b->region + 32 + 4 * (size_t)T);
   if (b->lds > 160 * 1024) return FMGSR_EINVAL;
-  const void* kp = kernel_ptr(b->op, b->prec);
+  const void* kp = kernel_ptr(b->op, b->prec, K);
   if (hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds) != hipSuccess) {
     (void)hipGetLastError();
     return FMGSR_EDEVICE;
@@ -1174,7 +1175,7 @@ fmgsr_status execute(fmgsr_batch_s* b, int op, bool adjoint, const double* f, co
   a.status = b->d_queue + 1;
   a.bars = b->d_queue + 2;
   if (op != b->op) {
-    const void* kp = kernel_ptr(op, b->prec);
+    const void* kp = kernel_ptr(op, b->prec, b->K);
     if (hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds) != hipSuccess) {
       (void)hipGetLastError();
       return FMGSR_EDEVICE;
@@ -1186,7 +1187,7 @@ fmgsr_status execute(fmgsr_batch_s* b, int op, bool adjoint, const double* f, co
   hipLaunchKernelGGL(k_queue_reset, dim3((unsigned)((nbars + 255) / 256)), dim3(256), 0, s,
                      b->d_queue, b->d_queue + 2, nbars);
   if (hipGetLastError() != hipSuccess) return FMGSR_EDEVICE;
-  if (launch(a, op, b->prec, b->grid, b->T, b->lds, s) != hipSuccess) return FMGSR_EDEVICE;
+  if (launch(a, op, b->prec, b->K, b->grid, b->T, b->lds, s) != hipSuccess) return FMGSR_EDEVICE;
   return FMGSR_OK;
 }
 
@@ -1244,7 +1245,7 @@ fmgsr_status fmgsr_batch_create(int32_t batch, const int64_t* n_host, const int6
       const int64_t sg = segments_host[j];
       if (sg < 1 || n % sg != 0) { delete b; return FMGSR_EINVAL; }
       const int64_t s = n / sg;
-      if (s % 2 != 0 || s + 2 * bt::pad_of(buffer) > (int64_t)bt::kMaxThreads * bt::kRunCells) {
+      if (s % 2 != 0 || s + 2 * bt::pad_of(buffer) > (int64_t)bt::kMaxThreads * bt::kMaxRun) {
         delete b;
         return FMGSR_EINVAL;
       }
@@ -1259,16 +1260,18 @@ fmgsr_status fmgsr_batch_create(int32_t batch, const int64_t* n_host, const int6
                    [&](int32_t x, int32_t y) { return b->n[x] > b->n[y]; });
   if (hipGetDevice(&b->device) != hipSuccess) { (void)hipGetLastError(); delete b; return FMGSR_EDEVICE; }
   // default shape: small batches (fewer problems than CUs) get the wide
-  // window and groups of workgroups; large batches one 256-thread workgroup
-  // per problem (the autotuner refines both)
+  // window (512 threads x 8 cells) and groups of workgroups; large batches
+  // one 256 x 4 workgroup per problem, three per CU (the autotuner refines
+  // both)
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) {
     (void)hipGetLastError();
     delete b;
     return FMGSR_EDEVICE;
   }
-  fmgsr_status st = bt::build_plan(b, batch < cus ? 512 : 256, 0, 4);
-  if (st == FMGSR_EINVAL && batch < cus) st = bt::build_plan(b, 256, 0, 4);
+  fmgsr_status st = batch < cus ? bt::build_plan(b, 512, 8, 0, 4) : bt::build_plan(b, 256, 4, 0, 4);
+  if (st == FMGSR_EINVAL) st = bt::build_plan(b, 256, 8, 0, 4);
+  if (st == FMGSR_EINVAL) st = bt::build_plan(b, 512, 8, 0, 4);
   if (st != FMGSR_OK) { bt::free_plan_device(b); delete b; return st; }
   *out = b;
   return FMGSR_OK;
@@ -1305,12 +1308,13 @@ fmgsr_status fmgsr_batch_autotune(fmgsr_batch b, const double* f_packed, const d
   if (!b) return FMGSR_EINVAL;
   hipStream_t s = (hipStream_t)hip_stream;
   const int shapes[2] = {256, 512};
+  const int runs[2] = {4, 8};
   const int halves = b->auto_segments ? 2 : 1;
   const int gcaps[5] = {1, 2, 4, 8, 16};
   const char* env = std::getenv("FMGSR_AUTOTUNE_LOG");
   const bool log = env && env[0] && env[0] != '0';
   double best = 1e300;
-  int bestT = b->T, bestH = 0, bestG = bt::kMaxGroup;
+  int bestT = b->T, bestK = b->K, bestH = 0, bestG = bt::kMaxGroup;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     (void)hipGetLastError();
@@ -1318,11 +1322,12 @@ fmgsr_status fmgsr_batch_autotune(fmgsr_batch b, const double* f_packed, const d
   }
   fmgsr_status st = FMGSR_OK;
   for (int T : shapes) {
+   for (int K : runs) {
     for (int h = 0; h < halves && st == FMGSR_OK; ++h) {
      int last_group = -1;
      for (int gc : gcaps) {
       if (st != FMGSR_OK) break;
-      fmgsr_status bs = bt::build_plan(b, T, h, gc);
+      fmgsr_status bs = bt::build_plan(b, T, K, h, gc);
       if (bs == FMGSR_OK && b->group == last_group) continue;  // same group size as before
       last_group = b->group;
       if (bs == FMGSR_EINVAL) continue;  // shape does not fit these problems
@@ -1340,16 +1345,18 @@ fmgsr_status fmgsr_batch_autotune(fmgsr_batch b, const double* f_packed, const d
         st = FMGSR_EDEVICE;
         break;
       }
-      if (log) std::fprintf(stderr, "fmgsr autotune: threads %d segment-halving %d group %d: %.3f ms\n",
-                            T, h, b->group, ms / reps);
-      if (ms / reps < best) { best = ms / reps; bestT = T; bestH = h; bestG = gc; }
+      if (log)
+        std::fprintf(stderr, "fmgsr autotune: threads %d run %d segment-halving %d group %d: %.3f ms\n",
+                     T, K, h, b->group, ms / reps);
+      if (ms / reps < best) { best = ms / reps; bestT = T; bestK = K; bestH = h; bestG = gc; }
      }
     }
+   }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != FMGSR_OK) return st;
-  st = bt::build_plan(b, bestT, bestH, bestG);
+  st = bt::build_plan(b, bestT, bestK, bestH, bestG);
   if (st == FMGSR_OK && ms_out) *ms_out = best;
   return st;
 }
@@ -1358,7 +1365,7 @@ fmgsr_status fmgsr_batch_query(fmgsr_batch b, fmgsr_batch_shape* shape, int64_t*
   if (!b) return FMGSR_EINVAL;
   if (shape) {
     shape->threads = b->T;
-    shape->run = bt::kRunCells;
+    shape->run = b->K;
     shape->grid = b->grid;
     shape->halo = b->halo;
     shape->lds_bytes = (int64_t)b->lds;

@@ -339,15 +339,17 @@ def test_c4_full_size_sampled_parity(dev):
 
 def test_group_split_matches_single_workgroup_bitwise(dev):
     """A problem solved alone (its levels split over a group of workgroups
-    meeting at barriers) equals the same problem inside a large batch (one
-    workgroup per problem) bit for bit, and neither run stalls."""
+    meeting at barriers, 512 threads x 8 cells) equals the same problem
+    inside a large batch (one 256 x 4 workgroup per problem) bit for bit, and
+    neither run stalls: the tiles are halo-exact, so neither the tiling nor
+    the split changes a value."""
     big = W.reaction_batch("small", seed=12, batch=600)
     f, k, _, _ = packed(big, dev)
     plan_big = fmgsr.Batch(big.sizes, big.levels, buffer=big.buffer, op="cubic")
     u_big = plan_big.solve(f, k)
     torch.cuda.synchronize()
     qb = plan_big.query()
-    assert qb["group"] == 1
+    assert qb["group"] == 1 and (qb["threads"], qb["run"]) == (256, 4)
     for j in (0, 17, 599):
         o, n = int(big.offsets[j]), int(big.sizes[j])
         one = fmgsr.Batch((n,), (big.levels[j],), buffer=big.buffer, op="cubic",
@@ -356,6 +358,6 @@ def test_group_split_matches_single_workgroup_bitwise(dev):
         torch.cuda.synchronize()
         q1 = one.query()
         print(f"problem {j}: n={n} group={q1['group']} grid={q1['grid']}", flush=True)
-        assert q1["group"] > 1 and q1["stalled"] == 0
+        assert q1["group"] > 1 and q1["stalled"] == 0 and q1["run"] == 8
         assert torch.equal(u1, u_big[o:o + n])
     assert plan_big.query()["stalled"] == 0
