@@ -86,7 +86,7 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def cpu_baseline(wl, log2n, runs, dev):
+def cpu_baseline(wl, log2n, runs, dev, sr_levels=1, tau="split"):
     """Time the FP64 oracle (single thread, as written) on a bounded sample:
     the same workload law and segment geometry at N = 2^log2n."""
     import torch
@@ -99,13 +99,15 @@ def cpu_baseline(wl, log2n, runs, dev):
     times = []
     for _ in range(runs):
         t0 = time.perf_counter()
-        oracle.fmgsr_solve(f, levels=log2n + 1, segments=seg, buffer=wl.buffer)
+        oracle.fmgsr_solve(f, levels=log2n + 1, segments=seg, buffer=wl.buffer, nsr=sr_levels,
+                           tau=tau)
         times.append(time.perf_counter() - t0)
         log(f"oracle N=2^{log2n}: {times[-1]:.2f} s")
     t = float(np.median(times))
     return {"value": n / t, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
             "sample": (f"one FMG-FAS-SR iteration of the {wl.name} law at N=2^{log2n} "
-                       f"({seg} segments x {wl.n // wl.segments} cells + {wl.buffer} buffer), "
+                       f"({seg} segments x {wl.n // wl.segments} cells + {wl.buffer} buffer, "
+                       f"{sr_levels} SR level(s), {tau} tau), "
                        f"single-threaded C oracle, median of {runs} runs ({t:.2f} s each)")}
 
 
@@ -120,7 +122,9 @@ def main():
                     help="Poisson workloads: accumulate h sum u and h sum u^2 on the fly and "
                          "never write the fine solution (u_out = NULL)")
     ap.add_argument("--tau", default="split", choices=["split", "literal"])
-    ap.add_argument("--sr-levels", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--sr-levels", type=int, default=1, choices=[0, 1, 2, 3],
+                    help="Poisson workloads: number of SR levels (2 and 3: the finest levels "
+                         "below the top are SR levels too, split tau only)")
     ap.add_argument("--cpu-log2n", type=int, default=24)
     ap.add_argument("--cpu-runs", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -220,8 +224,11 @@ def main():
     dom_launch_ms = dom["total_ms"] / dom["launches"]
     dom_bytes = dom["algo_bytes"] / dom["launches"]
     achieved = dom_bytes / (dom_launch_ms * 1e-3) / 1e9
-    traffic = traffic_for(wl.name + ("" if args.precision == "fp64" else "_" + args.precision),
-                          dominant, kernel_source_hash())
+    variant = (("" if args.precision == "fp64" else "_" + args.precision)
+               + ("" if args.sr_levels == 1 else f"_sr{args.sr_levels}")
+               + ("" if args.tau == "split" else "_literal")
+               + ("_functionals" if args.functionals_only else ""))
+    traffic = traffic_for(wl.name + variant, dominant, kernel_source_hash())
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": dominant,
@@ -230,7 +237,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, args.cpu_log2n, args.cpu_runs, dev)
+        cpu = cpu_baseline(wl, args.cpu_log2n, args.cpu_runs, dev, args.sr_levels, args.tau)
 
     value = n / (ms * 1e-3)
     out = {
@@ -239,7 +246,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64+f32relax", "data": "synthetic",
         "config": {"workload": f"{wl.name}: {wl.description}"
-                               + ("" if args.precision == "fp64" else ", FP32 relaxation"),
+                               + ("" if args.precision == "fp64" else ", FP32 relaxation")
+                               + ("" if args.sr_levels == 1 else f", {args.sr_levels} SR levels"),
                    "n": n, "levels": wl.levels, "precision": args.precision,
                    "segments": wl.segments, "buffer": wl.buffer, "nu": [2, 1],
                    "smoother": "red-black GS", "tau": args.tau, "sr_levels": args.sr_levels,

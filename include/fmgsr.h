@@ -91,9 +91,15 @@ typedef struct {
 typedef struct {
   int32_t nu1;           /* pre-smoothing sweeps per smoother call (>= 0)     */
   int32_t nu2;           /* post-smoothing sweeps per smoother call (>= 0)    */
-  int32_t sr_levels;     /* 1: the finest level is an SR level (full update +
-                            compatible relaxation, never stored); 0: plain
-                            FMG-FAS with every level stored                    */
+  int32_t sr_levels;     /* number k of SR levels, 0..levels-1.  1: the
+                            finest level is an SR level (block smoother,
+                            full update + compatible relaxation, never
+                            stored); k >= 2: the k finest levels are (Sec. 4
+                            studies 0-3), each pre-smoothed by the block
+                            smoother and post-smoothed by the full update +
+                            CR, the ones below the finest stored; split tau
+                            only (literal: FMGSR_ENOTSUP); 0: plain FMG-FAS
+                            with every level stored                          */
   int32_t tau_mode;      /* FMGSR_TAU_SPLIT or FMGSR_TAU_LITERAL              */
   void *workspace;       /* device scratch of >= fmgsr_workspace_bytes()
                             bytes, or NULL: the library then allocates and
@@ -101,7 +107,7 @@ typedef struct {
   size_t workspace_bytes;
   int32_t precision;     /* FMGSR_FP64 or FMGSR_FP32_RELAX                    */
   int32_t reserved;      /* must be 0                                         */
-  double *functionals;   /* fmgsr_solve with sr_levels = 1: NULL, or a device
+  double *functionals;   /* fmgsr_solve with sr_levels >= 1: NULL, or a device
                             array [2] that receives h sum u and h sum u^2 of
                             the finest-level result, accumulated segment by
                             segment while the SR up pass rebuilds u (Sec. 3.2:
@@ -133,15 +139,16 @@ size_t fmgsr_workspace_bytes(int64_t n, int32_t levels, const fmgsr_options *opt
  *   n           finest cells; n % 2^(levels-1) == 0 and N0 = n >> (levels-1)
  *               <= 1024.
  *   levels      number of grids, 1..40.
- *   n_segments  SR segments on the finest level (used when sr_levels = 1):
+ *   n_segments  SR segments on each SR level (used when sr_levels >= 1):
  *               n % n_segments == 0, the core s = n / n_segments is even, and
- *               s + 2 (buffer + 2) <= 8192.
+ *               s + 2 (buffer + 2) <= 8192; on the k-th SR level below the
+ *               finest the core is s / 2^k, which must be an even integer.
  *   buffer      buffer (halo) cells on each side of a segment, 0..1024; each
  *               segment is smoothed on [i s - buffer, (i+1) s + buffer)
  *               clipped to the domain, with the exterior frozen, and only its
  *               core is kept (additive block Jacobi, Sec. 3).
- *   opt         options (NULL = defaults); nu1, nu2 in 0..16; sr_levels 0 or
- *               1 (1 needs levels >= 2).
+ *   opt         options (NULL = defaults); nu1, nu2 in 0..16; sr_levels in
+ *               0..levels-1.
  *   u_out       [n] result: the finest-level solution after the cycle,
  *               written once as it is produced (Sec. 3.2, streaming); may be
  *               NULL when opt->functionals is set.

@@ -4,18 +4,25 @@
 // Schedule of one FMG cycle (Fig. 3) on levels 0..M (M = levels - 1):
 //   forcing hierarchy   F^l = I F^{l+1}, l = M-1..0 (F^M = f), up to four
 //                       levels per launch
-//   coarse core         levels 0..C (C = largest level <= M-1 with at most
-//                       kCoreMaxCells cells) in one workgroup: the FMG cycles
-//                       up to level C, then one V-cycle bottom per later step
+//   coarse core         levels 0..C (C = largest level <= M - max(1, nSR)
+//                       with at most kCoreMaxCells cells) in one workgroup:
+//                       the FMG cycles up to level C, then one V-cycle bottom
+//                       per later step
 //   step t = C+1..M     vertical down kernels over levels t..C+1 (up to four
 //                       levels each), coarse core, vertical up kernels over
 //                       levels C+1..t
 // A stored level keeps two arrays: U (pre-smoothed iterate, written by the
 // down leg, read by the up leg) and V (post-smoothed iterate; the FMG
 // result of step t that step t+1 interpolates from).  Separate arrays keep
-// every launch free of read/write overlap between workgroups.  The SR level
-// (t = M with sr_levels = 1) is never stored: its down pass writes only
+// every launch free of read/write overlap between workgroups.  The finest
+// SR level (t = M, sr_levels >= 1) is never stored: its down pass writes only
 // I^ of the smoothed cores (Uh) and its up pass streams the cores to u_out.
+// With sr_levels = k >= 2 the levels M-k+1 .. M-1 are SR levels too (the
+// semantics of Sec. 4's runs with two and three SR levels): wherever they
+// are visited, their pre-smoothing is the block smoother (segment kernels
+// with the same segment count, so cores halve per level) started from I^ of
+// the SR level above, and their post-smoothing is the full update Pi + CR;
+// their V arrays are stored for the next FMG step.
 // With literal tau every stored level is its own launch, preceded by the
 // tau kernel that forms its right-hand side.
 #include <hip/hip_runtime.h>
@@ -139,9 +146,9 @@ fmgsr_status make_plan(int64_t n, int32_t levels, const fmgsr_options& o, Plan* 
   const int64_t n0 = n >> M;
   if (n0 > kMaxN0) return FMGSR_EINVAL;
   if (o.nu1 < 0 || o.nu1 > 16 || o.nu2 < 0 || o.nu2 > 16) return FMGSR_EINVAL;
-  if (o.sr_levels < 0) return FMGSR_EINVAL;
-  if (o.sr_levels > 1) return FMGSR_ENOTSUP;
-  if (o.sr_levels == 1 && M < 1) return FMGSR_EINVAL;
+  if (o.sr_levels < 0 || o.sr_levels > M) return FMGSR_EINVAL;
+  // per-patch literal tau exists for the finest SR level only
+  if (o.sr_levels > 1 && o.tau_mode == FMGSR_TAU_LITERAL) return FMGSR_ENOTSUP;
   if (o.tau_mode != FMGSR_TAU_SPLIT && o.tau_mode != FMGSR_TAU_LITERAL) return FMGSR_EINVAL;
   if (o.precision != FMGSR_FP64 && o.precision != FMGSR_FP32_RELAX) return FMGSR_EINVAL;
   if (o.reserved != 0) return FMGSR_EINVAL;
@@ -160,7 +167,8 @@ fmgsr_status make_plan(int64_t n, int32_t levels, const fmgsr_options& o, Plan* 
   p->d_up = p->literal ? 1 : fuse_depth(true, o.nu2);
   // coarse core top level
   int C = 0;
-  while (C + 1 <= M - 1 && (n0 << (C + 1)) <= kCoreMaxCells) ++C;
+  const int cmax = M - std::max(o.sr_levels, 1);  // SR levels stay above the core
+  while (C + 1 <= cmax && (n0 << (C + 1)) <= kCoreMaxCells) ++C;
   p->C = C;
   // workspace layout
   const size_t hier = (size_t)(M >= 1 ? lvl_off_ws(n0, M) : 0) * sizeof(double);  // levels 0..M-1
@@ -175,14 +183,19 @@ fmgsr_status make_plan(int64_t n, int32_t levels, const fmgsr_options& o, Plan* 
   return FMGSR_OK;
 }
 
-// Segments of the SR level: core s = n / n_segments (even), window of
-// s + 2 pad cells per workgroup, pad = even >= buffer + 1.
+// Segments of the SR levels: the same count on each, core s_l = n_l /
+// n_segments (even on every SR level), window of s + 2 pad cells per
+// workgroup on the finest, pad = even >= buffer + 1.
 fmgsr_status plan_segments(int64_t n_segments, int32_t buffer, Plan* p) {
   if (p->nsr == 0) return FMGSR_OK;
   if (buffer < 0 || buffer > 1024) return FMGSR_EINVAL;
   if (n_segments < 1 || p->n % n_segments != 0) return FMGSR_EINVAL;
   const int64_t s = p->n / n_segments;
   if (s < 2 || (s & 1)) return FMGSR_EINVAL;
+  for (int k = 1; k < p->nsr; ++k) {
+    const int64_t nk = p->n >> k;
+    if (nk % n_segments != 0 || (nk / n_segments) < 2 || ((nk / n_segments) & 1)) return FMGSR_EINVAL;
+  }
   const int64_t pad = ((int64_t)buffer + 2) & ~(int64_t)1;
   const int64_t cells = s + 2 * pad;
   if (cells > (int64_t)kSegRun * kSegMaxThreads) return FMGSR_EINVAL;
@@ -321,28 +334,38 @@ struct Ctx {
     check();
   }
 
-  void seg_launch(bool up, const double* coarse, double* out, double* q_out) {
+  // Segment pass over SR level l: down (coarse = Pi source, or direct =
+  // the level's restricted iterate) writes I^ of the cores to out (and the
+  // literal coarse rhs to q_out); up writes the cores to out.
+  void seg_launch(int l, bool up, const double* coarse, const double* direct, double* out,
+                  double* q_out) {
     SegArgs a;
     std::memset(&a, 0, sizeof(a));
-    if (up && functionals) a.part = Uh;  // Uh is dead once the down pass has been consumed
-    a.n = p->n;
+    const bool finest = (l == p->M);
+    if (up && finest && functionals) a.part = Uh;  // Uh is dead once the down pass has been consumed
+    a.n = nl(l);
     a.gL = gL;
     a.gR = gR;
     a.nu = up ? p->nu2 : p->nu1;
-    a.s = p->s;
+    a.s = p->s >> (p->M - l);
     a.buffer = p->b;
     a.pad = p->pad;
-    a.win = (int)(p->s + 2 * p->pad);
+    a.win = (int)(a.s + 2 * p->pad);
     a.coarse = coarse;
-    a.f = f;
+    a.direct = direct;
+    a.f = forcing(l);
     a.out = out;
     a.q_out = q_out;
-    const double nb = (double)p->n * 8.0;
-    // coarse n/2 and f n read; down writes n/2 (+ n/2 literal tau), up writes n
-    const double bytes = up ? nb * 2.5 : nb * 2.0 + (q_out ? nb * 0.5 : 0.0);
-    const size_t lds = (size_t)p->seg_threads * (kSegRun + 1 + 4) * sizeof(double);
+    const int64_t thr = (a.win + kSegRun - 1) / kSegRun;
+    const int threads = finest ? p->seg_threads : (int)((thr + 63) / 64 * 64);
+    const double nb = (double)a.n * 8.0;
+    // source (Pi: n/2, direct: n) and f read; down writes n/2 (+ n/2 literal
+    // tau), up writes n
+    const double src = direct ? nb : nb * 0.5;
+    const double bytes = up ? nb * 2.5 : nb + src + nb * 0.5 + (q_out ? nb * 0.5 : 0.0);
+    const size_t lds = (size_t)threads * (kSegRun + 1 + 4) * sizeof(double);
     ProfScope ps(up ? "k_sr_up" : "k_sr_down", bytes, st);
-    const dim3 g((unsigned)p->S), b(p->seg_threads);
+    const dim3 g((unsigned)p->S), b(threads);
     if (up && p->f32) hipLaunchKernelGGL((k_sr_up<kSegRun, true>), g, b, lds, st, a);
     else if (up) hipLaunchKernelGGL((k_sr_up<kSegRun, false>), g, b, lds, st, a);
     else if (p->f32) hipLaunchKernelGGL((k_sr_down<kSegRun, true>), g, b, lds, st, a);
@@ -361,8 +384,9 @@ struct Ctx {
     for (int l = M; l > 0; l -= kMaxFuse) forcing_launch(l, std::min(kMaxFuse, l));
     // FMG cycles on the coarse core levels
     core_launch(0, kSrcDirect, nullptr, nullptr);
+    const int sr_lo = M - P.nsr + 1;  // lowest SR level (M + 1: none)
     for (int t = C + 1; t <= M && err == FMGSR_OK; ++t) {
-      const bool sr = (P.nsr == 1 && t == M);
+      const bool sr = (P.nsr >= 1 && t >= sr_lo);
       double* Ut = (t == M) ? Utop : lv(U, t);
       auto U_of = [&](int l) -> double* { return l == t ? Ut : lv(U, l); };
       // right-hand side in use on level l during this step
@@ -370,10 +394,15 @@ struct Ctx {
         if (l == t) return forcing(t);
         return P.literal ? lv(Q, l) : lv(F, l);
       };
+      // I^ of the smoothed SR level l+1 (the start of level l's down visit):
+      // Uh below the finest level; below an SR level l+1 < M, the U array of
+      // level l+1, which SR levels do not otherwise use
+      auto H = [&](int l) -> double* { return l == M - 1 ? Uh : lv(U, l + 1); };
       int top = t;  // highest stored level of this step
       if (sr) {
-        seg_launch(false, lv(V, M - 1), Uh, P.literal ? lv(Q, M - 1) : nullptr);
-        top = M - 1;
+        seg_launch(t, false, lv(V, t - 1), nullptr, H(t - 1), P.literal ? lv(Q, t - 1) : nullptr);
+        for (int l = t - 1; l >= sr_lo; --l) seg_launch(l, false, nullptr, H(l), H(l - 1), nullptr);
+        top = sr_lo - 1;
       }
       // pre-smoothing leg: stored levels top..C+1
       for (int hi = top; hi >= C + 1;) {
@@ -381,15 +410,15 @@ struct Ctx {
         int src_kind;
         const double* src;
         if (hi == t) { src_kind = kSrcInterp; src = lv(V, t - 1); }
-        else if (sr && hi == M - 1) { src_kind = kSrcDirect; src = Uh; }
+        else if (sr && hi == top) { src_kind = kSrcDirect; src = H(top); }
         else { src_kind = kSrcRestrict; src = U_of(hi + 1); }
         if (P.literal && src_kind == kSrcRestrict) tau_launch(U_of(hi + 1), rhs_of(hi + 1), hi, lv(Q, hi));
         down_launch(hi, d, src_kind, src, rhs_of(hi), U_of(hi));
         hi -= d;
       }
       // coarse core: V-cycle bottom from level C
-      if (sr && C == M - 1) {
-        core_launch(1, kSrcDirect, Uh, rhs_of(C));
+      if (sr && C == top) {
+        core_launch(1, kSrcDirect, H(C), rhs_of(C));
       } else {
         const double* uf = U_of(C + 1);
         if (P.literal) tau_launch(uf, rhs_of(C + 1), C, lv(Q, C));
@@ -404,8 +433,10 @@ struct Ctx {
         lo += d;
       }
       if (sr) {
-        seg_launch(true, lv(V, M - 1), u_out, nullptr);
-        if (functionals) {
+        // full update and compatible relaxation on each SR level, upwards
+        for (int l = sr_lo; l <= t; ++l)
+          seg_launch(l, true, lv(V, l - 1), nullptr, l == M ? u_out : lv(V, l), nullptr);
+        if (functionals && t == M) {
           ProfScope ps("k_functionals", (double)P.S * 16.0 + 16.0, st);
           hipLaunchKernelGGL(k_functionals, dim3(1), dim3(1024), 0, st, Uh, (int64_t)P.S,
                              1.0 / (double)P.n, functionals);
@@ -465,7 +496,7 @@ fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_lef
   // on-the-fly functionals (SR level only); u_out may then be NULL: the fine
   // solution never reaches HBM
   if (o.functionals) {
-    if (p.nsr != 1 || p.s < 4 || !is_device_ptr(o.functionals)) return FMGSR_EINVAL;
+    if (p.nsr < 1 || p.s < 4 || !is_device_ptr(o.functionals)) return FMGSR_EINVAL;
   }
   if (!is_device_ptr(f) || (u_out ? !is_device_ptr(u_out) : !o.functionals)) return FMGSR_EINVAL;
   if ((const void*)f == (const void*)u_out) return FMGSR_EINVAL;

@@ -499,6 +499,9 @@ struct SegArgs {
   int64_t pad;           // window offset left of the core
   int win;               // window cells actually used (s + 2 pad)
   const double* coarse;  // level n/2 iterate (Pi source; Kaczmarz target)
+  const double* direct;  // down, several SR levels: the patch iterate is this
+                         // level-n array (I^ of the finer SR level) instead of
+                         // Pi coarse; nullptr otherwise
   const double* f;       // fine right-hand side
   double* out;           // down: I^ of the smoothed cores [n/2]; up: u_out [n] or nullptr
   double* q_out;         // down, literal tau: coarse rhs [n/2] (else nullptr)
@@ -538,7 +541,10 @@ __device__ __forceinline__ void segment_sums(const double (&u)[K], int a, int b,
 
 // Down pass (Fig. 3 steps 1-5 fused): Pi, nu sweeps on the extended patch,
 // then I^ (and literal tau) on the core's coarse cells.  The fine iterate
-// never leaves the chip.
+// never leaves the chip.  With a.direct the patch starts from that array
+// instead of Pi: an SR level below the finest one, pre-smoothed in blocks
+// from the restricted iterate of the level above (Sec. 4's runs with two
+// and three SR levels).
 template <int K, bool F32>
 __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
   extern __shared__ double sm[];
@@ -554,13 +560,21 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
   const int64_t lo = (core_lo - a.buffer > 0) ? core_lo - a.buffer : 0;
   const int64_t hi = (core_hi + a.buffer < n) ? core_hi + a.buffer : n;
   if (a.q_out == nullptr && window_interior(wlo, (int64_t)W * K, n)) {
-    const double* cb = a.coarse + (wlo >> 1);
-    double tf[K], tc[K / 2], c[K / 2];
+    double tf[K];
     issue_loads<K, false>(tf, a.f + wlo, a.win);
-    issue_loads<K / 2, false>(tc, cb, a.win / 2 + 2);
-    stage_tmp<K, false>(st, tf, f, a.win);
-    stage_tmp<K / 2, false>(st, tc, c, a.win / 2 + 2);
-    interp_fast<K>(u, c, cb + threadIdx.x * (K / 2), x);
+    if (a.direct) {  // uniform per launch
+      double tu[K];
+      issue_loads<K, false>(tu, a.direct + wlo, a.win);
+      stage_tmp<K, false>(st, tf, f, a.win);
+      stage_tmp<K, false>(st, tu, u, a.win);
+    } else {
+      const double* cb = a.coarse + (wlo >> 1);
+      double tc[K / 2], c[K / 2];
+      issue_loads<K / 2, false>(tc, cb, a.win / 2 + 2);
+      stage_tmp<K, false>(st, tf, f, a.win);
+      stage_tmp<K / 2, false>(st, tc, c, a.win / 2 + 2);
+      interp_fast<K>(u, c, cb + threadIdx.x * (K / 2), x);
+    }
     half_scaled<K>(f, f, n);
     const RunBounds rb = run_bounds(g0, K, lo, hi, n);
     Xch4 x4{st, 0};  // the stage is idle during the sweeps (8 W <= W (K + 1) doubles)
@@ -573,7 +587,8 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
     return;
   }
   load_run<K>(st, f, wlo, a.win, n, [&](int64_t g) { return a.f[g]; });
-  load_interp_run<K>(st, u, wlo, a.win, n, a.coarse, a.gL, a.gR, x);
+  if (a.direct) load_run<K>(st, u, wlo, a.win, n, [&](int64_t g) { return a.direct[g]; });
+  else load_interp_run<K>(st, u, wlo, a.win, n, a.coarse, a.gL, a.gR, x);
   smooth_general<K, F32>(u, f, g0, a.nu, lo, hi, n, a.gL, a.gR, x);
   double uc[K / 2];
 #pragma unroll

@@ -109,6 +109,69 @@ def test_parity_vs_oracle(dev, case):
     compare(u_gpu, u_ref, bitwise=(n0 == 1))
 
 
+# several SR levels (Sec. 4 studies 0-3): block pre-smoothing from I^ of the
+# SR level above and full update + CR on every SR level, split tau
+# (n, levels, segments, buffer, nu, sr_levels, g, seed)
+MULTI_SR_CASES = [
+    (1 << 10, 11, 4, 4, (2, 1), 2, (0.0, 0.0), 30),
+    (1 << 10, 11, 4, 2, (1, 1), 3, (0.2, -0.1), 31),     # thin buffer: blocks matter
+    (16, 5, 1, 1, (2, 1), 4, (0.3, -0.2), 32),           # every level above the coarsest
+    (64, 7, 8, 2, (2, 1), 2, (0.0, 0.0), 33),            # core directly below the SR levels
+    (1 << 12, 13, 8, 0, (2, 1), 2, (0.0, 0.0), 34),      # no buffer
+    (1 << 14, 15, 16, 8, (2, 1), 2, (0.0, 0.0), 35),     # stored level between core and SR
+    (1 << 16, 17, 64, 1, (2, 1), 3, (0.25, -1.5), 36),
+    (5 << 12, 13, 5, 8, (2, 1), 2, (0.0, 0.0), 37),      # N0 = 5
+    (7 << 12, 12, 28, 3, (3, 2), 2, (0.1, 0.2), 38),     # N0 = 14
+]
+
+
+@pytest.mark.parametrize("case", MULTI_SR_CASES,
+                         ids=lambda c: f"n{c[0]}_L{c[1]}_S{c[2]}_b{c[3]}_nu{c[4][0]}{c[4][1]}_sr{c[5]}")
+def test_parity_several_sr_levels(dev, case):
+    n, levels, S, b, nu, sr, g, seed = case
+    print(f"case n={n} levels={levels} S={S} b={b} nu={nu} sr={sr}", flush=True)
+    f = rhs(n, seed)
+    kw = dict(g=g, levels=levels, segments=S, buffer=b, nu=nu, sr_levels=sr)
+    u_gpu = gpu_solve(dev, f, **kw)
+    u_ref = oracle_solve(f, **kw)
+    compare(u_gpu, u_ref, bitwise=(n >> (levels - 1)) == 1)
+    # the extra SR levels are a different smoother: the result moves, within
+    # the method's accuracy
+    one = oracle_solve(f, **dict(kw, sr_levels=1))
+    assert not np.array_equal(u_ref, one)
+
+
+def test_several_sr_levels_fp32_and_functionals(dev):
+    n, levels, S, b = 1 << 14, 15, 16, 8
+    k, c = W.modes("inv_k2", 16, 40)
+    f_host = W.rhs_numpy(n, k, c)
+    kw = dict(levels=levels, segments=S, buffer=b, sr_levels=2)
+    ref = oracle_solve(f_host, **kw)
+    ustar, uex = closed_form_pair(n, k, c)
+    disc = np.linalg.norm(ustar - uex) / np.linalg.norm(uex)
+    u32 = gpu_solve(dev, f_host, precision="fp32relax", **kw)
+    d32 = np.linalg.norm(u32 - ref) / np.linalg.norm(ref)
+    print(f"sr_levels=2 fp32 relaxation vs oracle {d32:.2e}, disc {disc:.2e}", flush=True)
+    assert d32 <= 0.1 * disc
+    f = torch.from_numpy(f_host).to(dev)
+    fun = torch.zeros(2, dtype=torch.float64, device=dev)
+    fmgsr.solve(f, functionals=fun, write_u=False, **kw)
+    torch.cuda.synchronize()
+    want = fsum_functionals(ref)
+    got = fun.cpu().numpy()
+    assert np.all(np.abs(got - want) <= 1e-13 * np.abs(want)), (got, want)
+
+
+def test_several_sr_levels_rejections(dev):
+    f = torch.zeros(1 << 10, dtype=torch.float64, device=dev)
+    with pytest.raises(fmgsr.FmgsrError):      # odd core on the third SR level
+        fmgsr.solve(f, levels=11, segments=256, buffer=4, sr_levels=3)
+    with pytest.raises(fmgsr.FmgsrError):      # literal tau
+        fmgsr.solve(f, levels=11, segments=4, buffer=4, sr_levels=2, tau="literal")
+    with pytest.raises(fmgsr.FmgsrError):      # as many SR levels as grids
+        fmgsr.solve(f, levels=11, segments=1, buffer=4, sr_levels=11)
+
+
 def test_repeatable_and_workspace_reuse(dev):
     n, levels = 1 << 14, 15
     f = torch.from_numpy(rhs(n, 30)).to(dev)
@@ -156,6 +219,22 @@ def test_workload_c2_full_size_parity(dev):
     u_ref = oracle_solve(f_host, levels=wl.levels, segments=wl.segments, buffer=wl.buffer)
     err = compare(u.cpu().numpy(), u_ref, bitwise=True)
     print(f"c2 parity rel = {err:.3e}", flush=True)
+
+
+def test_workload_c2_two_sr_levels(dev):
+    """N = 2^24 with the two finest levels as SR levels (2^12 segments of
+    4096 and of 2048 cells, 8 buffer cells)."""
+    wl = W.WORKLOADS["c2"]
+    k, c = W.modes(wl.law, wl.n_modes, 1)
+    f = W.rhs_torch(wl.n, k, c, dev)
+    kw = dict(levels=wl.levels, segments=wl.segments, buffer=wl.buffer, sr_levels=2)
+    print("c2, 2 SR levels: GPU solve", flush=True)
+    u = fmgsr.solve(f, **kw)
+    torch.cuda.synchronize()
+    print("c2, 2 SR levels: oracle solve", flush=True)
+    u_ref = oracle_solve(f.cpu().numpy(), **kw)
+    err = compare(u.cpu().numpy(), u_ref, bitwise=True)
+    print(f"c2 (2 SR levels) parity rel = {err:.3e}", flush=True)
 
 
 def closed_form_pair(n, k, c):

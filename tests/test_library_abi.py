@@ -50,13 +50,17 @@ def _solve_raw(n, levels, segs, buf, **kw):
     ((1024, 11, 4, 4), {"nu": (17, 1)}),  # too many sweeps
     ((1024, 11, 4, 4), {}),               # valid sizes, NULL device pointers
     ((1, 1, 1, 0), {"sr_levels": 1}),     # SR level needs a coarser level
+    ((1024, 11, 4, 4), {"sr_levels": 11}),  # more SR levels than coarser grids
+    ((1024, 11, 256, 4), {"sr_levels": 3}),  # core 4 -> 2 -> 1: odd on the third SR level
+    ((1024, 11, 4, 4), {"sr_levels": 2}),  # valid multi-level SR, NULL device pointers
 ])
 def test_invalid_arguments_rejected_on_host(args, kw):
     assert _solve_raw(*args, **kw) == F.FMGSR_EINVAL
 
 
 def test_unsupported_requests():
-    assert _solve_raw(1024, 11, 4, 4, sr_levels=2) == F.FMGSR_ENOTSUP
+    # per-patch literal tau exists for the finest SR level only
+    assert _solve_raw(1024, 11, 4, 4, sr_levels=2, tau="literal") == F.FMGSR_ENOTSUP
     assert _solve_raw(1024, 11, 4, 4, tau="literal", precision="fp32relax") == F.FMGSR_ENOTSUP
     o = F.make_options()
     for kind, expect in ((1, F.FMGSR_EINVAL), (2, F.FMGSR_EINVAL), (7, F.FMGSR_EINVAL)):
