@@ -134,6 +134,11 @@ struct Plan {
   int d_down = 1, d_up = 1;
   int64_t S = 1, s = 0, b = 0, pad = 0;
   int seg_threads = 0;
+  // sr_levels >= 2: levels M and M-1 are never stored; the finest segment
+  // passes rebuild level M-1 on a window of s/2 + 2 p1 cells
+  int64_t p1 = 0;
+  int R = 1;
+  int seg2_threads = 0;
   // workspace layout (byte offsets)
   size_t off_F = 0, off_U = 0, off_V = 0, off_Uh = 0, off_Q = 0, off_Utop = 0, total = 0;
 };
@@ -172,10 +177,15 @@ fmgsr_status make_plan(int64_t n, int32_t levels, const fmgsr_options& o, Plan* 
   p->C = C;
   // workspace layout
   const size_t hier = (size_t)(M >= 1 ? lvl_off_ws(n0, M) : 0) * sizeof(double);  // levels 0..M-1
+  // with two or more SR levels, V holds levels 0..M-2 only and U levels
+  // 0..M-2 plus I^ of level M-1 (n/4 cells) in level M-1's place
+  const bool two = (o.sr_levels >= 2);
+  const size_t hierV = two ? (size_t)lvl_off_ws(n0, M - 1) * sizeof(double) : hier;
+  const size_t hierU = two ? hierV + (size_t)(n >> 2) * sizeof(double) : hier;
   size_t off = 0;
   p->off_F = off; off = align_up(off + hier);
-  p->off_U = off; off = align_up(off + hier);
-  p->off_V = off; off = align_up(off + hier);
+  p->off_U = off; off = align_up(off + hierU);
+  p->off_V = off; off = align_up(off + hierV);
   p->off_Uh = off; off = align_up(off + (p->nsr ? (size_t)(n / 2) * sizeof(double) : 0));
   p->off_Q = off; off = align_up(off + (p->literal ? hier : 0));
   p->off_Utop = off; off = align_up(off + (p->nsr == 0 && M >= 1 ? (size_t)n * sizeof(double) : 0));
@@ -205,6 +215,17 @@ fmgsr_status plan_segments(int64_t n_segments, int32_t buffer, Plan* p) {
   p->b = buffer;
   p->pad = pad;
   p->seg_threads = (int)((thr + 63) / 64 * 64);
+  if (p->nsr >= 2) {
+    // level-(M-1) margin: pad/2 + 2 cells for Pi's reach from the level-M
+    // window, 3 per CR iteration of stale cells from the window edges, even
+    p->p1 = ((pad / 2 + 3 * (int64_t)p->nu2 + 6) + 1) & ~(int64_t)1;
+    p->R = (int)((pad / 2 + 2 + s / 2 - 1) / (s / 2));
+    const int64_t cells1 = s / 2 + 2 * p->p1;
+    const int64_t thr1 = std::max(thr, (cells1 + kSegRun / 2 - 1) / (kSegRun / 2));
+    if (thr1 > kSegMaxThreads) return FMGSR_EINVAL;
+    p->seg2_threads = (int)((thr1 + 63) / 64 * 64);
+    if (p->seg2_threads > kSegMaxThreads) return FMGSR_EINVAL;
+  }
   return FMGSR_OK;
 }
 
@@ -373,6 +394,45 @@ struct Ctx {
     check();
   }
 
+  // Finest segment pass with level M-1 unstored: rebuilds V^{M-1} from
+  // V^{M-2} per segment, then the level-M down (I^ of the cores to Uh) or
+  // up (cores to u_out, functionals) pass.
+  void seg2_launch(bool up) {
+    Seg2Args a;
+    std::memset(&a, 0, sizeof(a));
+    const int M = p->M;
+    a.n = p->n;
+    a.gL = gL;
+    a.gR = gR;
+    a.nu1 = p->nu1;
+    a.nu2 = p->nu2;
+    a.s = p->s;
+    a.S = p->S;
+    a.R = p->R;
+    a.buffer = p->b;
+    a.pad = p->pad;
+    a.win = (int)(p->s + 2 * p->pad);
+    a.p1 = p->p1;
+    a.win1 = (int)(p->s / 2 + 2 * p->p1);
+    a.v2 = lv(V, M - 2);
+    a.f1 = lv(F, M - 1);
+    a.f = f;
+    a.out = up ? u_out : Uh;
+    if (up && functionals) a.part = Uh;
+    const double nb = (double)p->n * 8.0;
+    // V^{M-2} n/4, F^{M-1} n/2 and f n read; down writes n/2, up writes n
+    const double bytes = nb * 1.75 + (up ? (u_out ? nb : 0.0) : nb * 0.5);
+    const int threads = p->seg2_threads;
+    const size_t lds = (size_t)threads * (kSegRun + 1 + 4) * sizeof(double);
+    ProfScope ps(up ? "k_sr2_up" : "k_sr2_down", bytes, st);
+    const dim3 g((unsigned)p->S), b(threads);
+    if (up && p->f32) hipLaunchKernelGGL((k_sr2<kSegRun, true, true>), g, b, lds, st, a);
+    else if (up) hipLaunchKernelGGL((k_sr2<kSegRun, false, true>), g, b, lds, st, a);
+    else if (p->f32) hipLaunchKernelGGL((k_sr2<kSegRun, true, false>), g, b, lds, st, a);
+    else hipLaunchKernelGGL((k_sr2<kSegRun, false, false>), g, b, lds, st, a);
+    check();
+  }
+
   void run() {
     const Plan& P = *p;
     const int M = P.M, C = P.C;
@@ -398,9 +458,13 @@ struct Ctx {
       // Uh below the finest level; below an SR level l+1 < M, the U array of
       // level l+1, which SR levels do not otherwise use
       auto H = [&](int l) -> double* { return l == M - 1 ? Uh : lv(U, l + 1); };
+      // with two or more SR levels, level M-1 is never stored either: the
+      // finest passes rebuild it from V^{M-2}
+      const bool two = (P.nsr >= 2);
       int top = t;  // highest stored level of this step
       if (sr) {
-        seg_launch(t, false, lv(V, t - 1), nullptr, H(t - 1), P.literal ? lv(Q, t - 1) : nullptr);
+        if (two && t == M) seg2_launch(false);
+        else seg_launch(t, false, lv(V, t - 1), nullptr, H(t - 1), P.literal ? lv(Q, t - 1) : nullptr);
         for (int l = t - 1; l >= sr_lo; --l) seg_launch(l, false, nullptr, H(l), H(l - 1), nullptr);
         top = sr_lo - 1;
       }
@@ -434,8 +498,11 @@ struct Ctx {
       }
       if (sr) {
         // full update and compatible relaxation on each SR level, upwards
-        for (int l = sr_lo; l <= t; ++l)
-          seg_launch(l, true, lv(V, l - 1), nullptr, l == M ? u_out : lv(V, l), nullptr);
+        for (int l = sr_lo; l <= t; ++l) {
+          if (two && l == M - 1) continue;  // rebuilt by the finest passes
+          if (two && l == M) seg2_launch(true);
+          else seg_launch(l, true, lv(V, l - 1), nullptr, l == M ? u_out : lv(V, l), nullptr);
+        }
         if (functionals && t == M) {
           ProfScope ps("k_functionals", (double)P.S * 16.0 + 16.0, st);
           hipLaunchKernelGGL(k_functionals, dim3(1), dim3(1024), 0, st, Uh, (int64_t)P.S,
@@ -517,7 +584,9 @@ fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_lef
     (void)hipFuncSetAttribute((const void*)k_coarse_core, hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024);
     for (const void* k : {(const void*)k_sr_down<kSegRun, false>, (const void*)k_sr_up<kSegRun, false>,
-                          (const void*)k_sr_down<kSegRun, true>, (const void*)k_sr_up<kSegRun, true>})
+                          (const void*)k_sr_down<kSegRun, true>, (const void*)k_sr_up<kSegRun, true>,
+                          (const void*)k_sr2<kSegRun, false, false>, (const void*)k_sr2<kSegRun, false, true>,
+                          (const void*)k_sr2<kSegRun, true, false>, (const void*)k_sr2<kSegRun, true, true>})
       (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     (void)hipGetLastError();
   });

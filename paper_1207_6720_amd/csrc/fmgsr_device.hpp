@@ -260,6 +260,10 @@ __device__ __forceinline__ void store_run(double* st, const double (&v)[K], int6
   __syncthreads();
 }
 
+template <int K>
+__device__ __forceinline__ void interp_from_e(double (&u)[K], const double (&e)[K / 2 + 4],
+                                              int64_t J0, int64_t nc, double gL, double gR);
+
 // Pi of the coarse level into the runs.  The coarse cells under the run,
 // c[0..K/2) = J0..J0+K/2-1, arrive as one coalesced load; the two coarse
 // values on each side come from the neighbouring threads (window-edge
@@ -286,6 +290,16 @@ __device__ __forceinline__ void interp_from_run(double (&u)[K], const double (&c
   for (int p = 0; p < K / 2; ++p) e[p + 2] = c[p];
   e[K / 2 + 2] = r0;
   e[K / 2 + 3] = r1;
+  interp_from_e<K>(u, e, J0, nc, gL, gR);
+}
+
+// Pi of the coarse values e[m] = cell J0 - 2 + m (m < K/2 + 4) into the run
+// of fine cells 2 J0 .. 2 J0 + K - 1 of a level with 2 nc cells.  Values of
+// e outside [0, nc) are never read (Dirichlet reflections instead, nested
+// for a one-cell level); fine cells outside the level become 0.
+template <int K>
+__device__ __forceinline__ void interp_from_e(double (&u)[K], const double (&e)[K / 2 + 4],
+                                              int64_t J0, int64_t nc, double gL, double gR) {
 #pragma unroll
   for (int p = 0; p < K / 2; ++p) {
     const int64_t J = J0 + p;

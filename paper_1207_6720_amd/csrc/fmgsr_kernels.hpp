@@ -725,6 +725,144 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two unstored SR levels (M and M-1): the finest segment passes rebuild the
+// level-(M-1) iterate they need from V^{M-2} instead of reading it.
+//
+// V^{M-1} is, per level-(M-1) segment j, the compatible relaxation of
+// Pi V^{M-2} on j's patch (Eq. 5, Fig. 5).  A level-M segment i needs it on
+// the coarse image of its window plus Pi's reach: the core of level-(M-1)
+// segment i and pad/2 + 2 cells on each side, which belong to segments
+// i-R .. i+R (R = 1 unless the cores are tiny).  The workgroup holds a
+// level-(M-1) window of s/2 + 2 p1 cells around that core and runs the
+// relaxation 2R + 1 times on it, once with each of those segments' patches
+// (exterior frozen at Pi V^{M-2}), keeping each run's result in that
+// segment's zone.  A relaxation sweep reaches 3 cells per iteration
+// (Kaczmarz pairs and a red-black sweep), so p1 >= pad/2 + 2 + 3 nu2 + 2
+// keeps every kept cell exact; the window edges' stale cells are never read.
+// ---------------------------------------------------------------------------
+struct Seg2Args {
+  int64_t n;             // level-M cells
+  double gL, gR;
+  int nu1, nu2;          // level-M pre-sweeps (down); CR iterations
+  int64_t s;             // level-M core cells per segment (level M-1: s / 2)
+  int64_t S;             // segments
+  int R;                 // level-(M-1) segments needed on each side
+  int64_t buffer;        // buffer cells per side on both levels
+  int64_t pad;           // level-M window offset left of the core
+  int win;               // level-M window cells, s + 2 pad
+  int64_t p1;            // level-(M-1) window offset left of the core (even)
+  int win1;              // level-(M-1) window cells, s / 2 + 2 p1
+  const double* v2;      // V^{M-2} [n/4]
+  const double* f1;      // forcing of level M-1 [n/2]
+  const double* f;       // fine right-hand side [n]
+  double* out;           // down: I^ of the smoothed level-M cores [n/2];
+                         // up: u_out [n] or nullptr
+  double* part;          // up: per-segment (sum u, sum u^2), or nullptr
+};
+
+// One CR iteration pass count nu on a run: nu x [Kaczmarz projection of the
+// pairs inside [lo, hi) onto c (Eq. 8), red-black sweep on [lo, hi)].
+template <int K, bool F32>
+__device__ __forceinline__ void cr_run(double (&u)[K], const double (&f)[K],
+                                       const double (&c)[K / 2], int64_t g0, int nu, int64_t lo,
+                                       int64_t hi, int64_t n, double gL, double gR, Xch& x) {
+  const double h2 = 1.0 / ((double)n * (double)n);
+  const double gL2 = 2.0 * gL, gR2 = 2.0 * gR;
+  const double bdiv = (n == 1) ? 4.0 : 3.0;
+  const RunBounds rb = run_bounds(g0, K, lo, hi, n);
+  for (int it = 0; it < nu; ++it) {
+#pragma unroll
+    for (int p = 0; p < K / 2; ++p) {
+      if (2 * p >= rb.jlo && 2 * p + 1 < rb.jhi) {  // both children in the patch
+        const double r = c[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
+        u[2 * p] = u[2 * p] + r;
+        u[2 * p + 1] = u[2 * p + 1] + r;
+      }
+    }
+    if constexpr (F32) {
+      cf_sweeps<K>(u, f, g0, 1, lo, hi, n, gL, gR, x);
+    } else {
+      rb_half<K, 0>(u, f, rb, h2, gL2, gR2, bdiv, x);
+      rb_half<K, 1>(u, f, rb, h2, gL2, gR2, bdiv, x);
+    }
+  }
+}
+
+template <int K, bool F32, bool UP>
+__global__ __launch_bounds__(kSegMaxThreads) void k_sr2(Seg2Args a) {
+  constexpr int K1 = K / 2;  // level-(M-1) cells per thread
+  extern __shared__ double sm[];
+  const int W = blockDim.x;
+  double* st = sm;                   // W (K+1)
+  Xch x{sm + W * (K + 1), 0};        // 4 W
+  const int64_t n = a.n, n1 = n >> 1, n2 = n >> 2;
+  const int64_t seg = blockIdx.x;
+  const int64_t s1 = a.s >> 1;
+  // ---- level M-1: V^{M-1} on [w1lo, w1lo + K1 W) ----
+  const int64_t w1lo = seg * s1 - a.p1;
+  const int64_t g1 = w1lo + (int64_t)threadIdx.x * K1;
+  double F1[K1], c2[K1 / 2], u0[K1], v1[K1];
+  load_run<K1>(st, F1, w1lo, a.win1, n1, [&](int64_t g) { return a.f1[g]; });
+  load_run<K1 / 2>(st, c2, w1lo >> 1, a.win1 / 2 + 2, n2, [&](int64_t J) { return a.v2[J]; });
+  interp_from_run<K1>(u0, c2, g1, n1, a.v2, a.gL, a.gR, x);
+#pragma unroll
+  for (int j = 0; j < K1; ++j) v1[j] = u0[j];
+  for (int r = -a.R; r <= a.R; ++r) {
+    const int64_t sj = seg + r;  // uniform per workgroup
+    if (sj < 0 || sj >= a.S) continue;
+    double u[K1];
+#pragma unroll
+    for (int j = 0; j < K1; ++j) u[j] = u0[j];
+    const int64_t lo = (sj * s1 - a.buffer > 0) ? sj * s1 - a.buffer : 0;
+    const int64_t hi = ((sj + 1) * s1 + a.buffer < n1) ? (sj + 1) * s1 + a.buffer : n1;
+    cr_run<K1, F32>(u, F1, c2, g1, a.nu2, lo, hi, n1, a.gL, a.gR, x);
+    // this run's zone: its core, extended outwards for the outermost runs
+    const int64_t zlo = (r == -a.R) ? INT64_MIN : sj * s1;
+    const int64_t zhi = (r == a.R) ? INT64_MAX : (sj + 1) * s1;
+#pragma unroll
+    for (int j = 0; j < K1; ++j)
+      if (g1 + j >= zlo && g1 + j < zhi) v1[j] = u[j];
+  }
+  // ---- level M: Pi V^{M-1} on the segment window ----
+  run_to_stage<K1>(st, v1);
+  __syncthreads();
+  const int64_t core_lo = seg * a.s, core_hi = core_lo + a.s;
+  const int64_t wlo = core_lo - a.pad;
+  const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
+  const int64_t J0 = g0 >> 1;
+  double e[K / 2 + 4];
+#pragma unroll
+  for (int m = 0; m < K / 2 + 4; ++m) {
+    int64_t idx = J0 - 2 + m - w1lo;  // window-local level-(M-1) cell
+    idx = idx < 0 ? 0 : (idx >= (int64_t)K1 * W ? (int64_t)K1 * W - 1 : idx);
+    e[m] = st[sidx<K1>((int)idx)];
+  }
+  __syncthreads();
+  double u[K], f[K], c[K / 2];
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) c[p] = e[p + 2];
+  interp_from_e<K>(u, e, J0, n1, a.gL, a.gR);
+  load_run<K>(st, f, wlo, a.win, n, [&](int64_t g) { return a.f[g]; });
+  const int64_t lo = (core_lo - a.buffer > 0) ? core_lo - a.buffer : 0;
+  const int64_t hi = (core_hi + a.buffer < n) ? core_hi + a.buffer : n;
+  if constexpr (!UP) {
+    smooth_general<K, F32>(u, f, g0, a.nu1, lo, hi, n, a.gL, a.gR, x);
+    double uc[K / 2];
+#pragma unroll
+    for (int p = 0; p < K / 2; ++p) uc[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
+    store_run<K / 2>(st, uc, wlo >> 1, core_lo >> 1, core_hi >> 1, a.out);
+  } else {
+    cr_run<K, F32>(u, f, c, g0, a.nu2, lo, hi, n, a.gL, a.gR, x);
+    if (a.out) store_run<K>(st, u, wlo, core_lo, core_hi < n ? core_hi : n, a.out);
+    if (a.part) {
+      const int64_t c0 = core_lo - g0, c1 = (core_hi < n ? core_hi : n) - g0;
+      segment_sums<K>(u, (int)(c0 < 0 ? 0 : (c0 > K ? K : c0)),
+                      (int)(c1 < 0 ? 0 : (c1 > K ? K : c1)), st, a.part);
+    }
+  }
+}
+
 // Functionals of the fine solution from the per-segment sums (fixed order:
 // each thread walks a strided set of segments in order, then the shuffle
 // tree and the wavefronts in order): out[0] = h sum u, out[1] = h sum u^2.
