@@ -789,6 +789,103 @@ __device__ __forceinline__ void cr_run(double (&u)[K], const double (&f)[K],
   }
 }
 
+// Up pass on interior windows: every level-(M-1) load in flight at once,
+// one exchange per sweep.  (The down pass keeps the general code: there the
+// one-exchange sweeps' extra registers cost half the resident workgroups,
+// more than they save; measured.)
+template <int K, bool F32>
+__device__ void sr2_up_interior(const Seg2Args& a, double* st, Xch& x) {
+  constexpr int K1 = K / 2;
+  const int W = blockDim.x;
+  const int64_t n = a.n, n1 = n >> 1;
+  const int64_t seg = blockIdx.x;
+  const int64_t s1 = a.s >> 1;
+  const int64_t w1lo = seg * s1 - a.p1;
+  const int64_t g1 = w1lo + (int64_t)threadIdx.x * K1;
+  const int64_t core_lo = seg * a.s, core_hi = core_lo + a.s;
+  const int64_t wlo = core_lo - a.pad;
+  const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
+  const int64_t J0 = g0 >> 1;
+  const int64_t lo = core_lo - a.buffer, hi = core_hi + a.buffer;  // inside the level
+  const double* cb = a.v2 + (w1lo >> 1);
+  double tF[K1], tc[K1 / 2];
+  issue_loads<K1, false>(tF, a.f1 + w1lo, a.win1);
+  issue_loads<K1 / 2, false>(tc, cb, a.win1 / 2 + 2);
+  double F1[K1], c2[K1 / 2], u0[K1], v1[K1];
+  stage_tmp<K1, false>(st, tF, F1, a.win1);
+  stage_tmp<K1 / 2, false>(st, tc, c2, a.win1 / 2 + 2);
+  interp_fast<K1>(u0, c2, cb + threadIdx.x * (K1 / 2), x);
+  half_scaled<K1>(F1, F1, n1);
+  Xch4 x4{st, 0};  // the stage is idle during the sweeps (8 W <= W (K + 1) doubles)
+#pragma unroll
+  for (int j = 0; j < K1; ++j) v1[j] = u0[j];
+  for (int r = -a.R; r <= a.R; ++r) {
+    const int64_t sj = seg + r;
+    if (sj < 0 || sj >= a.S) continue;
+    double u[K1];
+#pragma unroll
+    for (int j = 0; j < K1; ++j) u[j] = u0[j];
+    const int64_t plo = (sj * s1 - a.buffer > 0) ? sj * s1 - a.buffer : 0;
+    const int64_t phi = ((sj + 1) * s1 + a.buffer < n1) ? (sj + 1) * s1 + a.buffer : n1;
+    const RunBounds rb = run_bounds(g1, K1, plo, phi, n1);
+    const bool nb_upd = g1 + K1 >= plo && g1 + K1 < phi;
+    for (int it = 0; it < a.nu2; ++it) {
+#pragma unroll
+      for (int p = 0; p < K1 / 2; ++p) {
+        if (2 * p >= rb.jlo && 2 * p + 1 < rb.jhi) {
+          const double d = c2[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
+          u[2 * p] = u[2 * p] + d;
+          u[2 * p + 1] = u[2 * p + 1] + d;
+        }
+      }
+      smooth_masked<K1, F32>(u, F1, 1, rb.jlo, rb.jhi, nb_upd, x, x4);
+    }
+    const int64_t zlo = (r == -a.R) ? INT64_MIN : sj * s1;
+    const int64_t zhi = (r == a.R) ? INT64_MAX : (sj + 1) * s1;
+#pragma unroll
+    for (int j = 0; j < K1; ++j)
+      if (g1 + j >= zlo && g1 + j < zhi) v1[j] = u[j];
+  }
+  double tf[K];  // in flight while V^{M-1} goes through the stage
+  issue_loads<K, false>(tf, a.f + wlo, a.win);
+  __syncthreads();  // last exchange through the stage read
+  run_to_stage<K1>(st, v1);
+  __syncthreads();
+  double e[K / 2 + 4];
+#pragma unroll
+  for (int m = 0; m < K / 2 + 4; ++m) {
+    int64_t idx = J0 - 2 + m - w1lo;
+    idx = idx < 0 ? 0 : (idx >= (int64_t)K1 * W ? (int64_t)K1 * W - 1 : idx);
+    e[m] = st[sidx<K1>((int)idx)];
+  }
+  __syncthreads();
+  double u[K], f[K];
+  stage_tmp<K, false>(st, tf, f, a.win);
+  interp_from_e<K>(u, e, J0, n1, a.gL, a.gR);
+  half_scaled<K>(f, f, n);
+  const RunBounds rb = run_bounds(g0, K, lo, hi, n);
+  const bool nb_upd = g0 + K >= lo && g0 + K < hi;
+  {
+    for (int it = 0; it < a.nu2; ++it) {
+#pragma unroll
+      for (int p = 0; p < K / 2; ++p) {
+        if (2 * p >= rb.jlo && 2 * p + 1 < rb.jhi) {
+          const double d = e[p + 2] - (u[2 * p] + u[2 * p + 1]) * 0.5;
+          u[2 * p] = u[2 * p] + d;
+          u[2 * p + 1] = u[2 * p + 1] + d;
+        }
+      }
+      smooth_masked<K, F32>(u, f, 1, rb.jlo, rb.jhi, nb_upd, x, x4);
+    }
+    __syncthreads();
+    if (a.out) store_run_fast<K>(st, u, a.out + wlo, (int)a.pad, (int)(a.pad + a.s));
+    if (a.part) {
+      const int e0 = (int)threadIdx.x * K;
+      segment_sums<K>(u, (int)a.pad - e0, (int)(a.pad + a.s) - e0, st, a.part);
+    }
+  }
+}
+
 template <int K, bool F32, bool UP>
 __global__ __launch_bounds__(kSegMaxThreads) void k_sr2(Seg2Args a) {
   constexpr int K1 = K / 2;  // level-(M-1) cells per thread
@@ -799,6 +896,14 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr2(Seg2Args a) {
   const int64_t n = a.n, n1 = n >> 1, n2 = n >> 2;
   const int64_t seg = blockIdx.x;
   const int64_t s1 = a.s >> 1;
+  if constexpr (UP) {
+    const int64_t wlo_m = seg * a.s - a.pad;
+    if (window_interior(seg * s1 - a.p1, (int64_t)W * K1, n1) &&
+        window_interior(wlo_m, (int64_t)W * K, n)) {
+      sr2_up_interior<K, F32>(a, st, x);
+      return;
+    }
+  }
   // ---- level M-1: V^{M-1} on [w1lo, w1lo + K1 W) ----
   const int64_t w1lo = seg * s1 - a.p1;
   const int64_t g1 = w1lo + (int64_t)threadIdx.x * K1;
