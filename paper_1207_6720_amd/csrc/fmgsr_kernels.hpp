@@ -1051,35 +1051,41 @@ __global__ __launch_bounds__(kCoreThreads) void k_coarse_core(CoreArgs a) {
   double* PA = E + esz;           // parallel cyclic reduction, two buffers
   const double gL = a.gL, gR = a.gR, gL2 = 2.0 * gL, gR2 = 2.0 * gR;
   const int nC = n0 << C;
-  // inputs: all global loads of a level are issued before any is consumed
-#pragma unroll 1
-  for (int l = 0; l <= C; ++l) {
-    const int nl = n0 << l;
-    const double* Fl = (l == C && a.mode == 1) ? a.rhs_top : a.F[l];
-    double v[kCoreMaxCells / kCoreThreads];
+  // inputs: every global load of the kernel is issued before any is
+  // consumed (one HBM round trip instead of one per level).  The level stack
+  // in LDS is the flattened index q of (level l, cell i), q = lvl_off(l) + i;
+  // each lane finds its level from q and its pointer in a small LDS table.
+  __shared__ const double* lp[12];
+  if (tid <= C) lp[tid] = (tid == C && a.mode == 1) ? a.rhs_top : a.F[tid];
+  __syncthreads();
+  constexpr int kQ = (int)(2 * kCoreMaxCells / kCoreThreads);  // ntot < 2 kCoreMaxCells
+  constexpr int kV = (int)(kCoreMaxCells / kCoreThreads);
+  double vq[kQ], vs[kV];
 #pragma unroll
-    for (int k = 0; k < (int)(kCoreMaxCells / kCoreThreads); ++k) {
-      const int i = tid + k * T;
-      v[k] = Fl[i < nl ? i : nl - 1];
-    }
-#pragma unroll
-    for (int k = 0; k < (int)(kCoreMaxCells / kCoreThreads); ++k) {
-      const int i = tid + k * T;
-      if (i < nl) Q[lvl_off(n0, l) + i] = v[k];
-    }
+  for (int k = 0; k < kQ; ++k) {
+    const int q = tid + k * T;
+    const int qq = q < ntot ? q : 0;
+    const int l = 31 - __clz(qq / n0 + 1);
+    vq[k] = lp[l][qq - lvl_off(n0, l)];
   }
   if (a.mode == 1) {
-    double v[kCoreMaxCells / kCoreThreads];
 #pragma unroll
-    for (int k = 0; k < (int)(kCoreMaxCells / kCoreThreads); ++k) {
+    for (int k = 0; k < kV; ++k) {
       int i = tid + k * T;
       i = i < nC ? i : nC - 1;
-      v[k] = (a.src_kind == kSrcRestrict) ? (a.src[2 * i] + a.src[2 * i + 1]) * 0.5 : a.src[i];
+      vs[k] = (a.src_kind == kSrcRestrict) ? (a.src[2 * i] + a.src[2 * i + 1]) * 0.5 : a.src[i];
     }
+  }
 #pragma unroll
-    for (int k = 0; k < (int)(kCoreMaxCells / kCoreThreads); ++k) {
+  for (int k = 0; k < kQ; ++k) {
+    const int q = tid + k * T;
+    if (q < ntot) Q[q] = vq[k];
+  }
+  if (a.mode == 1) {
+#pragma unroll
+    for (int k = 0; k < kV; ++k) {
       const int i = tid + k * T;
-      if (i < nC) U[lvl_off(n0, C) + i] = v[k];
+      if (i < nC) U[lvl_off(n0, C) + i] = vs[k];
     }
   }
   __syncthreads();
