@@ -113,3 +113,16 @@ def test_workspace_sizes():
     assert F.workspace_bytes(n, 21, tau="literal") >= split + hier
     assert F.workspace_bytes(n, 21, sr_levels=0) >= 3 * hier + n * 8
     assert F.workspace_bytes(1000, 11) == 0
+
+
+def test_two_sr_levels_store_neither_finest_level():
+    """With two or more SR levels, level M-1 keeps no U or V array: the
+    workspace shrinks by V^{M-1} (n/2 cells) and by U^{M-1} less the n/4 cells
+    that hold I^ of level M-1; more SR levels store the same."""
+    for n, levels in ((1 << 20, 21), (5 << 16, 17), (1 << 28, 29)):
+        one = F.workspace_bytes(n, levels, sr_levels=1)
+        two = F.workspace_bytes(n, levels, sr_levels=2)
+        three = F.workspace_bytes(n, levels, sr_levels=3)
+        saved = (n // 2 + n // 2 - n // 4) * 8
+        assert abs((one - two) - saved) <= 3 * 256, (n, one - two, saved)
+        assert three == two
