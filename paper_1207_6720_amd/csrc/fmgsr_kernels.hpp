@@ -1021,8 +1021,15 @@ struct CoreArgs {
 
 __device__ __forceinline__ int lvl_off(int n0, int l) { return n0 * ((1 << l) - 1); }
 
-// One red-black sweep of a level (n cells) in LDS.
-__device__ __forceinline__ void core_rb(double* u, const double* q, int n, double gL2, double gR2) {
+// One red-black sweep of a level (n cells) in LDS.  A thread owns the
+// pairs (2J, 2J+1), J = tid + k T, in both colours, so at its black update
+// it holds the pair's final values and can also produce, in the same phase,
+//   rc:  I^ of the level (the next coarser level's start, n/2 cells), and
+//   e:   the correction e = u - I^ ufine of this level (ufine: the finer
+//        level's pre-smoothed iterate), read by the next finer level.
+__device__ __forceinline__ void core_rb(double* u, const double* q, int n, double gL2, double gR2,
+                                        double* rc = nullptr, double* e = nullptr,
+                                        const double* ufine = nullptr) {
   const double h2 = 1.0 / ((double)n * (double)n);
   const double bdiv = (n == 1) ? 4.0 : 3.0;
 #pragma unroll 1
@@ -1032,7 +1039,15 @@ __device__ __forceinline__ void core_rb(double* u, const double* q, int n, doubl
       double l = (i > 0) ? u[i - 1] : gL2;
       double r = (i < n - 1) ? u[i + 1] : gR2;
       const double num = q[i] * h2 + (l + r);
-      u[i] = (i > 0 && i < n - 1) ? num * 0.5 : num / bdiv;
+      const double v = (i > 0 && i < n - 1) ? num * 0.5 : num / bdiv;
+      u[i] = v;
+      if (colour == 1) {  // i = 2J + 1; l is the pair's red cell u[2J]
+        if (rc) rc[i >> 1] = (l + v) * 0.5;
+        if (e) {
+          e[i - 1] = l - (ufine[2 * (i - 1)] + ufine[2 * (i - 1) + 1]) * 0.5;
+          e[i] = v - (ufine[2 * i] + ufine[2 * i + 1]) * 0.5;
+        }
+      }
     }
     __syncthreads();
   }
@@ -1115,10 +1130,14 @@ __global__ __launch_bounds__(kCoreThreads) void k_coarse_core(CoreArgs a) {
       const int nm = n0 << m, nc = nm >> 1;
       double* uf = U + lvl_off(n0, m);
       double* qf = Q + lvl_off(n0, m);
-#pragma unroll 1
-      for (int s = 0; s < a.nu1; ++s) core_rb(uf, qf, nm, gL2, gR2);
       double* uc = U + lvl_off(n0, m - 1);
       double* qc = Q + lvl_off(n0, m - 1);
+      // split tau: the last sweep also restricts (one phase less)
+      const bool fused = !a.literal && a.nu1 > 0;
+#pragma unroll 1
+      for (int s = 0; s < a.nu1; ++s)
+        core_rb(uf, qf, nm, gL2, gR2, (fused && s == a.nu1 - 1) ? uc : nullptr);
+      if (fused) continue;
       const double w = (double)nm * (double)nm, wc = (double)nc * (double)nc;
 #pragma unroll 1
       for (int J = tid; J < nc; J += T) {
@@ -1217,15 +1236,19 @@ __global__ __launch_bounds__(kCoreThreads) void k_coarse_core(CoreArgs a) {
       }
       __syncthreads();
     }
-    // up leg
+    // up leg; e = u^m - I^ u^{m+1} comes from level m's last sweep when it
+    // has one, else from its own phase
+    bool have_e = false;
 #pragma unroll 1
     for (int m = 0; m < t; ++m) {
       const int nc = n0 << m, nf = nc << 1;
       const double* uc = U + lvl_off(n0, m);
       double* uf = U + lvl_off(n0, m + 1);
+      if (!have_e) {
 #pragma unroll 1
-      for (int J = tid; J < nc; J += T) E[J] = uc[J] - (uf[2 * J] + uf[2 * J + 1]) * 0.5;
-      __syncthreads();
+        for (int J = tid; J < nc; J += T) E[J] = uc[J] - (uf[2 * J] + uf[2 * J + 1]) * 0.5;
+        __syncthreads();
+      }
 #pragma unroll 1
       for (int J = tid; J < nc; J += T) {
         const double eJ = E[J];
@@ -1235,8 +1258,13 @@ __global__ __launch_bounds__(kCoreThreads) void k_coarse_core(CoreArgs a) {
         uf[2 * J + 1] = uf[2 * J + 1] + (3.0 * eJ + ep) * 0.25;
       }
       __syncthreads();
+      // the last sweep also forms the next level's e (level m+1 against m+2)
+      const bool next_e = (m + 1 < t) && a.nu2 > 0;
 #pragma unroll 1
-      for (int s = 0; s < a.nu2; ++s) core_rb(uf, Q + lvl_off(n0, m + 1), nf, gL2, gR2);
+      for (int s = 0; s < a.nu2; ++s)
+        core_rb(uf, Q + lvl_off(n0, m + 1), nf, gL2, gR2, nullptr,
+                (next_e && s == a.nu2 - 1) ? E : nullptr, U + lvl_off(n0, m + 2));
+      have_e = next_e;
     }
   }
 #pragma unroll 1
