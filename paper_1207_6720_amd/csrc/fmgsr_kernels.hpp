@@ -1001,7 +1001,7 @@ __global__ __launch_bounds__(1024) void k_functionals(const double* __restrict__
 // call site per phase) so that each phase issues few instructions.
 // ---------------------------------------------------------------------------
 
-constexpr int kCoreThreads = 256;
+constexpr int kCoreThreads = 512;
 constexpr int64_t kCoreMaxCells = 2048;
 constexpr int64_t kMaxN0 = 1024;
 
