@@ -1053,6 +1053,102 @@ __device__ __forceinline__ void core_rb(double* u, const double* q, int n, doubl
   }
 }
 
+// Levels of at most 64 cells run on the first wavefront alone, one cell per
+// lane, with neighbours from DPP wavefront shifts (no LDS round trip and no
+// workgroup barrier per half-sweep).  Same expression trees as the LDS code.
+__device__ __forceinline__ double dpp_shift(double v, bool from_left) {
+  // wave_shr:1 (lane i takes lane i-1) or wave_shl:1 (lane i takes lane i+1);
+  // lanes without a source get 0
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  int rlo, rhi;
+  if (from_left) {
+    rlo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xF, 0xF, false);
+    rhi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xF, 0xF, false);
+  } else {
+    rlo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xF, 0xF, false);
+    rhi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xF, 0xF, false);
+  }
+  return __hiloint2double(rhi, rlo);
+}
+
+// nu red-black sweeps of a level of n <= 64 cells held one per lane.
+__device__ __forceinline__ double wave_rb(double u, double q, int n, int nu, double gL2,
+                                          double gR2) {
+  const int i = threadIdx.x;
+  const double h2 = 1.0 / ((double)n * (double)n);
+  const double bdiv = (n == 1) ? 4.0 : 3.0;
+#pragma unroll 1
+  for (int s = 0; s < nu; ++s) {
+#pragma unroll
+    for (int colour = 0; colour < 2; ++colour) {
+      const double lv = dpp_shift(u, true), rv = dpp_shift(u, false);
+      if (i < n && (i & 1) == colour) {
+        const double l = (i > 0) ? lv : gL2;
+        const double r = (i < n - 1) ? rv : gR2;
+        const double num = q * h2 + (l + r);
+        u = (i > 0 && i < n - 1) ? num * 0.5 : num / bdiv;
+      }
+    }
+  }
+  return u;
+}
+
+// Down leg of a V-cycle on levels top..1 (top <= the last level of at most
+// 64 cells), first wavefront only: sweeps, then I^ into the next level.  The
+// pre-smoothed iterates go to U (the up leg needs them); level 0 gets I^ of
+// level 1 as the solve's start.  Split tau: Q is the forcing.
+__device__ void wave_down(double* U, const double* Q, int n0, int top, int nu1, double gL2,
+                          double gR2) {
+  const int i = threadIdx.x;
+  int n = n0 << top;
+  double u = (i < n) ? U[lvl_off(n0, top) + i] : 0.0;
+#pragma unroll 1
+  for (int m = top; m >= 1; --m, n >>= 1) {
+    const double q = (i < n) ? Q[lvl_off(n0, m) + i] : 0.0;
+    u = wave_rb(u, q, n, nu1, gL2, gR2);
+    if (i < n) U[lvl_off(n0, m) + i] = u;
+    const int j0 = (2 * i < n) ? 2 * i : 0, j1 = (2 * i + 1 < n) ? 2 * i + 1 : 0;
+    const double a0 = __shfl(u, j0), a1 = __shfl(u, j1);
+    u = (i < n / 2) ? (a0 + a1) * 0.5 : 0.0;
+  }
+  if (i < n0) U[i] = u;
+}
+
+// Up leg on levels 1..top (first wavefront): correction from the level
+// below (Eq. 4, e = u^{m} - I^ u^{m+1}_pre), then nu2 sweeps; level top's
+// result goes to U.
+__device__ void wave_up(double* U, const double* Q, int n0, int top, int nu2, double gL2,
+                        double gR2) {
+  const int i = threadIdx.x;
+  int nc = n0;
+  double uc = (i < nc) ? U[i] : 0.0;
+#pragma unroll 1
+  for (int m = 0; m < top; ++m, nc <<= 1) {
+    const int nf = nc << 1;
+    const double up = (i < nf) ? U[lvl_off(n0, m + 1) + i] : 0.0;  // pre-smoothed
+    const int j0 = (2 * i < nf) ? 2 * i : 0, j1 = (2 * i + 1 < nf) ? 2 * i + 1 : 0;
+    const double p0 = __shfl(up, j0), p1 = __shfl(up, j1);
+    const double e = (i < nc) ? uc - (p0 + p1) * 0.5 : 0.0;
+    const int J = i >> 1;
+    const double eJ = __shfl(e, J < nc ? J : 0);
+    const double eL = __shfl(e, (J > 0 && J - 1 < nc) ? J - 1 : 0);
+    const double eR = __shfl(e, (J + 1 < nc) ? J + 1 : 0);
+    double u = up;
+    if (i < nf) {
+      if ((i & 1) == 0) {
+        const double em = (J > 0) ? eL : -eJ;
+        u = up + (3.0 * eJ + em) * 0.25;
+      } else {
+        const double ep = (J < nc - 1) ? eR : -eJ;
+        u = up + (3.0 * eJ + ep) * 0.25;
+      }
+    }
+    const double q = (i < nf) ? Q[lvl_off(n0, m + 1) + i] : 0.0;
+    uc = wave_rb(u, q, nf, nu2, gL2, gR2);
+  }
+  if (i < (n0 << top)) U[lvl_off(n0, top) + i] = uc;
+}
+
 __global__ __launch_bounds__(kCoreThreads) void k_coarse_core(CoreArgs a) {
   extern __shared__ double sm[];
   const int C = a.top;
@@ -1066,6 +1162,8 @@ __global__ __launch_bounds__(kCoreThreads) void k_coarse_core(CoreArgs a) {
   double* PA = E + esz;           // parallel cyclic reduction, two buffers
   const double gL = a.gL, gR = a.gR, gL2 = 2.0 * gL, gR2 = 2.0 * gR;
   const int nC = n0 << C;
+  int lw = -1;  // last level of at most 64 cells (first-wavefront levels)
+  while (lw + 1 <= C && (n0 << (lw + 1)) <= 64) ++lw;
   // inputs: every global load of the kernel is issued before any is
   // consumed (one HBM round trip instead of one per level).  The level stack
   // in LDS is the flattened index q of (level l, cell i), q = lvl_off(l) + i;
@@ -1124,9 +1222,11 @@ __global__ __launch_bounds__(kCoreThreads) void k_coarse_core(CoreArgs a) {
       }
       __syncthreads();
     }
-    // down leg
+    // down leg: levels above 64 cells on the whole workgroup, the rest on
+    // the first wavefront (split tau)
+    const int wtop = (lw >= 1 && !a.literal) ? min(t, lw) : 0;
 #pragma unroll 1
-    for (int m = t; m >= 1; --m) {
+    for (int m = t; m >= wtop + 1 && m >= 1; --m) {
       const int nm = n0 << m, nc = nm >> 1;
       double* uf = U + lvl_off(n0, m);
       double* qf = Q + lvl_off(n0, m);
@@ -1158,6 +1258,10 @@ __global__ __launch_bounds__(kCoreThreads) void k_coarse_core(CoreArgs a) {
         }
         uc[J] = u0;
       }
+      __syncthreads();
+    }
+    if (wtop >= 1) {
+      if (tid < 64) wave_down(U, Q, n0, wtop, a.nu1, gL2, gR2);
       __syncthreads();
     }
     // exact solve of level 0: one-cell closed form, else parallel cyclic
@@ -1236,11 +1340,15 @@ __global__ __launch_bounds__(kCoreThreads) void k_coarse_core(CoreArgs a) {
       }
       __syncthreads();
     }
+    if (wtop >= 1) {
+      if (tid < 64) wave_up(U, Q, n0, wtop, a.nu2, gL2, gR2);
+      __syncthreads();
+    }
     // up leg; e = u^m - I^ u^{m+1} comes from level m's last sweep when it
     // has one, else from its own phase
     bool have_e = false;
 #pragma unroll 1
-    for (int m = 0; m < t; ++m) {
+    for (int m = wtop; m < t; ++m) {
       const int nc = n0 << m, nf = nc << 1;
       const double* uc = U + lvl_off(n0, m);
       double* uf = U + lvl_off(n0, m + 1);
