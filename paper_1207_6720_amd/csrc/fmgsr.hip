@@ -219,7 +219,10 @@ fmgsr_status plan_segments(int64_t n_segments, int32_t buffer, Plan* p) {
     // level-(M-1) margin: pad/2 + 2 cells for Pi's reach from the level-M
     // window, 3 per CR iteration of stale cells from the window edges, even
     p->p1 = ((pad / 2 + 3 * (int64_t)p->nu2 + 6) + 1) & ~(int64_t)1;
-    p->R = (int)((pad / 2 + 2 + s / 2 - 1) / (s / 2));
+    // b >= 2 nu2: the level-(M-1) relaxation's cores do not see the segment
+    // edges, and one run over the window serves all zones; else one run per
+    // segment the window reaches
+    p->R = (buffer >= 2 * p->nu2) ? 0 : (int)((pad / 2 + 2 + s / 2 - 1) / (s / 2));
     const int64_t cells1 = s / 2 + 2 * p->p1;
     const int64_t thr1 = std::max(thr, (cells1 + kSegRun / 2 - 1) / (kSegRun / 2));
     if (thr1 > kSegMaxThreads) return FMGSR_EINVAL;

@@ -740,6 +740,9 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
 // segment's zone.  A relaxation sweep reaches 3 cells per iteration
 // (Kaczmarz pairs and a red-black sweep), so p1 >= pad/2 + 2 + 3 nu2 + 2
 // keeps every kept cell exact; the window edges' stale cells are never read.
+// When b >= 2 nu2 the block relaxation's cores equal the unsegmented
+// relaxation bit for bit (the patch edges' influence does not reach the
+// cores), so one run over the whole window serves every zone (R = 0).
 // ---------------------------------------------------------------------------
 struct Seg2Args {
   int64_t n;             // level-M cells
@@ -747,7 +750,8 @@ struct Seg2Args {
   int nu1, nu2;          // level-M pre-sweeps (down); CR iterations
   int64_t s;             // level-M core cells per segment (level M-1: s / 2)
   int64_t S;             // segments
-  int R;                 // level-(M-1) segments needed on each side
+  int R;                 // level-(M-1) segments needed on each side; 0: one
+                         // run over the whole window (b >= 2 nu2)
   int64_t buffer;        // buffer cells per side on both levels
   int64_t pad;           // level-M window offset left of the core
   int win;               // level-M window cells, s + 2 pad
@@ -825,8 +829,9 @@ __device__ void sr2_up_interior(const Seg2Args& a, double* st, Xch& x) {
     double u[K1];
 #pragma unroll
     for (int j = 0; j < K1; ++j) u[j] = u0[j];
-    const int64_t plo = (sj * s1 - a.buffer > 0) ? sj * s1 - a.buffer : 0;
-    const int64_t phi = ((sj + 1) * s1 + a.buffer < n1) ? (sj + 1) * s1 + a.buffer : n1;
+    int64_t plo = (sj * s1 - a.buffer > 0) ? sj * s1 - a.buffer : 0;
+    int64_t phi = ((sj + 1) * s1 + a.buffer < n1) ? (sj + 1) * s1 + a.buffer : n1;
+    if (a.R == 0) { plo = w1lo; phi = w1lo + a.win1; }  // interior: inside the level
     const RunBounds rb = run_bounds(g1, K1, plo, phi, n1);
     const bool nb_upd = g1 + K1 >= plo && g1 + K1 < phi;
     for (int it = 0; it < a.nu2; ++it) {
@@ -919,8 +924,12 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr2(Seg2Args a) {
     double u[K1];
 #pragma unroll
     for (int j = 0; j < K1; ++j) u[j] = u0[j];
-    const int64_t lo = (sj * s1 - a.buffer > 0) ? sj * s1 - a.buffer : 0;
-    const int64_t hi = ((sj + 1) * s1 + a.buffer < n1) ? (sj + 1) * s1 + a.buffer : n1;
+    int64_t lo = (sj * s1 - a.buffer > 0) ? sj * s1 - a.buffer : 0;
+    int64_t hi = ((sj + 1) * s1 + a.buffer < n1) ? (sj + 1) * s1 + a.buffer : n1;
+    if (a.R == 0) {  // the whole window, clipped to the level
+      lo = w1lo > 0 ? w1lo : 0;
+      hi = (w1lo + a.win1 < n1) ? w1lo + a.win1 : n1;
+    }
     cr_run<K1, F32>(u, F1, c2, g1, a.nu2, lo, hi, n1, a.gL, a.gR, x);
     // this run's zone: its core, extended outwards for the outermost runs
     const int64_t zlo = (r == -a.R) ? INT64_MIN : sj * s1;

@@ -124,7 +124,8 @@ MULTI_SR_CASES = [
     (7 << 12, 12, 28, 3, (3, 2), 2, (0.1, 0.2), 38),     # N0 = 14
     # the unstored level M-1 is rebuilt per finest segment from the
     # relaxation of the level-(M-1) segments its window reaches
-    (1 << 12, 13, 512, 8, (2, 1), 2, (0.0, 0.0), 39),    # 4-cell cores: two segments per side
+    (1 << 12, 13, 512, 5, (2, 3), 2, (0.0, 0.0), 39),    # 4-cell cores, b < 2 nu2: two segments per side
+    (1 << 12, 13, 512, 8, (2, 1), 2, (0.0, 0.0), 40),    # b >= 2 nu2: one run per window
     (1 << 12, 13, 16, 20, (1, 4), 2, (0.3, 0.0), 41),    # four CR iterations
     (1 << 12, 13, 256, 3, (2, 3), 3, (0.0, -0.5), 42),
     (1 << 13, 14, 4, 64, (2, 1), 2, (0.0, 0.0), 43),     # widest buffer

@@ -235,6 +235,40 @@ def test_blocks_equal_global_when_buffer_covers(nu):
         assert not np.array_equal(oracle.smooth_blocks(v, F, S, 2 * nu - 2, nu), glob)
 
 
+def _cr_global(v, F, c, nu, gL, gR):
+    """Unsegmented compatible relaxation written out here: nu x [Kaczmarz
+    projection of every pair onto I^ u = c, red-black sweep]."""
+    u = v.copy()
+    for _ in range(nu):
+        r = c - (u[0::2] + u[1::2]) * 0.5
+        u[0::2] = u[0::2] + r
+        u[1::2] = u[1::2] + r
+        u = oracle.rb_sweep(u, F, gL=gL, gR=gR)
+    return u
+
+
+@pytest.mark.parametrize("nu", [1, 2, 3, 4])
+def test_compatible_relaxation_blocks_equal_global_when_buffer_covers(nu):
+    """Cores of the blocked compatible relaxation (Fig. 5) equal the
+    unsegmented one bitwise once b >= 2 nu (the GPU rebuilds an unstored
+    level with one run over a window when this holds), and differ below."""
+    rng = np.random.default_rng(100 + nu)  # own stream: leaves the shared one untouched
+    for n, S in ((256, 4), (96, 6), (64, 8)):
+        v = rng.standard_normal(n)
+        F = rng.standard_normal(n) * n * n
+        c = rng.standard_normal(n // 2)
+        glob = _cr_global(v, F, c, nu, 0.3, -0.2)
+        for b in (2 * nu, 2 * nu + 1, 2 * nu + 5):
+            out = oracle.smooth_blocks(v, F, S, b, nu, kaczmarz_c=c, gL=0.3, gR=-0.2)
+            assert np.array_equal(out, glob), (n, S, b)
+    n, S = 256, 4
+    v = rng.standard_normal(n)
+    F = rng.standard_normal(n) * n * n
+    c = rng.standard_normal(n // 2)
+    glob = _cr_global(v, F, c, nu, 0.0, 0.0)
+    assert not np.array_equal(oracle.smooth_blocks(v, F, S, 2 * nu - 1, nu, kaczmarz_c=c), glob)
+
+
 def test_blocks_order_invariant_and_local():
     n, S, b = 96, 12, 1
     v = RNG.standard_normal(n)
