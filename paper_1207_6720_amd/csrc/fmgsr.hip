@@ -276,7 +276,7 @@ struct Ctx {
     double bytes = 0.0;
     for (int i = 0; i < levels; ++i) {
       a.out[i] = (i == 0) ? top_out : lv(U, top - i);
-      bytes += (double)nl(top - i) * 8.0;  // U written
+      if (a.out[i]) bytes += (double)nl(top - i) * 8.0;  // U written
     }
     const double nb = (double)a.n * 8.0;
     bytes += nb + (src_kind == kSrcInterp ? nb * 0.5 : src_kind == kSrcRestrict ? nb * 2.0 : nb);
@@ -464,27 +464,37 @@ struct Ctx {
       // with two or more SR levels, level M-1 is never stored either: the
       // finest passes rebuild it from V^{M-2}
       const bool two = (P.nsr >= 2);
+      // One SR level with split tau and b >= 2 nu1 - 1: the block smoother's
+      // cores equal global red-black sweeps bit for bit, so the SR down pass
+      // (Pi, sweeps, I^ of the cores) is the top level of an ordinary
+      // vertical down kernel whose level-M output is simply not stored; the
+      // restricted iterate never goes through HBM.
+      const bool fused_down = sr && t == M && P.nsr == 1 && !P.literal &&
+                              P.b >= 2 * (int64_t)P.nu1 - 1 && P.d_down >= 2 && M - 1 > C;
       int top = t;  // highest stored level of this step
-      if (sr) {
+      int dtop = t;  // top of the vertical down leg
+      if (sr && !fused_down) {
         if (two && t == M) seg2_launch(false);
         else seg_launch(t, false, lv(V, t - 1), nullptr, H(t - 1), P.literal ? lv(Q, t - 1) : nullptr);
         for (int l = t - 1; l >= sr_lo; --l) seg_launch(l, false, nullptr, H(l), H(l - 1), nullptr);
-        top = sr_lo - 1;
+        top = dtop = sr_lo - 1;
+      } else if (fused_down) {
+        top = M - 1;
       }
-      // pre-smoothing leg: stored levels top..C+1
-      for (int hi = top; hi >= C + 1;) {
+      // pre-smoothing leg: levels dtop..C+1
+      for (int hi = dtop; hi >= C + 1;) {
         const int d = std::min(P.d_down, hi - C);
         int src_kind;
         const double* src;
         if (hi == t) { src_kind = kSrcInterp; src = lv(V, t - 1); }
-        else if (sr && hi == top) { src_kind = kSrcDirect; src = H(top); }
+        else if (sr && !fused_down && hi == top) { src_kind = kSrcDirect; src = H(top); }
         else { src_kind = kSrcRestrict; src = U_of(hi + 1); }
         if (P.literal && src_kind == kSrcRestrict) tau_launch(U_of(hi + 1), rhs_of(hi + 1), hi, lv(Q, hi));
-        down_launch(hi, d, src_kind, src, rhs_of(hi), U_of(hi));
+        down_launch(hi, d, src_kind, src, rhs_of(hi), (fused_down && hi == M) ? nullptr : U_of(hi));
         hi -= d;
       }
       // coarse core: V-cycle bottom from level C
-      if (sr && C == top) {
+      if (sr && !fused_down && C == top) {
         core_launch(1, kSrcDirect, H(C), rhs_of(C));
       } else {
         const double* uf = U_of(C + 1);

@@ -162,7 +162,8 @@ struct VertArgs {
   const double* rhs;     // right-hand side of the top level
   const double* coarse;  // up: post-smoothed level below the bottom level
   const double* pre[kMaxFuse];  // up: pre-smoothed iterates, index = levels below top
-  double* out[kMaxFuse];        // down: U of each level; up: out[0] = top result
+  double* out[kMaxFuse];        // down: U of each level (null: not stored);
+                                // up: out[0] = top result
 };
 
 struct TileGeom {
@@ -193,7 +194,7 @@ __device__ void down_level(const VertArgs& a, double* st, Xch& x, double (&u)[K]
                            const double (&f)[K]) {
   const TileGeom G = tile_geom(a, I, K);
   smooth_general<K, F32>(u, f, G.g0, a.nu, G.lo, G.hi, G.n, a.gL, a.gR, x);
-  store_run<K>(st, u, G.wlo, G.clo, G.chi, a.out[I]);
+  if (a.out[I]) store_run<K>(st, u, G.wlo, G.clo, G.chi, a.out[I]);  // null: SR level
   if constexpr (I + 1 < kMaxFuse && K >= 4) {
     if (I + 1 < a.levels) {
       double u1[K / 2], f1[K / 2];
@@ -223,7 +224,8 @@ __device__ void down_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4,
     if (more) fw_fast<K>(f, f1, x);
   half_scaled<K>(f, f, a.n >> I);
   smooth_fast<K, F32>(u, f, a.nu, x, x4);
-  store_run_fast<K>(st, u, a.out[I] + wlo, (int)(a.halo >> I), (int)((a.halo + a.core) >> I));
+  if (a.out[I])  // null: an SR level, never stored (uniform per launch)
+    store_run_fast<K>(st, u, a.out[I] + wlo, (int)(a.halo >> I), (int)((a.halo + a.core) >> I));
   if constexpr (I + 1 < kMaxFuse && K >= 4) {
     if (more) {
       double u1[K / 2];
