@@ -120,6 +120,16 @@ bool up_fits(int nu, int d, int64_t halo) {
   return halo >= inv;  // only the top level's core is written
 }
 
+// Up kernel whose top level is an SR level (full update Pi from the level
+// below, then nu x [Kaczmarz, sweep]): Pi reaches two coarse cells, and each
+// relaxation iteration spreads staleness by three (the pair and the sweep).
+bool sr_up_fits(int nu, int d, int64_t halo) {
+  int64_t inv = 2 + 2 * nu;
+  for (int i = d - 2; i >= 1; --i) inv = 2 * (inv + 1) + 2 * nu;
+  inv = 2 * (inv + 2) + 3 * nu;
+  return halo >= inv;
+}
+
 int fuse_depth(bool up, int nu) {
   for (int d = kMaxFuse; d > 1; --d)
     if (up ? up_fits(nu, d, kTileHalo) : down_fits(nu, d, kTileHalo)) return d;
@@ -132,6 +142,7 @@ struct Plan {
   int nu1 = 2, nu2 = 1, nsr = 1, literal = 0;
   bool f32 = false;  // FP32 relaxation (correction form) on stored and SR levels
   int d_down = 1, d_up = 1;
+  int d_srup = 0;  // levels of an up kernel topped by the SR level (0: none fit)
   int64_t S = 1, s = 0, b = 0, pad = 0;
   int seg_threads = 0;
   // sr_levels >= 2: levels M and M-1 are never stored; the finest segment
@@ -170,6 +181,8 @@ fmgsr_status make_plan(int64_t n, int32_t levels, const fmgsr_options& o, Plan* 
   p->literal = (o.tau_mode == FMGSR_TAU_LITERAL);
   p->d_down = p->literal ? 1 : fuse_depth(false, o.nu1);
   p->d_up = p->literal ? 1 : fuse_depth(true, o.nu2);
+  for (int d = kMaxFuse; d >= 2 && p->d_srup == 0; --d)
+    if (sr_up_fits(o.nu2, d, kTileHalo)) p->d_srup = d;
   // coarse core top level
   int C = 0;
   const int cmax = M - std::max(o.sr_levels, 1);  // SR levels stay above the core
@@ -288,15 +301,17 @@ struct Ctx {
   }
 
   // Up leg over levels top-levels+1..top; result of the top level to out.
+  // top_pre == nullptr: the top level is the SR level (full update + CR)
   void up_launch(int top, int levels, const double* rhs, const double* coarse,
                  const double* top_pre, double* out) {
     VertArgs a = vargs(top, levels, p->nu2);
     a.rhs = rhs;
     a.coarse = coarse;
+    a.sr_top = (top_pre == nullptr);
     double bytes = 0.0;
     for (int i = 0; i < levels; ++i) {
       a.pre[i] = (i == 0) ? top_pre : lv(U, top - i);
-      bytes += (double)nl(top - i) * 8.0;  // pre read
+      if (a.pre[i]) bytes += (double)nl(top - i) * 8.0;  // pre read
     }
     bytes += (double)a.n * 16.0 + (double)nl(top - levels) * 8.0;  // rhs, out; coarse
     a.out[0] = out;
@@ -501,15 +516,24 @@ struct Ctx {
         if (P.literal) tau_launch(uf, rhs_of(C + 1), C, lv(Q, C));
         core_launch(1, kSrcRestrict, uf, rhs_of(C));
       }
-      // post-smoothing leg: stored levels C+1..top
-      for (int lo = C + 1; lo <= top;) {
-        const int d = std::min(P.d_up, top - lo + 1);
+      // One SR level, split tau, b >= 2 nu2, no functionals: the SR up pass
+      // (Pi + compatible relaxation) equals the unsegmented one on the cores
+      // bit for bit, so it is the top level of the last vertical up kernel,
+      // which then never writes V^{M-1}.
+      const bool fused_up = fused_down && P.b >= 2 * (int64_t)P.nu2 && P.d_srup >= 2 &&
+                            !functionals && M - P.d_srup >= C;
+      const int utop = fused_up ? M - P.d_srup : top;  // last ordinary up level
+      // post-smoothing leg: stored levels C+1..utop
+      for (int lo = C + 1; lo <= utop;) {
+        const int d = std::min(P.d_up, utop - lo + 1);
         const int hi = lo + d - 1;
         double* out = (hi == top && !sr) ? ((t == M) ? u_out : lv(V, t)) : lv(V, hi);
         up_launch(hi, d, rhs_of(hi), lv(V, lo - 1), U_of(hi), out);
         lo += d;
       }
-      if (sr) {
+      if (fused_up) {
+        up_launch(M, P.d_srup, f, lv(V, M - P.d_srup), nullptr, u_out);
+      } else if (sr) {
         // full update and compatible relaxation on each SR level, upwards
         for (int l = sr_lo; l <= t; ++l) {
           if (two && l == M - 1) continue;  // rebuilt by the finest passes

@@ -162,6 +162,9 @@ struct VertArgs {
   const double* rhs;     // right-hand side of the top level
   const double* coarse;  // up: post-smoothed level below the bottom level
   const double* pre[kMaxFuse];  // up: pre-smoothed iterates, index = levels below top
+  int sr_top;            // up: the top level is an unstored SR level, rebuilt by
+                         // the full update from the level below and compatible
+                         // relaxation (pre[0] unused)
   double* out[kMaxFuse];        // down: U of each level (null: not stored);
                                 // up: out[0] = top result
 };
@@ -313,6 +316,43 @@ __device__ void up_level(const VertArgs& a, double* st, Xch& x, const double (&f
     const int64_t cwlo = G.wlo >> 1;
     load_run<K / 2>(st, c, cwlo, wcount / 2, nc, [&](int64_t J) { return a.coarse[J]; });
   }
+  if (I == 0 && a.sr_top) {
+    // SR top level (Eq. 5, Fig. 5): u = Pi c, then nu x [Kaczmarz onto
+    // I^ u = c, red-black sweep]; the window-edge neighbours' coarse values
+    // are unknown here (they only feed halo cells)
+    double l1, r0, l2, r1;
+    x.swap(c[0], c[K / 2 - 1], l1, r0);
+    x.swap(c[1], c[K / 2 - 2], l2, r1);
+    double e[K / 2 + 4];
+    e[0] = l2;
+    e[1] = l1;
+#pragma unroll
+    for (int p = 0; p < K / 2; ++p) e[p + 2] = c[p];
+    e[K / 2 + 2] = r0;
+    e[K / 2 + 3] = r1;
+    interp_from_e<K>(u, e, G.g0 >> 1, nc, a.gL, a.gR);
+    const RunBounds rb = run_bounds(G.g0, K, G.lo, G.hi, G.n);
+    const double h2 = 1.0 / ((double)G.n * (double)G.n);
+    const double gL2 = 2.0 * a.gL, gR2 = 2.0 * a.gR;
+    const double bdiv = (G.n == 1) ? 4.0 : 3.0;
+    for (int it = 0; it < a.nu; ++it) {
+#pragma unroll
+      for (int p = 0; p < K / 2; ++p) {
+        if (2 * p >= rb.jlo && 2 * p + 1 < rb.jhi) {  // both children updatable
+          const double r = c[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
+          u[2 * p] = u[2 * p] + r;
+          u[2 * p + 1] = u[2 * p + 1] + r;
+        }
+      }
+      if constexpr (F32) {
+        cf_sweeps<K>(u, f, G.g0, 1, G.lo, G.hi, G.n, a.gL, a.gR, x);
+      } else {
+        rb_half<K, 0>(u, f, rb, h2, gL2, gR2, bdiv, x);
+        rb_half<K, 1>(u, f, rb, h2, gL2, gR2, bdiv, x);
+      }
+    }
+    return;
+  }
   // correction (Eq. 4): u = pre + P(c - I^ pre)
   load_run<K>(st, u, G.wlo, wcount, G.n, [&](int64_t g) { return a.pre[I][g]; });
   double e[K / 2];
@@ -360,6 +400,34 @@ __device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4, d
     stage_tmp<K / 2, true>(st, tc, c, 0);
   }
   half_scaled<K>(f, f, a.n >> I);
+  if (I == 0 && a.sr_top) {
+    // SR top level: u = Pi c, then nu x [Kaczmarz onto I^ u = c, sweep]
+    double l1, r0, l2, r1;
+    x.swap(c[0], c[K / 2 - 1], l1, r0);
+    x.swap(c[1], c[K / 2 - 2], l2, r1);
+    double ec[K / 2 + 4];
+    ec[0] = l2;
+    ec[1] = l1;
+#pragma unroll
+    for (int p = 0; p < K / 2; ++p) ec[p + 2] = c[p];
+    ec[K / 2 + 2] = r0;
+    ec[K / 2 + 3] = r1;
+#pragma unroll
+    for (int p = 0; p < K / 2; ++p) {
+      u[2 * p] = interp_even(ec[p], ec[p + 1], ec[p + 2], ec[p + 3]);
+      u[2 * p + 1] = interp_odd(ec[p + 1], ec[p + 2], ec[p + 3], ec[p + 4]);
+    }
+    for (int it = 0; it < a.nu; ++it) {
+#pragma unroll
+      for (int p = 0; p < K / 2; ++p) {
+        const double r = c[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
+        u[2 * p] = u[2 * p] + r;
+        u[2 * p + 1] = u[2 * p + 1] + r;
+      }
+      smooth_fast<K, F32>(u, f, 1, x, x4);
+    }
+    return;
+  }
   stage_tmp<K, true>(st, tp, u, 0);
   double e[K / 2];
 #pragma unroll
@@ -392,7 +460,7 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
   if (window_interior(wlo0, wcount, a.n)) {
     double tf[K], tp[K];
     issue_loads<K, true>(tf, a.rhs + wlo0, 0);
-    issue_loads<K, true>(tp, a.pre[0] + wlo0, 0);
+    if (!a.sr_top) issue_loads<K, true>(tp, a.pre[0] + wlo0, 0);
     stage_tmp<K, true>(st, tf, f, 0);
     up_level_fast<K, 0, F32>(a, st, x, x4, f, u, tp, wlo0);
     store_run_fast<K>(st, u, a.out[0] + wlo0, (int)a.halo, (int)(a.halo + a.core));
