@@ -163,7 +163,8 @@ def main():
     kw = dict(levels=wl.levels, segments=wl.segments, buffer=wl.buffer, nu=(2, 1),
               sr_levels=args.sr_levels, tau=args.tau, precision=args.precision, **kw_out)
     ws = fmgsr.alloc_workspace(n, wl.levels, dev, nu=(2, 1), sr_levels=args.sr_levels,
-                               tau=args.tau)
+                               tau=args.tau, segments=wl.segments, buffer=wl.buffer,
+                               functionals=args.functionals_only)
     stream = torch.cuda.current_stream(dev)
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -265,7 +266,11 @@ def main():
                    "workspace_bytes_full_grid_fmg": fmgsr.workspace_bytes(n, wl.levels, sr_levels=0,
                                                                           tau=args.tau),
                    "workspace_bytes_sr": fmgsr.workspace_bytes(n, wl.levels, sr_levels=1,
-                                                               tau=args.tau)},
+                                                               tau=args.tau, segments=wl.segments,
+                                                               buffer=wl.buffer),
+                   "workspace_bytes_two_sr_levels": fmgsr.workspace_bytes(
+                       n, wl.levels, sr_levels=2, tau=args.tau, segments=wl.segments,
+                       buffer=wl.buffer)},
         "kernels": {kname: {"launches": v["launches"], "ms": round(v["total_ms"], 4),
                             "GBps": round(v["algo_bytes"] / max(v["total_ms"], 1e-9) / 1e6, 1)}
                     for kname, v in sorted(prof_all.items(), key=lambda kv: -kv[1]["total_ms"])},

@@ -122,9 +122,17 @@ typedef struct {
  * workspace. */
 void fmgsr_default_options(fmgsr_options *opt);
 
-/* Bytes of device workspace fmgsr_solve needs for these sizes and options
- * (0 if the arguments are invalid). */
+/* Bytes of device workspace fmgsr_solve needs for these sizes and options,
+ * whatever the segments (0 if the arguments are invalid). */
 size_t fmgsr_workspace_bytes(int64_t n, int32_t levels, const fmgsr_options *opt);
+
+/* The same for these segments and buffer exactly (0 if invalid); never more
+ * than fmgsr_workspace_bytes.  With one SR level, split tau, buffer >=
+ * 2 nu1 - 1 and >= 2 nu2 and no functionals the SR passes run as the top
+ * level of the vertical kernels and the restricted fine iterate (n/2
+ * doubles) is never stored. */
+size_t fmgsr_workspace_bytes_for(int64_t n, int32_t levels, int64_t n_segments, int32_t buffer,
+                                 const fmgsr_options *opt);
 
 /*
  * fmgsr_solve -- one FMG-FAS-SR iteration (Fig. 3) for -u'' = f.

@@ -143,6 +143,10 @@ struct Plan {
   bool f32 = false;  // FP32 relaxation (correction form) on stored and SR levels
   int d_down = 1, d_up = 1;
   int d_srup = 0;  // levels of an up kernel topped by the SR level (0: none fit)
+  bool functionals = false;
+  // one SR level whose segment passes are exact as the top level of the
+  // vertical kernels (set with the segments)
+  bool fuse_down = false, fuse_up = false;
   int64_t S = 1, s = 0, b = 0, pad = 0;
   int seg_threads = 0;
   // sr_levels >= 2: levels M and M-1 are never stored; the finest segment
@@ -169,6 +173,7 @@ fmgsr_status make_plan(int64_t n, int32_t levels, const fmgsr_options& o, Plan* 
   if (o.precision != FMGSR_FP64 && o.precision != FMGSR_FP32_RELAX) return FMGSR_EINVAL;
   if (o.reserved != 0) return FMGSR_EINVAL;
   p->f32 = (o.precision == FMGSR_FP32_RELAX);
+  p->functionals = (o.functionals != nullptr);
   // literal tau differentiates the iterate (L_h u), amplifying the FP32
   // rounding of the relaxation by ~n^2 into every coarse right-hand side
   if (p->f32 && o.tau_mode == FMGSR_TAU_LITERAL) return FMGSR_ENOTSUP;
@@ -199,9 +204,10 @@ fmgsr_status make_plan(int64_t n, int32_t levels, const fmgsr_options& o, Plan* 
   p->off_F = off; off = align_up(off + hier);
   p->off_U = off; off = align_up(off + hierU);
   p->off_V = off; off = align_up(off + hierV);
-  p->off_Uh = off; off = align_up(off + (p->nsr ? (size_t)(n / 2) * sizeof(double) : 0));
   p->off_Q = off; off = align_up(off + (p->literal ? hier : 0));
   p->off_Utop = off; off = align_up(off + (p->nsr == 0 && M >= 1 ? (size_t)n * sizeof(double) : 0));
+  // Uh last: plan_bytes() leaves it out when the segments never use it
+  p->off_Uh = off; off = align_up(off + (p->nsr ? (size_t)(n / 2) * sizeof(double) : 0));
   p->total = std::max<size_t>(off, kAlign);
   return FMGSR_OK;
 }
@@ -228,6 +234,14 @@ fmgsr_status plan_segments(int64_t n_segments, int32_t buffer, Plan* p) {
   p->b = buffer;
   p->pad = pad;
   p->seg_threads = (int)((thr + 63) / 64 * 64);
+  // One SR level, split tau: with b >= 2 nu1 - 1 the block smoother's cores
+  // equal global red-black sweeps bit for bit, and with b >= 2 nu2 the
+  // blocked compatible relaxation's cores equal the unsegmented one, so the
+  // SR down / up passes are exact as the top level of a vertical kernel.
+  p->fuse_down = p->nsr == 1 && !p->literal && buffer >= 2 * (int64_t)p->nu1 - 1 &&
+                 p->d_down >= 2 && p->M - 1 > p->C;
+  p->fuse_up = p->fuse_down && buffer >= 2 * (int64_t)p->nu2 && p->d_srup >= 2 &&
+               !p->functionals && p->M - p->d_srup >= p->C;
   if (p->nsr >= 2) {
     // level-(M-1) margin: pad/2 + 2 cells for Pi's reach from the level-M
     // window, 3 per CR iteration of stale cells from the window edges, even
@@ -245,6 +259,14 @@ fmgsr_status plan_segments(int64_t n_segments, int32_t buffer, Plan* p) {
   return FMGSR_OK;
 }
 
+
+// Workspace these segments actually use: the restricted SR iterate Uh (the
+// last region of the layout, after every region the solve may need) is
+// only needed by the segment passes and the functionals.
+size_t plan_bytes(const Plan& p) {
+  const bool uh = p.nsr >= 2 || (p.nsr == 1 && !(p.fuse_down && p.fuse_up)) || p.functionals;
+  return uh ? p.total : std::max<size_t>(p.off_Uh, kAlign);
+}
 
 struct Ctx {
   const Plan* p;
@@ -484,8 +506,7 @@ struct Ctx {
       // (Pi, sweeps, I^ of the cores) is the top level of an ordinary
       // vertical down kernel whose level-M output is simply not stored; the
       // restricted iterate never goes through HBM.
-      const bool fused_down = sr && t == M && P.nsr == 1 && !P.literal &&
-                              P.b >= 2 * (int64_t)P.nu1 - 1 && P.d_down >= 2 && M - 1 > C;
+      const bool fused_down = sr && t == M && P.fuse_down;
       int top = t;  // highest stored level of this step
       int dtop = t;  // top of the vertical down leg
       if (sr && !fused_down) {
@@ -520,8 +541,7 @@ struct Ctx {
       // (Pi + compatible relaxation) equals the unsegmented one on the cores
       // bit for bit, so it is the top level of the last vertical up kernel,
       // which then never writes V^{M-1}.
-      const bool fused_up = fused_down && P.b >= 2 * (int64_t)P.nu2 && P.d_srup >= 2 &&
-                            !functionals && M - P.d_srup >= C;
+      const bool fused_up = fused_down && P.fuse_up;
       const int utop = fused_up ? M - P.d_srup : top;  // last ordinary up level
       // post-smoothing leg: stored levels C+1..utop
       for (int lo = C + 1; lo <= utop;) {
@@ -576,6 +596,17 @@ size_t fmgsr_workspace_bytes(int64_t n, int32_t levels, const fmgsr_options* opt
   return p.total;
 }
 
+size_t fmgsr_workspace_bytes_for(int64_t n, int32_t levels, int64_t n_segments, int32_t buffer,
+                                 const fmgsr_options* opt) {
+  fmgsr_options o;
+  if (opt) o = *opt;
+  else fmgsr_default_options(&o);
+  Plan p;
+  if (make_plan(n, levels, o, &p) != FMGSR_OK) return 0;
+  if (plan_segments(n_segments, buffer, &p) != FMGSR_OK) return 0;
+  return plan_bytes(p);
+}
+
 fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_left,
                          double g_right, int64_t n, int32_t levels, int64_t n_segments,
                          int32_t buffer, const fmgsr_options* opt, double* u_out,
@@ -608,9 +639,9 @@ fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_lef
   char* ws = (char*)o.workspace;
   bool own = false;
   if (ws) {
-    if (o.workspace_bytes < p.total || !is_device_ptr(ws)) return FMGSR_ENOMEM;
+    if (o.workspace_bytes < plan_bytes(p) || !is_device_ptr(ws)) return FMGSR_ENOMEM;
   } else {
-    if (hipMallocAsync((void**)&ws, p.total, stream) != hipSuccess) {
+    if (hipMallocAsync((void**)&ws, plan_bytes(p), stream) != hipSuccess) {
       (void)hipGetLastError();
       return FMGSR_ENOMEM;
     }

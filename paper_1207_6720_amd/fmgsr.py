@@ -66,6 +66,9 @@ def lib():
         L.fmgsr_default_options.restype = None
         L.fmgsr_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(Options)]
         L.fmgsr_workspace_bytes.restype = ctypes.c_size_t
+        L.fmgsr_workspace_bytes_for.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                                ctypes.c_int32, ctypes.POINTER(Options)]
+        L.fmgsr_workspace_bytes_for.restype = ctypes.c_size_t
         L.fmgsr_solve.argtypes = [ctypes.POINTER(Operator), ctypes.c_void_p, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
                                   ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p,
@@ -113,9 +116,17 @@ def make_options(nu=(2, 1), sr_levels=1, tau="split", workspace=None, precision=
     return o
 
 
-def workspace_bytes(n, levels, nu=(2, 1), sr_levels=1, tau="split"):
+def workspace_bytes(n, levels, nu=(2, 1), sr_levels=1, tau="split", segments=None, buffer=None,
+                    functionals=False):
+    """Workspace bytes for any segments, or (segments and buffer given) for
+    exactly these segments and buffer."""
     o = make_options(nu, sr_levels, tau)
-    return int(lib().fmgsr_workspace_bytes(int(n), int(levels), ctypes.byref(o)))
+    if functionals:
+        o.functionals = ctypes.c_void_p(1)  # only its presence matters for the size
+    if segments is None:
+        return int(lib().fmgsr_workspace_bytes(int(n), int(levels), ctypes.byref(o)))
+    return int(lib().fmgsr_workspace_bytes_for(int(n), int(levels), int(segments), int(buffer),
+                                               ctypes.byref(o)))
 
 
 def alloc_workspace(n, levels, device, **kw):

@@ -188,6 +188,15 @@ def test_repeatable_and_workspace_reuse(dev):
     b = fmgsr.solve(f, levels=levels, segments=4, buffer=8, workspace=ws)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+    # the exact size for these segments (no restricted fine iterate) suffices
+    exact = fmgsr.alloc_workspace(n, levels, dev, segments=4, buffer=8)
+    assert exact.numel() == ws.numel() - (n // 2) * 8
+    exact.fill_(255)
+    c = fmgsr.solve(f, levels=levels, segments=4, buffer=8, workspace=exact)
+    torch.cuda.synchronize()
+    assert torch.equal(a, c)
+    with pytest.raises(fmgsr.FmgsrError):  # a smaller one is refused
+        fmgsr.solve(f, levels=levels, segments=4, buffer=8, workspace=exact[:-256])
 
 
 def test_side_stream(dev):

@@ -115,6 +115,26 @@ def test_workspace_sizes():
     assert F.workspace_bytes(1000, 11) == 0
 
 
+def test_exact_workspace_for_segments():
+    """With one SR level, split tau and a buffer covering both sweep cones the
+    SR passes run inside the vertical kernels and the restricted fine
+    iterate (n/2 doubles) is not stored; otherwise the exact size is the
+    bound."""
+    n, L, S = 1 << 20, 21, 256
+    bound = F.workspace_bytes(n, L)
+    assert F.workspace_bytes(n, L, segments=S, buffer=8) == bound - (n // 2) * 8
+    assert F.workspace_bytes(n, L, segments=S, buffer=3, nu=(2, 1)) == bound - (n // 2) * 8
+    for kw in (dict(buffer=2), dict(buffer=8, functionals=True), dict(buffer=3, nu=(2, 2))):
+        assert F.workspace_bytes(n, L, segments=S, **kw) == bound, kw
+    lit = F.workspace_bytes(n, L, tau="literal")
+    assert F.workspace_bytes(n, L, segments=S, buffer=8, tau="literal") == lit
+    assert F.workspace_bytes(n, L, segments=3, buffer=8) == 0      # invalid segments
+    # plain FMG-FAS stores the finest level: nothing may be left out
+    for tau in ("split", "literal"):
+        assert (F.workspace_bytes(n, L, segments=1, buffer=0, sr_levels=0, tau=tau)
+                == F.workspace_bytes(n, L, sr_levels=0, tau=tau))
+
+
 def test_two_sr_levels_store_neither_finest_level():
     """With two or more SR levels, level M-1 keeps no U or V array: the
     workspace shrinks by V^{M-1} (n/2 cells) and by U^{M-1} less the n/4 cells
