@@ -240,8 +240,8 @@ fmgsr_status plan_segments(int64_t n_segments, int32_t buffer, Plan* p) {
   // SR down / up passes are exact as the top level of a vertical kernel.
   p->fuse_down = p->nsr == 1 && !p->literal && buffer >= 2 * (int64_t)p->nu1 - 1 &&
                  p->d_down >= 2 && p->M - 1 > p->C;
-  p->fuse_up = p->fuse_down && buffer >= 2 * (int64_t)p->nu2 && p->d_srup >= 2 &&
-               !p->functionals && p->M - p->d_srup >= p->C;
+  p->fuse_up = p->fuse_down && buffer >= 2 * (int64_t)p->nu2 &&
+               std::min(p->d_srup, p->M - p->C) >= 2 && !p->functionals;
   if (p->nsr >= 2) {
     // level-(M-1) margin: pad/2 + 2 cells for Pi's reach from the level-M
     // window, 3 per CR iteration of stale cells from the window edges, even
@@ -542,7 +542,8 @@ struct Ctx {
       // bit for bit, so it is the top level of the last vertical up kernel,
       // which then never writes V^{M-1}.
       const bool fused_up = fused_down && P.fuse_up;
-      const int utop = fused_up ? M - P.d_srup : top;  // last ordinary up level
+      const int dsr = std::min(P.d_srup, M - C);       // levels of the SR-topped up kernel
+      const int utop = fused_up ? M - dsr : top;       // last ordinary up level
       // post-smoothing leg: stored levels C+1..utop
       for (int lo = C + 1; lo <= utop;) {
         const int d = std::min(P.d_up, utop - lo + 1);
@@ -552,7 +553,7 @@ struct Ctx {
         lo += d;
       }
       if (fused_up) {
-        up_launch(M, P.d_srup, f, lv(V, M - P.d_srup), nullptr, u_out);
+        up_launch(M, dsr, f, lv(V, M - dsr), nullptr, u_out);
       } else if (sr) {
         // full update and compatible relaxation on each SR level, upwards
         for (int l = sr_lo; l <= t; ++l) {
