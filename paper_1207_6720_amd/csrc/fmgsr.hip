@@ -155,7 +155,8 @@ struct Plan {
   int R = 1;
   int seg2_threads = 0;
   // workspace layout (byte offsets)
-  size_t off_F = 0, off_U = 0, off_V = 0, off_Uh = 0, off_Q = 0, off_Utop = 0, total = 0;
+  size_t off_F = 0, off_U = 0, off_V = 0, off_Uh = 0, off_Q = 0, off_Utop = 0, off_P = 0,
+         total = 0;
 };
 
 // Geometry, options and workspace layout (segment arguments excluded).
@@ -206,6 +207,10 @@ fmgsr_status make_plan(int64_t n, int32_t levels, const fmgsr_options& o, Plan* 
   p->off_V = off; off = align_up(off + hierV);
   p->off_Q = off; off = align_up(off + (p->literal ? hier : 0));
   p->off_Utop = off; off = align_up(off + (p->nsr == 0 && M >= 1 ? (size_t)n * sizeof(double) : 0));
+  // per-tile functional partials of the SR-topped up kernel (2 per tile)
+  const int64_t tile_core = (int64_t)kRun * kTileThreads - 2 * kTileHalo;
+  p->off_P = off;
+  off = align_up(off + (p->nsr >= 1 ? (size_t)(2 * ((n + tile_core - 1) / tile_core) + 2) * sizeof(double) : 0));
   // Uh last: plan_bytes() leaves it out when the segments never use it
   p->off_Uh = off; off = align_up(off + (p->nsr ? (size_t)(n / 2) * sizeof(double) : 0));
   p->total = std::max<size_t>(off, kAlign);
@@ -241,7 +246,7 @@ fmgsr_status plan_segments(int64_t n_segments, int32_t buffer, Plan* p) {
   p->fuse_down = p->nsr == 1 && !p->literal && buffer >= 2 * (int64_t)p->nu1 - 1 &&
                  p->d_down >= 2 && p->M - 1 > p->C;
   p->fuse_up = p->fuse_down && buffer >= 2 * (int64_t)p->nu2 &&
-               std::min(p->d_srup, p->M - p->C) >= 2 && !p->functionals;
+               std::min(p->d_srup, p->M - p->C) >= 2;
   if (p->nsr >= 2) {
     // level-(M-1) margin: pad/2 + 2 cells for Pi's reach from the level-M
     // window, 3 per CR iteration of stale cells from the window edges, even
@@ -262,9 +267,9 @@ fmgsr_status plan_segments(int64_t n_segments, int32_t buffer, Plan* p) {
 
 // Workspace these segments actually use: the restricted SR iterate Uh (the
 // last region of the layout, after every region the solve may need) is
-// only needed by the segment passes and the functionals.
+// only needed by the segment passes (also for their functional partials).
 size_t plan_bytes(const Plan& p) {
-  const bool uh = p.nsr >= 2 || (p.nsr == 1 && !(p.fuse_down && p.fuse_up)) || p.functionals;
+  const bool uh = p.nsr >= 2 || (p.nsr == 1 && !(p.fuse_down && p.fuse_up));
   return uh ? p.total : std::max<size_t>(p.off_Uh, kAlign);
 }
 
@@ -276,6 +281,7 @@ struct Ctx {
   double* u_out;
   double* functionals = nullptr;  // [2] device: h sum u, h sum u^2 of the result
   double *F, *U, *V, *Uh, *Q, *Utop;
+  double* P;  // per-tile functional partials
   fmgsr_status err = FMGSR_OK;
 
   double* lv(double* base, int l) const { return base + lvl_off_ws(p->n0, l); }
@@ -335,8 +341,9 @@ struct Ctx {
       a.pre[i] = (i == 0) ? top_pre : lv(U, top - i);
       if (a.pre[i]) bytes += (double)nl(top - i) * 8.0;  // pre read
     }
-    bytes += (double)a.n * 16.0 + (double)nl(top - levels) * 8.0;  // rhs, out; coarse
+    bytes += (double)a.n * (out ? 16.0 : 8.0) + (double)nl(top - levels) * 8.0;  // rhs, out; coarse
     a.out[0] = out;
+    if (a.sr_top && functionals) a.part = P;
     const int64_t blocks = (a.n + a.core - 1) / a.core;
     ProfScope ps("k_up", bytes, st);
     if (p->f32) hipLaunchKernelGGL((k_up<kRun, true>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
@@ -554,6 +561,13 @@ struct Ctx {
       }
       if (fused_up) {
         up_launch(M, dsr, f, lv(V, M - dsr), nullptr, u_out);
+        if (functionals) {
+          const int64_t tiles = (p->n + tile_core() - 1) / tile_core();
+          ProfScope ps("k_functionals", (double)tiles * 16.0 + 16.0, st);
+          hipLaunchKernelGGL(k_functionals, dim3(1), dim3(1024), 0, st, this->P, tiles,
+                             1.0 / (double)p->n, functionals);
+          check();
+        }
       } else if (sr) {
         // full update and compatible relaxation on each SR level, upwards
         for (int l = sr_lo; l <= t; ++l) {
@@ -673,6 +687,7 @@ fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_lef
   c.Uh = (double*)(ws + p.off_Uh);
   c.Q = (double*)(ws + p.off_Q);
   c.Utop = (double*)(ws + p.off_Utop);
+  c.P = (double*)(ws + p.off_P);
   c.run();
   if (own && hipFreeAsync(ws, stream) != hipSuccess) {
     (void)hipGetLastError();

@@ -165,6 +165,8 @@ struct VertArgs {
   int sr_top;            // up: the top level is an unstored SR level, rebuilt by
                          // the full update from the level below and compatible
                          // relaxation (pre[0] unused)
+  double* part;          // up, SR top: per-tile (sum u, sum u^2) of the top core,
+                         // or nullptr
   double* out[kMaxFuse];        // down: U of each level (null: not stored);
                                 // up: out[0] = top result
 };
@@ -444,6 +446,38 @@ __device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4, d
   smooth_fast<K, F32>(u, f, a.nu, x, x4);
 }
 
+// Sums of the core cells [a, b) of this thread's run (run-local indices),
+// in cell order, then over each wavefront by a fixed shuffle tree, then over
+// the wavefronts in order; thread 0 writes (sum u, sum u^2) of the
+// workgroup's core (an SR segment or a vertical tile) to part[2 blockIdx.x].
+// The order never depends on scheduling.
+__device__ __forceinline__ void wave_sum2(double& s1, double& s2) {
+  for (int o = 32; o > 0; o >>= 1) {
+    s1 = s1 + __shfl_down(s1, o);
+    s2 = s2 + __shfl_down(s2, o);
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void segment_sums(const double (&u)[K], int a, int b, double* st,
+                                             double* __restrict__ part) {
+  double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+    if (j >= a && j < b) { s1 = s1 + u[j]; s2 = s2 + u[j] * u[j]; }
+  wave_sum2(s1, s2);
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) { st[w] = s1; st[32 + w] = s2; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t1 = st[0], t2 = st[32];
+    for (int i = 1; i < nw; ++i) { t1 = t1 + st[i]; t2 = t2 + st[32 + i]; }
+    part[2 * (int64_t)blockIdx.x] = t1;
+    part[2 * (int64_t)blockIdx.x + 1] = t2;
+  }
+}
+
 // Up leg over `levels` stored levels, bottom-up (Fig. 3 post-smoothing leg,
 // Eq. 4); only the top level's core is written.  Lower right-hand sides are
 // the full weighting of the top one (split tau).
@@ -463,13 +497,23 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
     if (!a.sr_top) issue_loads<K, true>(tp, a.pre[0] + wlo0, 0);
     stage_tmp<K, true>(st, tf, f, 0);
     up_level_fast<K, 0, F32>(a, st, x, x4, f, u, tp, wlo0);
-    store_run_fast<K>(st, u, a.out[0] + wlo0, (int)a.halo, (int)(a.halo + a.core));
+    if (a.out[0])  // null: functionals only, the fine solution is not written
+      store_run_fast<K>(st, u, a.out[0] + wlo0, (int)a.halo, (int)(a.halo + a.core));
+    if (a.part) {
+      const int e0 = (int)threadIdx.x * K;
+      segment_sums<K>(u, (int)a.halo - e0, (int)(a.halo + a.core) - e0, st, a.part);
+    }
     return;
   }
   const TileGeom G = tile_geom(a, 0, K);
   load_run<K>(st, f, G.wlo, wcount, G.n, [&](int64_t g) { return a.rhs[g]; });
   up_level<K, 0, F32>(a, st, x, f, u);
-  store_run<K>(st, u, G.wlo, G.clo, G.chi, a.out[0]);
+  if (a.out[0]) store_run<K>(st, u, G.wlo, G.clo, G.chi, a.out[0]);
+  if (a.part) {
+    const int64_t c0 = G.clo - G.g0, c1 = G.chi - G.g0;
+    segment_sums<K>(u, (int)(c0 < 0 ? 0 : (c0 > K ? K : c0)), (int)(c1 < 0 ? 0 : (c1 > K ? K : c1)),
+                    st, a.part);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -578,36 +622,6 @@ struct SegArgs {
   double* part;          // up: per-segment (sum u, sum u^2) of the core, or nullptr
 };
 
-// Sums of the core cells [a, b) of this thread's run (run-local indices),
-// in cell order, then over each wavefront by a fixed shuffle tree, then over
-// the wavefronts in order; thread 0 writes (sum u, sum u^2) of the segment
-// to part[2 seg].  The order never depends on scheduling.
-__device__ __forceinline__ void wave_sum2(double& s1, double& s2) {
-  for (int o = 32; o > 0; o >>= 1) {
-    s1 = s1 + __shfl_down(s1, o);
-    s2 = s2 + __shfl_down(s2, o);
-  }
-}
-
-template <int K>
-__device__ __forceinline__ void segment_sums(const double (&u)[K], int a, int b, double* st,
-                                             double* __restrict__ part) {
-  double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-  for (int j = 0; j < K; ++j)
-    if (j >= a && j < b) { s1 = s1 + u[j]; s2 = s2 + u[j] * u[j]; }
-  wave_sum2(s1, s2);
-  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) { st[w] = s1; st[32 + w] = s2; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t1 = st[0], t2 = st[32];
-    for (int i = 1; i < nw; ++i) { t1 = t1 + st[i]; t2 = t2 + st[32 + i]; }
-    part[2 * (int64_t)blockIdx.x] = t1;
-    part[2 * (int64_t)blockIdx.x + 1] = t2;
-  }
-}
 
 // Down pass (Fig. 3 steps 1-5 fused): Pi, nu sweeps on the extended patch,
 // then I^ (and literal tau) on the core's coarse cells.  The fine iterate

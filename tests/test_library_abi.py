@@ -118,13 +118,15 @@ def test_workspace_sizes():
 def test_exact_workspace_for_segments():
     """With one SR level, split tau and a buffer covering both sweep cones the
     SR passes run inside the vertical kernels and the restricted fine
-    iterate (n/2 doubles) is not stored; otherwise the exact size is the
-    bound."""
+    iterate (n/2 doubles) is not stored, with or without functionals;
+    otherwise the exact size is the bound."""
     n, L, S = 1 << 20, 21, 256
     bound = F.workspace_bytes(n, L)
     assert F.workspace_bytes(n, L, segments=S, buffer=8) == bound - (n // 2) * 8
     assert F.workspace_bytes(n, L, segments=S, buffer=3, nu=(2, 1)) == bound - (n // 2) * 8
-    for kw in (dict(buffer=2), dict(buffer=8, functionals=True), dict(buffer=3, nu=(2, 2))):
+    # the functionals are then summed per vertical tile, not in Uh
+    assert F.workspace_bytes(n, L, segments=S, buffer=8, functionals=True) == bound - (n // 2) * 8
+    for kw in (dict(buffer=2), dict(buffer=2, functionals=True), dict(buffer=3, nu=(2, 2))):
         assert F.workspace_bytes(n, L, segments=S, **kw) == bound, kw
     lit = F.workspace_bytes(n, L, tau="literal")
     assert F.workspace_bytes(n, L, segments=S, buffer=8, tau="literal") == lit
