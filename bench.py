@@ -264,7 +264,8 @@ def main():
         "memory": {"inputs_and_workspace_bytes": mem_inputs, "peak_allocated_bytes": peak_mem,
                    "workspace_bytes": ws.numel(),
                    "workspace_bytes_full_grid_fmg": fmgsr.workspace_bytes(n, wl.levels, sr_levels=0,
-                                                                          tau=args.tau),
+                                                                          tau=args.tau, segments=1,
+                                                                          buffer=0),
                    "workspace_bytes_sr": fmgsr.workspace_bytes(n, wl.levels, sr_levels=1,
                                                                tau=args.tau, segments=wl.segments,
                                                                buffer=wl.buffer),

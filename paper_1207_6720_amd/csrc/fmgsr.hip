@@ -92,9 +92,6 @@ int64_t lvl_off_ws(int64_t n0, int l) {
   return off;
 }
 
-// Stale cells (counted from a window edge) left on each level of a vertical
-// kernel walking `d` levels with nu sweeps per level; the halo must cover
-// them on every level whose core is written or read further on.
 // Stale cells (counted from a window edge) on each level of a vertical
 // kernel walking `d` levels with nu sweeps per level.  The window edge cell
 // is never updated, so every half-sweep spreads staleness by one cell; I^
@@ -127,6 +124,19 @@ bool sr_up_fits(int nu, int d, int64_t halo) {
   int64_t inv = 2 + 2 * nu;
   for (int i = d - 2; i >= 1; --i) inv = 2 * (inv + 1) + 2 * nu;
   inv = 2 * (inv + 2) + 3 * nu;
+  return halo >= inv;
+}
+
+// Up kernel that rebuilds its top level's pre-smoothed iterate (Pi of the
+// level below's FMG iterate, then the down leg's nu1 sweeps) instead of
+// reading it: the rebuild is stale in 2 nu1 cells plus Pi's two-cell reach,
+// which enter the correction through I^ (pairs) and P (one coarse cell more).
+bool rebuild_up_fits(int nu1, int nu2, int d, int64_t halo) {
+  if (d < 2) return false;
+  int64_t inv = 2 + 2 * nu2;
+  for (int i = d - 2; i >= 1; --i) inv = 2 * (inv + 1) + 2 * nu2;
+  const int64_t pre = (2 * (int64_t)nu1 + 2 + 1) / 2;
+  inv = 2 * (std::max(inv, pre) + 1) + 2 * nu2;
   return halo >= inv;
 }
 
@@ -264,11 +274,27 @@ fmgsr_status plan_segments(int64_t n_segments, int32_t buffer, Plan* p) {
   return FMGSR_OK;
 }
 
+// FMG step t (a stored level) rebuilds its top level's pre-smoothed iterate
+// inside its top up kernel, and its top down kernel never stores it.  Needs
+// split tau; both top kernels walk two or more levels (so the next down
+// kernel and the coarse core read lower levels only, and no up kernel of the
+// step writes V^{t-1}, the rebuild's source, before the top one); and the
+// rebuild's stale edge cells stay outside the top core's reach.
+bool rebuild_top(const Plan& p, int t) {
+  if (p.literal || t > p.M || t < p.C + 2) return false;
+  if (p.nsr >= 1 && t > p.M - p.nsr) return false;  // an SR level
+  const int dd = std::min(p.d_down, t - p.C), du = std::min(p.d_up, t - p.C);
+  return dd >= 2 && rebuild_up_fits(p.nu1, p.nu2, du, kTileHalo);
+}
 
 // Workspace these segments actually use: the restricted SR iterate Uh (the
 // last region of the layout, after every region the solve may need) is
-// only needed by the segment passes (also for their functional partials).
+// only needed by the segment passes (also for their functional partials);
+// without SR levels, the finest pre-smoothed iterate Utop (then the last
+// non-empty region) only when the finest step does not rebuild it.
 size_t plan_bytes(const Plan& p) {
+  if (p.nsr == 0)
+    return (p.M >= 1 && rebuild_top(p, p.M)) ? std::max<size_t>(p.off_Utop, kAlign) : p.total;
   const bool uh = p.nsr >= 2 || (p.nsr == 1 && !(p.fuse_down && p.fuse_up));
   return uh ? p.total : std::max<size_t>(p.off_Uh, kAlign);
 }
@@ -330,13 +356,18 @@ struct Ctx {
 
   // Up leg over levels top-levels+1..top; result of the top level to out.
   // top_pre == nullptr: the top level is the SR level (full update + CR)
+  // rebuild_src != nullptr: the top level's pre-smoothed iterate is rebuilt
+  // from that FMG iterate of the level below (top_pre unused)
   void up_launch(int top, int levels, const double* rhs, const double* coarse,
-                 const double* top_pre, double* out) {
+                 const double* top_pre, double* out, const double* rebuild_src = nullptr) {
     VertArgs a = vargs(top, levels, p->nu2);
     a.rhs = rhs;
     a.coarse = coarse;
-    a.sr_top = (top_pre == nullptr);
-    double bytes = 0.0;
+    a.src = rebuild_src;
+    a.nu_pre = p->nu1;
+    if (rebuild_src) top_pre = nullptr;
+    a.sr_top = (top_pre == nullptr && rebuild_src == nullptr);
+    double bytes = rebuild_src ? (double)nl(top - 1) * 8.0 : 0.0;  // Pi source read
     for (int i = 0; i < levels; ++i) {
       a.pre[i] = (i == 0) ? top_pre : lv(U, top - i);
       if (a.pre[i]) bytes += (double)nl(top - i) * 8.0;  // pre read
@@ -514,6 +545,8 @@ struct Ctx {
       // vertical down kernel whose level-M output is simply not stored; the
       // restricted iterate never goes through HBM.
       const bool fused_down = sr && t == M && P.fuse_down;
+      // the top up kernel rebuilds level t's pre-smoothed iterate
+      const bool rebuild = !sr && rebuild_top(P, t);
       int top = t;  // highest stored level of this step
       int dtop = t;  // top of the vertical down leg
       if (sr && !fused_down) {
@@ -533,7 +566,8 @@ struct Ctx {
         else if (sr && !fused_down && hi == top) { src_kind = kSrcDirect; src = H(top); }
         else { src_kind = kSrcRestrict; src = U_of(hi + 1); }
         if (P.literal && src_kind == kSrcRestrict) tau_launch(U_of(hi + 1), rhs_of(hi + 1), hi, lv(Q, hi));
-        down_launch(hi, d, src_kind, src, rhs_of(hi), (fused_down && hi == M) ? nullptr : U_of(hi));
+        const bool unstored = (fused_down && hi == M) || (rebuild && hi == t);
+        down_launch(hi, d, src_kind, src, rhs_of(hi), unstored ? nullptr : U_of(hi));
         hi -= d;
       }
       // coarse core: V-cycle bottom from level C
@@ -551,13 +585,17 @@ struct Ctx {
       const bool fused_up = fused_down && P.fuse_up;
       const int dsr = std::min(P.d_srup, M - C);       // levels of the SR-topped up kernel
       const int utop = fused_up ? M - dsr : top;       // last ordinary up level
-      // post-smoothing leg: stored levels C+1..utop
-      for (int lo = C + 1; lo <= utop;) {
-        const int d = std::min(P.d_up, utop - lo + 1);
-        const int hi = lo + d - 1;
+      // post-smoothing leg: stored levels C+1..utop, split from the top down
+      // (full kernels on top, a partial one at the bottom), run bottom-up
+      int his[64], nup = 0;
+      for (int hi = utop; hi >= C + 1; hi -= std::min(P.d_up, hi - C)) his[nup++] = hi;
+      for (int k = nup - 1; k >= 0; --k) {
+        const int hi = his[k];
+        const int d = std::min(P.d_up, hi - C);
+        const int lo = hi - d + 1;
         double* out = (hi == top && !sr) ? ((t == M) ? u_out : lv(V, t)) : lv(V, hi);
-        up_launch(hi, d, rhs_of(hi), lv(V, lo - 1), U_of(hi), out);
-        lo += d;
+        const double* rsrc = (rebuild && hi == t) ? lv(V, t - 1) : nullptr;
+        up_launch(hi, d, rhs_of(hi), lv(V, lo - 1), U_of(hi), out, rsrc);
       }
       if (fused_up) {
         up_launch(M, dsr, f, lv(V, M - dsr), nullptr, u_out);

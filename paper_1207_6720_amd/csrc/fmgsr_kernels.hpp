@@ -158,7 +158,12 @@ struct VertArgs {
   int64_t core;          // top-level core cells per workgroup (divisible by 2^kMaxFuse)
   int64_t halo;          // top-level halo (divisible by 2^kMaxFuse)
   int src_kind;          // down: how the top-level iterate starts
-  const double* src;     // down: coarser (Pi), finer (I^) or same-level array
+  const double* src;     // down: coarser (Pi), finer (I^) or same-level array;
+                         // up: the level below's FMG iterate when the top
+                         // level's pre-smoothed iterate is rebuilt here (Pi,
+                         // then nu_pre sweeps, as the down kernel made it)
+                         // instead of read from pre[0]; else null
+  int nu_pre;            // up with src: the down leg's sweeps per level
   const double* rhs;     // right-hand side of the top level
   const double* coarse;  // up: post-smoothed level below the bottom level
   const double* pre[kMaxFuse];  // up: pre-smoothed iterates, index = levels below top
@@ -356,7 +361,18 @@ __device__ void up_level(const VertArgs& a, double* st, Xch& x, const double (&f
     return;
   }
   // correction (Eq. 4): u = pre + P(c - I^ pre)
-  load_run<K>(st, u, G.wlo, wcount, G.n, [&](int64_t g) { return a.pre[I][g]; });
+  bool rebuilt = false;
+  if constexpr (I == 0) {
+    if (a.src) {
+      // the pre-smoothed top level, rebuilt exactly as the down kernel made
+      // it in the same window; its stale edge cells stay outside the core's
+      // reach
+      load_interp_run<K>(st, u, G.wlo, wcount, G.n, a.src, a.gL, a.gR, x);
+      smooth_general<K, F32>(u, f, G.g0, a.nu_pre, G.lo, G.hi, G.n, a.gL, a.gR, x);
+      rebuilt = true;
+    }
+  }
+  if (!rebuilt) load_run<K>(st, u, G.wlo, wcount, G.n, [&](int64_t g) { return a.pre[I][g]; });
   double e[K / 2];
 #pragma unroll
   for (int p = 0; p < K / 2; ++p) e[p] = c[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
@@ -430,7 +446,21 @@ __device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4, d
     }
     return;
   }
-  stage_tmp<K, true>(st, tp, u, 0);
+  bool rebuilt = false;
+  if constexpr (I == 0) {
+    if (a.src) {
+      // rebuilt pre-smoothed top level (tp[0, K/2) holds the Pi source run)
+      const double* cb = a.src + (wlo0 >> 1);
+      double tc[K / 2], cs[K / 2];
+#pragma unroll
+      for (int k = 0; k < K / 2; ++k) tc[k] = tp[k];
+      stage_tmp<K / 2, true>(st, tc, cs, 0);
+      interp_fast<K>(u, cs, cb + threadIdx.x * (K / 2), x);
+      smooth_fast<K, F32>(u, f, a.nu_pre, x, x4);
+      rebuilt = true;
+    }
+  }
+  if (!rebuilt) stage_tmp<K, true>(st, tp, u, 0);
   double e[K / 2];
 #pragma unroll
   for (int p = 0; p < K / 2; ++p) e[p] = c[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
@@ -494,7 +524,13 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
   if (window_interior(wlo0, wcount, a.n)) {
     double tf[K], tp[K];
     issue_loads<K, true>(tf, a.rhs + wlo0, 0);
-    if (!a.sr_top) issue_loads<K, true>(tp, a.pre[0] + wlo0, 0);
+    if (a.src) {  // Pi source run of the rebuilt top level, in tp[0, K/2)
+      const double* cb = a.src + (wlo0 >> 1);
+#pragma unroll
+      for (int k = 0; k < K / 2; ++k) tp[k] = cb[threadIdx.x + k * kTileThreads];
+    } else if (!a.sr_top) {
+      issue_loads<K, true>(tp, a.pre[0] + wlo0, 0);
+    }
     stage_tmp<K, true>(st, tf, f, 0);
     up_level_fast<K, 0, F32>(a, st, x, x4, f, u, tp, wlo0);
     if (a.out[0])  // null: functionals only, the fine solution is not written

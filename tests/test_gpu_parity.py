@@ -94,6 +94,13 @@ CASES = [
     (1 << 13, 14, 2, 9, (4, 4), 1, "split", (0.0, 0.0), 23),
     # levels = 1 with N0 > 1 (one exact solve)
     (1000, 1, 1, 0, (2, 1), 0, "split", (0.2, 0.7), 24),
+    # the top up kernel of each stored step rebuilds the pre-smoothed top
+    # level: many down sweeps (two-level down kernels), no post-sweeps,
+    # uneven up kernel splits
+    (1 << 14, 15, 1, 0, (10, 0), 0, "split", (0.3, -0.2), 25),
+    (1 << 15, 16, 1, 0, (10, 1), 0, "split", (0.0, 0.0), 26),
+    (1 << 14, 15, 16, 8, (8, 3), 1, "split", (0.0, 0.0), 27),
+    (1 << 13, 14, 8, 9, (5, 2), 1, "split", (-0.4, 0.2), 28),
 ]
 
 

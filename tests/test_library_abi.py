@@ -131,10 +131,18 @@ def test_exact_workspace_for_segments():
     lit = F.workspace_bytes(n, L, tau="literal")
     assert F.workspace_bytes(n, L, segments=S, buffer=8, tau="literal") == lit
     assert F.workspace_bytes(n, L, segments=3, buffer=8) == 0      # invalid segments
-    # plain FMG-FAS stores the finest level: nothing may be left out
-    for tau in ("split", "literal"):
-        assert (F.workspace_bytes(n, L, segments=1, buffer=0, sr_levels=0, tau=tau)
-                == F.workspace_bytes(n, L, sr_levels=0, tau=tau))
+    # plain FMG-FAS with split tau rebuilds the finest pre-smoothed iterate
+    # inside its top up kernel (n doubles less) when both top kernels walk two
+    # or more levels; literal tau, one-level up kernels (nu2 = 16) and a finest
+    # level right above the coarse core store it
+    assert (F.workspace_bytes(n, L, segments=1, buffer=0, sr_levels=0)
+            == F.workspace_bytes(n, L, sr_levels=0) - n * 8)
+    for kw in (dict(tau="literal"), dict(nu=(2, 16))):
+        assert (F.workspace_bytes(n, L, segments=1, buffer=0, sr_levels=0, **kw)
+                == F.workspace_bytes(n, L, sr_levels=0, **kw)), kw
+    n2, L2 = 1 << 11, 12
+    assert (F.workspace_bytes(n2, L2, segments=1, buffer=0, sr_levels=0)
+            == F.workspace_bytes(n2, L2, sr_levels=0))
 
 
 def test_two_sr_levels_store_neither_finest_level():
