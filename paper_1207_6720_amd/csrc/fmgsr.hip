@@ -140,6 +140,30 @@ bool rebuild_up_fits(int nu1, int nu2, int d, int64_t halo) {
   return halo >= inv;
 }
 
+// Deep pair: the up kernel also rebuilds the pre-smoothed iterates of levels
+// 1..d-2 (the bottom one still comes from HBM).  The rebuilt level i is stale
+// in the down leg's cells s_i from the window edge (down_fits), which enter
+// the correction through I^ and P like the rebuilt top level's.  sr: the top
+// level is the SR level (full update; its own iterate is not needed).
+bool deep_fits(int nu1, int nu2, int d, int64_t halo, bool sr) {
+  if (d < 3 || !down_fits(nu1, d, halo)) return false;
+  int64_t s[kMaxFuse];
+  int64_t dinv = 0, rinv = 0;
+  for (int i = 0; i < d; ++i) {
+    if (i > 0) {
+      rinv = (rinv + 2) / 2;
+      dinv = std::max((dinv + 1) / 2, rinv);
+    }
+    dinv += 2 * nu1;
+    s[i] = dinv;
+  }
+  s[0] += 2;  // Pi's reach
+  int64_t inv = 2 + 2 * nu2;
+  for (int i = d - 2; i >= 1; --i) inv = 2 * (std::max(inv, (s[i] + 1) / 2) + 1) + 2 * nu2;
+  inv = sr ? 2 * (inv + 2) + 3 * nu2 : 2 * (std::max(inv, (s[0] + 1) / 2) + 1) + 2 * nu2;
+  return halo >= inv;
+}
+
 int fuse_depth(bool up, int nu) {
   for (int d = kMaxFuse; d > 1; --d)
     if (up ? up_fits(nu, d, kTileHalo) : down_fits(nu, d, kTileHalo)) return d;
@@ -334,16 +358,20 @@ struct Ctx {
   }
 
   // Down leg over levels top..top-levels+1.
+  // deep: paired with a deep up kernel, which rebuilds levels top-1 ..
+  // top-levels+2 (interior tiles do not store them)
   void down_launch(int top, int levels, int src_kind, const double* src, const double* rhs,
-                   double* top_out) {
+                   double* top_out, bool deep = false) {
     VertArgs a = vargs(top, levels, p->nu1);
     a.src_kind = src_kind;
     a.src = src;
     a.rhs = rhs;
+    a.deep = deep;
     double bytes = 0.0;
     for (int i = 0; i < levels; ++i) {
       a.out[i] = (i == 0) ? top_out : lv(U, top - i);
-      if (a.out[i]) bytes += (double)nl(top - i) * 8.0;  // U written
+      const bool skipped = deep && i >= 1 && i + 1 < levels;
+      if (a.out[i] && !skipped) bytes += (double)nl(top - i) * 8.0;  // U written
     }
     const double nb = (double)a.n * 8.0;
     bytes += nb + (src_kind == kSrcInterp ? nb * 0.5 : src_kind == kSrcRestrict ? nb * 2.0 : nb);
@@ -356,21 +384,27 @@ struct Ctx {
 
   // Up leg over levels top-levels+1..top; result of the top level to out.
   // top_pre == nullptr: the top level is the SR level (full update + CR)
-  // rebuild_src != nullptr: the top level's pre-smoothed iterate is rebuilt
-  // from that FMG iterate of the level below (top_pre unused)
+  // Top level: sr_top: the SR level (full update from the level below and
+  // compatible relaxation); else rebuild_src != nullptr: its pre-smoothed
+  // iterate is rebuilt from that FMG iterate of the level below; else read
+  // from top_pre.  deep: levels top-1 .. top-levels+2 are rebuilt as well
+  // (from rebuild_src, also with sr_top).
   void up_launch(int top, int levels, const double* rhs, const double* coarse,
-                 const double* top_pre, double* out, const double* rebuild_src = nullptr) {
+                 const double* top_pre, double* out, const double* rebuild_src = nullptr,
+                 bool sr_top = false, bool deep = false) {
     VertArgs a = vargs(top, levels, p->nu2);
     a.rhs = rhs;
     a.coarse = coarse;
     a.src = rebuild_src;
     a.nu_pre = p->nu1;
-    if (rebuild_src) top_pre = nullptr;
-    a.sr_top = (top_pre == nullptr && rebuild_src == nullptr);
+    a.sr_top = sr_top;
+    a.deep = deep;
+    if (rebuild_src || sr_top) top_pre = nullptr;
     double bytes = rebuild_src ? (double)nl(top - 1) * 8.0 : 0.0;  // Pi source read
     for (int i = 0; i < levels; ++i) {
       a.pre[i] = (i == 0) ? top_pre : lv(U, top - i);
-      if (a.pre[i]) bytes += (double)nl(top - i) * 8.0;  // pre read
+      const bool rebuilt = deep && i + 1 < levels;
+      if (a.pre[i] && !rebuilt) bytes += (double)nl(top - i) * 8.0;  // pre read
     }
     bytes += (double)a.n * (out ? 16.0 : 8.0) + (double)nl(top - levels) * 8.0;  // rhs, out; coarse
     a.out[0] = out;
@@ -545,8 +579,19 @@ struct Ctx {
       // vertical down kernel whose level-M output is simply not stored; the
       // restricted iterate never goes through HBM.
       const bool fused_down = sr && t == M && P.fuse_down;
-      // the top up kernel rebuilds level t's pre-smoothed iterate
+      // one SR level with both passes inside the vertical kernels: a deep
+      // pair when both SR-topped kernels walk the same levels
+      const int dsr_n = std::min(P.d_srup, M - C);
+      const bool deep_sr = fused_down && P.fuse_up && !P.f32 && dsr_n == std::min(P.d_down, M - C) &&
+                           deep_fits(P.nu1, P.nu2, dsr_n, kTileHalo, true);
+      // the top up kernel rebuilds level t's pre-smoothed iterate, and with
+      // a deep pair the next levels' as well
       const bool rebuild = !sr && rebuild_top(P, t);
+      const int dtop_n = std::min(P.d_down, t - C);
+      // (not with FP32 relaxation: its up kernel runs one wavefront per SIMD
+      // and has no latency left to hide the extra sweeps in)
+      const bool deep_stored = rebuild && !P.f32 && dtop_n == std::min(P.d_up, t - C) &&
+                               deep_fits(P.nu1, P.nu2, dtop_n, kTileHalo, false);
       int top = t;  // highest stored level of this step
       int dtop = t;  // top of the vertical down leg
       if (sr && !fused_down) {
@@ -567,7 +612,8 @@ struct Ctx {
         else { src_kind = kSrcRestrict; src = U_of(hi + 1); }
         if (P.literal && src_kind == kSrcRestrict) tau_launch(U_of(hi + 1), rhs_of(hi + 1), hi, lv(Q, hi));
         const bool unstored = (fused_down && hi == M) || (rebuild && hi == t);
-        down_launch(hi, d, src_kind, src, rhs_of(hi), unstored ? nullptr : U_of(hi));
+        const bool deep = (hi == t) && (deep_stored || deep_sr);
+        down_launch(hi, d, src_kind, src, rhs_of(hi), unstored ? nullptr : U_of(hi), deep);
         hi -= d;
       }
       // coarse core: V-cycle bottom from level C
@@ -595,10 +641,12 @@ struct Ctx {
         const int lo = hi - d + 1;
         double* out = (hi == top && !sr) ? ((t == M) ? u_out : lv(V, t)) : lv(V, hi);
         const double* rsrc = (rebuild && hi == t) ? lv(V, t - 1) : nullptr;
-        up_launch(hi, d, rhs_of(hi), lv(V, lo - 1), U_of(hi), out, rsrc);
+        up_launch(hi, d, rhs_of(hi), lv(V, lo - 1), U_of(hi), out, rsrc, false,
+                  deep_stored && hi == t);
       }
       if (fused_up) {
-        up_launch(M, dsr, f, lv(V, M - dsr), nullptr, u_out);
+        up_launch(M, dsr, f, lv(V, M - dsr), nullptr, u_out, deep_sr ? lv(V, M - 1) : nullptr,
+                  true, deep_sr);
         if (functionals) {
           const int64_t tiles = (p->n + tile_core() - 1) / tile_core();
           ProfScope ps("k_functionals", (double)tiles * 16.0 + 16.0, st);

@@ -174,6 +174,11 @@ struct VertArgs {
                          // or nullptr
   double* out[kMaxFuse];        // down: U of each level (null: not stored);
                                 // up: out[0] = top result
+  int deep;              // a down / up pair over the same levels whose up
+                         // kernel rebuilds, on interior tiles, the pre-smoothed
+                         // iterates of levels 0..levels-2 from src (down:
+                         // those levels are stored only by tiles next to a
+                         // tile on the general path, whose up kernel reads them)
 };
 
 struct TileGeom {
@@ -224,6 +229,13 @@ __device__ __forceinline__ bool window_interior(int64_t wlo, int64_t cells, int6
   return wlo >= kInteriorMargin && wlo + cells + kInteriorMargin <= n;
 }
 
+// A deep pair's down kernel leaves out the levels between its top and its
+// bottom on interior tiles whose neighbours are interior too.
+__device__ __forceinline__ bool deep_skips(const VertArgs& a, int I, int64_t wlo0, int64_t wc) {
+  if (!a.deep || I == 0 || I + 1 >= a.levels) return false;
+  return window_interior(wlo0 - a.core, wc, a.n) && window_interior(wlo0 + a.core, wc, a.n);
+}
+
 template <int K, int I, bool F32>
 __device__ void down_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4, double (&u)[K],
                                 double (&f)[K], int64_t wlo0) {
@@ -234,7 +246,8 @@ __device__ void down_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4,
     if (more) fw_fast<K>(f, f1, x);
   half_scaled<K>(f, f, a.n >> I);
   smooth_fast<K, F32>(u, f, a.nu, x, x4);
-  if (a.out[I])  // null: an SR level, never stored (uniform per launch)
+  // null: a level never stored (uniform per launch)
+  if (a.out[I] && !deep_skips(a, I, wlo0, (int64_t)blockDim.x * (K << I)))
     store_run_fast<K>(st, u, a.out[I] + wlo, (int)(a.halo >> I), (int)((a.halo + a.core) >> I));
   if constexpr (I + 1 < kMaxFuse && K >= 4) {
     if (more) {
@@ -393,6 +406,58 @@ __device__ void up_level(const VertArgs& a, double* st, Xch& x, const double (&f
   smooth_general<K, F32>(u, f, G.g0, a.nu, G.lo, G.hi, G.n, a.gL, a.gR, x);
 }
 
+// Interior runs, fh = F h^2 / 2 of the level, c = its post-smoothed coarse
+// iterate.  SR top level (Eq. 5, Fig. 5): u = Pi c, then nu x [Kaczmarz onto
+// I^ u = c, sweep].
+template <int K, bool F32>
+__device__ __forceinline__ void sr_top_fast(const VertArgs& a, Xch& x, Xch4& x4, double (&fh)[K],
+                                            double (&u)[K], const double (&c)[K / 2]) {
+  double l1, r0, l2, r1;
+  x.swap(c[0], c[K / 2 - 1], l1, r0);
+  x.swap(c[1], c[K / 2 - 2], l2, r1);
+  double ec[K / 2 + 4];
+  ec[0] = l2;
+  ec[1] = l1;
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) ec[p + 2] = c[p];
+  ec[K / 2 + 2] = r0;
+  ec[K / 2 + 3] = r1;
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) {
+    u[2 * p] = interp_even(ec[p], ec[p + 1], ec[p + 2], ec[p + 3]);
+    u[2 * p + 1] = interp_odd(ec[p + 1], ec[p + 2], ec[p + 3], ec[p + 4]);
+  }
+  for (int it = 0; it < a.nu; ++it) {
+#pragma unroll
+    for (int p = 0; p < K / 2; ++p) {
+      const double r = c[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
+      u[2 * p] = u[2 * p] + r;
+      u[2 * p + 1] = u[2 * p + 1] + r;
+    }
+    smooth_fast<K, F32>(u, fh, 1, x, x4);
+  }
+}
+
+// Correction (Eq. 4) u = pre + P(c - I^ pre) of interior runs (u holds pre
+// on entry), then the post-sweeps.
+template <int K, bool F32>
+__device__ __forceinline__ void correct_fast(const VertArgs& a, Xch& x, Xch4& x4, double (&fh)[K],
+                                             double (&u)[K], const double (&c)[K / 2]) {
+  double e[K / 2];
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) e[p] = c[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
+  double el, er;
+  x.swap(e[0], e[K / 2 - 1], el, er);
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) {
+    const double em = (p == 0) ? el : e[p - 1];
+    const double ep = (p == K / 2 - 1) ? er : e[p + 1];
+    u[2 * p] = u[2 * p] + (3.0 * e[p] + em) * 0.25;
+    u[2 * p + 1] = u[2 * p + 1] + (3.0 * e[p] + ep) * 0.25;
+  }
+  smooth_fast<K, F32>(u, fh, a.nu, x, x4);
+}
+
 // tp holds this level's pre-smoothed iterate in flight (lane layout); the
 // coarser levels' loads are issued before descending, so every HBM read of
 // the kernel is outstanding at once.
@@ -418,33 +483,11 @@ __device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4, d
     stage_tmp<K / 2, true>(st, tc, c, 0);
   }
   half_scaled<K>(f, f, a.n >> I);
-  if (I == 0 && a.sr_top) {
-    // SR top level: u = Pi c, then nu x [Kaczmarz onto I^ u = c, sweep]
-    double l1, r0, l2, r1;
-    x.swap(c[0], c[K / 2 - 1], l1, r0);
-    x.swap(c[1], c[K / 2 - 2], l2, r1);
-    double ec[K / 2 + 4];
-    ec[0] = l2;
-    ec[1] = l1;
-#pragma unroll
-    for (int p = 0; p < K / 2; ++p) ec[p + 2] = c[p];
-    ec[K / 2 + 2] = r0;
-    ec[K / 2 + 3] = r1;
-#pragma unroll
-    for (int p = 0; p < K / 2; ++p) {
-      u[2 * p] = interp_even(ec[p], ec[p + 1], ec[p + 2], ec[p + 3]);
-      u[2 * p + 1] = interp_odd(ec[p + 1], ec[p + 2], ec[p + 3], ec[p + 4]);
+  if constexpr (I == 0) {
+    if (a.sr_top) {
+      sr_top_fast<K, F32>(a, x, x4, f, u, c);
+      return;
     }
-    for (int it = 0; it < a.nu; ++it) {
-#pragma unroll
-      for (int p = 0; p < K / 2; ++p) {
-        const double r = c[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
-        u[2 * p] = u[2 * p] + r;
-        u[2 * p + 1] = u[2 * p + 1] + r;
-      }
-      smooth_fast<K, F32>(u, f, 1, x, x4);
-    }
-    return;
   }
   bool rebuilt = false;
   if constexpr (I == 0) {
@@ -461,19 +504,60 @@ __device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4, d
     }
   }
   if (!rebuilt) stage_tmp<K, true>(st, tp, u, 0);
-  double e[K / 2];
+  correct_fast<K, F32>(a, x, x4, f, u, c);
+}
+
+// Deep pair, interior tile: level I < L - 1 of the up kernel, which first
+// redoes the down kernel's work on this level (the same window and code, so
+// the same bits wherever they reach the core): u enters with the level's
+// starting iterate (Pi on the top, I^ of the level above below it), f with
+// its right-hand side.  The bottom level L - 1 takes its pre-smoothed
+// iterate (tb) and the coarse iterate below it (tc) from HBM, loaded at the
+// start of the kernel.  u leaves with the level's post-smoothed iterate.
+template <int K, int I, int L, bool F32, int KB>
+__device__ void deep_level(const VertArgs& a, double* st, Xch& x, Xch4& x4, double (&f)[K],
+                           double (&u)[K], const double (&tb)[KB], const double (&tc)[KB / 2]) {
+  double f1[K / 2], c[K / 2];
+  fw_fast<K>(f, f1, x);
+  half_scaled<K>(f, f, a.n >> I);
+  smooth_fast<K, F32>(u, f, a.nu_pre, x, x4);  // the pre-smoothed iterate
 #pragma unroll
-  for (int p = 0; p < K / 2; ++p) e[p] = c[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
-  double el, er;
-  x.swap(e[0], e[K / 2 - 1], el, er);
-#pragma unroll
-  for (int p = 0; p < K / 2; ++p) {
-    const double em = (p == 0) ? el : e[p - 1];
-    const double ep = (p == K / 2 - 1) ? er : e[p + 1];
-    u[2 * p] = u[2 * p] + (3.0 * e[p] + em) * 0.25;
-    u[2 * p + 1] = u[2 * p + 1] + (3.0 * e[p] + ep) * 0.25;
+  for (int p = 0; p < K / 2; ++p) c[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
+  if constexpr (I + 2 < L) {
+    deep_level<K / 2, I + 1, L, F32, KB>(a, st, x, x4, f1, c, tb, tc);
+  } else {
+    static_assert(K / 2 == KB, "bottom run");
+    double cb[KB / 2];
+    stage_tmp<KB / 2, true>(st, tc, cb, 0);
+    half_scaled<KB>(f1, f1, a.n >> (I + 1));
+    stage_tmp<KB, true>(st, tb, c, 0);
+    correct_fast<KB, F32>(a, x, x4, f1, c, cb);
   }
-  smooth_fast<K, F32>(u, f, a.nu, x, x4);
+  // c: the post-smoothed iterate of level I + 1
+  if constexpr (I == 0) {
+    if (a.sr_top) {
+      sr_top_fast<K, F32>(a, x, x4, f, u, c);
+      return;
+    }
+  }
+  correct_fast<K, F32>(a, x, x4, f, u, c);
+}
+
+template <int K, int L, bool F32>
+__device__ __forceinline__ void deep_tile(const VertArgs& a, double* st, Xch& x, Xch4& x4,
+                                          double (&f)[K], double (&u)[K], int64_t wlo0) {
+  constexpr int KB = K >> (L - 1);
+  double tf[K], ts[K / 2], tb[KB], tc[KB / 2];
+  const double* cb = a.src + (wlo0 >> 1);
+  issue_loads<K, true>(tf, a.rhs + wlo0, 0);
+  issue_loads<K / 2, true>(ts, cb, 0);
+  issue_loads<KB, true>(tb, a.pre[L - 1] + (wlo0 >> (L - 1)), 0);
+  issue_loads<KB / 2, true>(tc, a.coarse + (wlo0 >> L), 0);
+  double cs[K / 2];
+  stage_tmp<K, true>(st, tf, f, 0);
+  stage_tmp<K / 2, true>(st, ts, cs, 0);
+  interp_fast<K>(u, cs, cb + threadIdx.x * (K / 2), x);
+  deep_level<K, 0, L, F32, KB>(a, st, x, x4, f, u, tb, tc);
 }
 
 // Sums of the core cells [a, b) of this thread's run (run-local indices),
@@ -522,17 +606,22 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
   const int64_t wlo0 = top_wlo(a);
   double u[K], f[K];
   if (window_interior(wlo0, wcount, a.n)) {
-    double tf[K], tp[K];
-    issue_loads<K, true>(tf, a.rhs + wlo0, 0);
-    if (a.src) {  // Pi source run of the rebuilt top level, in tp[0, K/2)
-      const double* cb = a.src + (wlo0 >> 1);
+    if (a.deep) {
+      if (a.levels == 4) deep_tile<K, 4, F32>(a, st, x, x4, f, u, wlo0);
+      else deep_tile<K, 3, F32>(a, st, x, x4, f, u, wlo0);
+    } else {
+      double tf[K], tp[K];
+      issue_loads<K, true>(tf, a.rhs + wlo0, 0);
+      if (a.src) {  // Pi source run of the rebuilt top level, in tp[0, K/2)
+        const double* cb = a.src + (wlo0 >> 1);
 #pragma unroll
-      for (int k = 0; k < K / 2; ++k) tp[k] = cb[threadIdx.x + k * kTileThreads];
-    } else if (!a.sr_top) {
-      issue_loads<K, true>(tp, a.pre[0] + wlo0, 0);
+        for (int k = 0; k < K / 2; ++k) tp[k] = cb[threadIdx.x + k * kTileThreads];
+      } else if (!a.sr_top) {
+        issue_loads<K, true>(tp, a.pre[0] + wlo0, 0);
+      }
+      stage_tmp<K, true>(st, tf, f, 0);
+      up_level_fast<K, 0, F32>(a, st, x, x4, f, u, tp, wlo0);
     }
-    stage_tmp<K, true>(st, tf, f, 0);
-    up_level_fast<K, 0, F32>(a, st, x, x4, f, u, tp, wlo0);
     if (a.out[0])  // null: functionals only, the fine solution is not written
       store_run_fast<K>(st, u, a.out[0] + wlo0, (int)a.halo, (int)(a.halo + a.core));
     if (a.part) {
