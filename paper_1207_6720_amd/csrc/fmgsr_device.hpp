@@ -138,6 +138,24 @@ struct Xch4 {
     r_second = r ? b[W + t + 1] : 0.0;
     r_extra = r ? b[3 * W + t + 1] : 0.0;
   }
+  // two cells on each side: the left neighbour's last two (l1 = its last)
+  // and the right neighbour's first two (r0 = its first)
+  __device__ void swap2(double c0, double c1, double cl1, double cl, double& l2, double& l1,
+                        double& r0, double& r1) {
+    const int W = blockDim.x, t = threadIdx.x;
+    double* b = buf + (sel ? 4 * W : 0);
+    sel ^= 1;
+    b[t] = c0;
+    b[W + t] = c1;
+    b[2 * W + t] = cl1;
+    b[3 * W + t] = cl;
+    __syncthreads();
+    const bool l = (t > 0), r = (t + 1 < W);
+    l2 = l ? b[2 * W + t - 1] : 0.0;
+    l1 = l ? b[3 * W + t - 1] : 0.0;
+    r0 = r ? b[t + 1] : 0.0;
+    r1 = r ? b[W + t + 1] : 0.0;
+  }
 };
 
 // Per-run bounds in 32-bit local indices (0..K): updatable cells [jlo, jhi)
@@ -438,10 +456,13 @@ __device__ __forceinline__ void stage_tmp(double* st, const double (&tmp)[K], do
   __syncthreads();
 }
 
-// Registers -> coalesced store of window cells [clo, chi) to base.
+// Registers -> coalesced store of window cells [clo, chi) to base.  trail =
+// false leaves out the closing barrier: only for the workgroup's last use of
+// the stage, or when a barrier comes before its next write.
 template <int K>
 __device__ __forceinline__ void store_run_fast(double* st, const double (&v)[K],
-                                               double* __restrict__ base, int clo, int chi) {
+                                               double* __restrict__ base, int clo, int chi,
+                                               bool trail = true) {
   const int W = blockDim.x;
   run_to_stage<K>(st, v);
   __syncthreads();
@@ -450,18 +471,32 @@ __device__ __forceinline__ void store_run_fast(double* st, const double (&v)[K],
     const int e = threadIdx.x + k * W;
     if (e >= clo && e < chi) base[e] = st[sidx<K>(e)];
   }
+  if (trail) __syncthreads();
+}
+
+// Two windows staged at once (kAll layout of issue_loads) through two stage
+// buffers, with one barrier and no closing one: the caller's next step must
+// be an exchange (whose barrier orders these reads before any later write).
+template <int K1, int K2>
+__device__ __forceinline__ void stage_two(double* st1, const double (&t1)[K1], double (&v1)[K1],
+                                          double* st2, const double (&t2)[K2], double (&v2)[K2]) {
+  const int W = blockDim.x;
+#pragma unroll
+  for (int k = 0; k < K1; ++k) st1[sidx<K1>(threadIdx.x + k * W)] = t1[k];
+#pragma unroll
+  for (int k = 0; k < K2; ++k) st2[sidx<K2>(threadIdx.x + k * W)] = t2[k];
   __syncthreads();
+  stage_to_run<K1>(st1, v1);
+  stage_to_run<K2>(st2, v2);
 }
 
 // Pi from the coarse run c (cells J0..J0+K/2-1 of this thread, cbase =
 // address of J0 in HBM): two coarse cells on each side from the neighbours,
 // from HBM at the window edges.  No boundary cases.
 template <int K>
-__device__ __forceinline__ void interp_fast(double (&u)[K], const double (&c)[K / 2],
-                                            const double* __restrict__ cbase, Xch& x) {
-  double l1, r0, l2, r1;
-  x.swap(c[0], c[K / 2 - 1], l1, r0);
-  x.swap(c[1], c[K / 2 - 2], l2, r1);
+__device__ __forceinline__ void interp_ring(double (&u)[K], const double (&c)[K / 2],
+                                            const double* __restrict__ cbase, double l2,
+                                            double l1, double r0, double r1) {
   if (threadIdx.x == 0) { l2 = cbase[-2]; l1 = cbase[-1]; }
   if (threadIdx.x == blockDim.x - 1) { r0 = cbase[K / 2]; r1 = cbase[K / 2 + 1]; }
   double e[K / 2 + 4];
@@ -476,6 +511,22 @@ __device__ __forceinline__ void interp_fast(double (&u)[K], const double (&c)[K 
     u[2 * p] = interp_even(e[p], e[p + 1], e[p + 2], e[p + 3]);
     u[2 * p + 1] = interp_odd(e[p + 1], e[p + 2], e[p + 3], e[p + 4]);
   }
+}
+template <int K>
+__device__ __forceinline__ void interp_fast(double (&u)[K], const double (&c)[K / 2],
+                                            const double* __restrict__ cbase, Xch& x) {
+  double l1, r0, l2, r1;
+  x.swap(c[0], c[K / 2 - 1], l1, r0);
+  x.swap(c[1], c[K / 2 - 2], l2, r1);
+  interp_ring<K>(u, c, cbase, l2, l1, r0, r1);
+}
+// The same with one exchange of two cells per side.
+template <int K>
+__device__ __forceinline__ void interp_fast(double (&u)[K], const double (&c)[K / 2],
+                                            const double* __restrict__ cbase, Xch4& x4) {
+  double l2, l1, r0, r1;
+  x4.swap2(c[0], c[1], c[K / 2 - 2], c[K / 2 - 1], l2, l1, r0, r1);
+  interp_ring<K>(u, c, cbase, l2, l1, r0, r1);
 }
 
 // Full weighting of a run (no boundary cases).

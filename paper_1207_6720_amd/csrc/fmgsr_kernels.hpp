@@ -248,7 +248,8 @@ __device__ void down_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4,
   smooth_fast<K, F32>(u, f, a.nu, x, x4);
   // null: a level never stored (uniform per launch)
   if (a.out[I] && !deep_skips(a, I, wlo0, (int64_t)blockDim.x * (K << I)))
-    store_run_fast<K>(st, u, a.out[I] + wlo, (int)(a.halo >> I), (int)((a.halo + a.core) >> I));
+    store_run_fast<K>(st, u, a.out[I] + wlo, (int)(a.halo >> I), (int)((a.halo + a.core) >> I),
+                      more);  // the last level's store is the stage's last use
   if constexpr (I + 1 < kMaxFuse && K >= 4) {
     if (more) {
       double u1[K / 2];
@@ -266,6 +267,7 @@ __device__ void down_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4,
 template <int K, bool F32>
 __global__ __launch_bounds__(kTileThreads) void k_down(VertArgs a) {
   __shared__ double st[kTileThreads * (K + 1)];
+  __shared__ double st2[kTileThreads * (K / 2 + 1)];
   __shared__ double xb[4 * kTileThreads];
   __shared__ double xb4[8 * kTileThreads];
   Xch x{xb, 0};
@@ -280,9 +282,8 @@ __global__ __launch_bounds__(kTileThreads) void k_down(VertArgs a) {
       const double* cb = a.src + (wlo0 >> 1);
       double tc[K / 2], c[K / 2];
       issue_loads<K / 2, true>(tc, cb, 0);
-      stage_tmp<K, true>(st, tf, f, 0);
-      stage_tmp<K / 2, true>(st, tc, c, 0);
-      interp_fast<K>(u, c, cb + threadIdx.x * (K / 2), x);
+      stage_two<K, K / 2>(st, tf, f, st2, tc, c);
+      interp_fast<K>(u, c, cb + threadIdx.x * (K / 2), x4);
     } else if (a.src_kind == kSrcRestrict) {
       const double2* fb = reinterpret_cast<const double2*>(a.src) + wlo0;
       double tu[K];
@@ -412,9 +413,8 @@ __device__ void up_level(const VertArgs& a, double* st, Xch& x, const double (&f
 template <int K, bool F32>
 __device__ __forceinline__ void sr_top_fast(const VertArgs& a, Xch& x, Xch4& x4, double (&fh)[K],
                                             double (&u)[K], const double (&c)[K / 2]) {
-  double l1, r0, l2, r1;
-  x.swap(c[0], c[K / 2 - 1], l1, r0);
-  x.swap(c[1], c[K / 2 - 2], l2, r1);
+  double l2, l1, r0, r1;
+  x4.swap2(c[0], c[1], c[K / 2 - 2], c[K / 2 - 1], l2, l1, r0, r1);
   double ec[K / 2 + 4];
   ec[0] = l2;
   ec[1] = l1;
@@ -498,7 +498,7 @@ __device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4, d
 #pragma unroll
       for (int k = 0; k < K / 2; ++k) tc[k] = tp[k];
       stage_tmp<K / 2, true>(st, tc, cs, 0);
-      interp_fast<K>(u, cs, cb + threadIdx.x * (K / 2), x);
+      interp_fast<K>(u, cs, cb + threadIdx.x * (K / 2), x4);
       smooth_fast<K, F32>(u, f, a.nu_pre, x, x4);
       rebuilt = true;
     }
@@ -528,9 +528,8 @@ __device__ void deep_level(const VertArgs& a, double* st, Xch& x, Xch4& x4, doub
   } else {
     static_assert(K / 2 == KB, "bottom run");
     double cb[KB / 2];
-    stage_tmp<KB / 2, true>(st, tc, cb, 0);
     half_scaled<KB>(f1, f1, a.n >> (I + 1));
-    stage_tmp<KB, true>(st, tb, c, 0);
+    stage_two<KB, KB / 2>(st, tb, c, st + kTileThreads * (KB + 1), tc, cb);
     correct_fast<KB, F32>(a, x, x4, f1, c, cb);
   }
   // c: the post-smoothed iterate of level I + 1
@@ -544,8 +543,8 @@ __device__ void deep_level(const VertArgs& a, double* st, Xch& x, Xch4& x4, doub
 }
 
 template <int K, int L, bool F32>
-__device__ __forceinline__ void deep_tile(const VertArgs& a, double* st, Xch& x, Xch4& x4,
-                                          double (&f)[K], double (&u)[K], int64_t wlo0) {
+__device__ __forceinline__ void deep_tile(const VertArgs& a, double* st, double* st2, Xch& x,
+                                          Xch4& x4, double (&f)[K], double (&u)[K], int64_t wlo0) {
   constexpr int KB = K >> (L - 1);
   double tf[K], ts[K / 2], tb[KB], tc[KB / 2];
   const double* cb = a.src + (wlo0 >> 1);
@@ -554,9 +553,8 @@ __device__ __forceinline__ void deep_tile(const VertArgs& a, double* st, Xch& x,
   issue_loads<KB, true>(tb, a.pre[L - 1] + (wlo0 >> (L - 1)), 0);
   issue_loads<KB / 2, true>(tc, a.coarse + (wlo0 >> L), 0);
   double cs[K / 2];
-  stage_tmp<K, true>(st, tf, f, 0);
-  stage_tmp<K / 2, true>(st, ts, cs, 0);
-  interp_fast<K>(u, cs, cb + threadIdx.x * (K / 2), x);
+  stage_two<K, K / 2>(st, tf, f, st2, ts, cs);
+  interp_fast<K>(u, cs, cb + threadIdx.x * (K / 2), x4);
   deep_level<K, 0, L, F32, KB>(a, st, x, x4, f, u, tb, tc);
 }
 
@@ -598,6 +596,7 @@ __device__ __forceinline__ void segment_sums(const double (&u)[K], int a, int b,
 template <int K, bool F32>
 __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
   __shared__ double st[kTileThreads * (K + 1)];
+  __shared__ double st2[kTileThreads * (K / 2 + 1)];
   __shared__ double xb[4 * kTileThreads];
   __shared__ double xb4[8 * kTileThreads];
   Xch x{xb, 0};
@@ -607,8 +606,8 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
   double u[K], f[K];
   if (window_interior(wlo0, wcount, a.n)) {
     if (a.deep) {
-      if (a.levels == 4) deep_tile<K, 4, F32>(a, st, x, x4, f, u, wlo0);
-      else deep_tile<K, 3, F32>(a, st, x, x4, f, u, wlo0);
+      if (a.levels == 4) deep_tile<K, 4, F32>(a, st, st2, x, x4, f, u, wlo0);
+      else deep_tile<K, 3, F32>(a, st, st2, x, x4, f, u, wlo0);
     } else {
       double tf[K], tp[K];
       issue_loads<K, true>(tf, a.rhs + wlo0, 0);
@@ -623,7 +622,8 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
       up_level_fast<K, 0, F32>(a, st, x, x4, f, u, tp, wlo0);
     }
     if (a.out[0])  // null: functionals only, the fine solution is not written
-      store_run_fast<K>(st, u, a.out[0] + wlo0, (int)a.halo, (int)(a.halo + a.core));
+      store_run_fast<K>(st, u, a.out[0] + wlo0, (int)a.halo, (int)(a.halo + a.core),
+                        false);  // segment_sums opens with a barrier
     if (a.part) {
       const int e0 = (int)threadIdx.x * K;
       segment_sums<K>(u, (int)a.halo - e0, (int)(a.halo + a.core) - e0, st, a.part);
