@@ -127,6 +127,11 @@ bool sr_up_fits(int nu, int d, int64_t halo) {
   return halo >= inv;
 }
 
+// Down launches of at least this many tiles take the three-workgroup kernel
+// (a full chip of them and more); smaller ones are bound by one workgroup's
+// latency, which its spills would lengthen.
+constexpr int64_t kDownWideTiles = 768;
+
 // Up kernel that rebuilds its top level's pre-smoothed iterate (Pi of the
 // level below's FMG iterate, then the down leg's nu1 sweeps) instead of
 // reading it: the rebuild is stale in 2 nu1 cells plus Pi's two-cell reach,
@@ -377,8 +382,12 @@ struct Ctx {
     bytes += nb + (src_kind == kSrcInterp ? nb * 0.5 : src_kind == kSrcRestrict ? nb * 2.0 : nb);
     const int64_t blocks = (a.n + a.core - 1) / a.core;
     ProfScope ps("k_down", bytes, st);
-    if (p->f32) hipLaunchKernelGGL((k_down<kRun, true>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
-    else hipLaunchKernelGGL((k_down<kRun, false>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+    const dim3 g((unsigned)blocks), b(kTileThreads);
+    const bool wide = blocks >= kDownWideTiles;
+    if (p->f32 && wide) hipLaunchKernelGGL((k_down<kRun, true, 3>), g, b, 0, st, a);
+    else if (p->f32) hipLaunchKernelGGL((k_down<kRun, true, 2>), g, b, 0, st, a);
+    else if (wide) hipLaunchKernelGGL((k_down<kRun, false, 3>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_down<kRun, false, 2>), g, b, 0, st, a);
     check();
   }
 

@@ -909,7 +909,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_batched(Args a) {
   extern __shared__ double lds[];
   double* st = lds;                                  // a.region >= T (K + 1) doubles
   double* red = lds + a.region;                      // 32 doubles
-  Xch x{red + 32, 0};                                // 4 T doubles
+  Xch x{red + 32, 0, 2 * (int)blockDim.x};  // 4 T doubles
   __shared__ int next;
   for (;;) {
     // slot -> (queue position, member): the G members of a problem are

@@ -82,11 +82,12 @@ __device__ __forceinline__ double relax(double fj, double l, double r, int64_t g
 // buffers are used alternately, so one barrier per exchange suffices.
 // ---------------------------------------------------------------------------
 struct Xch {
-  double* buf;  // 4 * W doubles
+  double* buf;  // two halves of `half` doubles
   int sel;
+  int half;     // >= 2 W for two-value exchanges, >= 4 W for four-value ones
   __device__ void swap(double first, double last, double& left_last, double& right_first) {
     const int W = blockDim.x, t = threadIdx.x;
-    double* b = buf + (sel ? 2 * W : 0);
+    double* b = buf + (sel ? half : 0);
     sel ^= 1;
     b[t] = first;
     b[W + t] = last;
@@ -96,8 +97,8 @@ struct Xch {
   }
   // one value only: the left neighbour's `mine` (0 for the first thread)
   __device__ double from_left(double mine) {
-    const int W = blockDim.x, t = threadIdx.x;
-    double* b = buf + (sel ? 2 * W : 0);
+    const int t = threadIdx.x;
+    double* b = buf + (sel ? half : 0);
     sel ^= 1;
     b[t] = mine;
     __syncthreads();
@@ -106,26 +107,21 @@ struct Xch {
   // the right neighbour's `mine` (0 for the last thread)
   __device__ double from_right(double mine) {
     const int W = blockDim.x, t = threadIdx.x;
-    double* b = buf + (sel ? 2 * W : 0);
+    double* b = buf + (sel ? half : 0);
     sel ^= 1;
     b[t] = mine;
     __syncthreads();
     return (t + 1 < W) ? b[t + 1] : 0.0;
   }
-};
 
-// Exchange of four values per thread, for sweeps with one exchange each:
-// every thread publishes (first, second, last, extra) and reads its left
-// neighbour's last and its right neighbour's first, second and extra (0 at
-// the workgroup edges).  Two halves of 4 W doubles alternate, so one barrier
-// per exchange suffices.
-struct Xch4 {
-  double* buf;  // 8 * W doubles
-  int sel;
+  // Exchange of four values per thread, for sweeps with one exchange each:
+  // every thread publishes (first, second, last, extra) and reads its left
+  // neighbour's last and its right neighbour's first, second and extra (0 at
+  // the workgroup edges).
   __device__ void swap(double first, double second, double last, double extra, double& l_last,
                        double& r_first, double& r_second, double& r_extra) {
     const int W = blockDim.x, t = threadIdx.x;
-    double* b = buf + (sel ? 4 * W : 0);
+    double* b = buf + (sel ? half : 0);
     sel ^= 1;
     b[t] = first;
     b[W + t] = second;
@@ -143,7 +139,7 @@ struct Xch4 {
   __device__ void swap2(double c0, double c1, double cl1, double cl, double& l2, double& l1,
                         double& r0, double& r1) {
     const int W = blockDim.x, t = threadIdx.x;
-    double* b = buf + (sel ? 4 * W : 0);
+    double* b = buf + (sel ? half : 0);
     sel ^= 1;
     b[t] = c0;
     b[W + t] = c1;
@@ -157,6 +153,10 @@ struct Xch4 {
     r1 = r ? b[W + t + 1] : 0.0;
   }
 };
+// The four-value role of the same exchanger.  A kernel may also pass one
+// object in both roles: consecutive exchanges of either kind then alternate
+// between the two halves, which keeps one barrier per exchange enough.
+using Xch4 = Xch;
 
 // Per-run bounds in 32-bit local indices (0..K): updatable cells [jlo, jhi)
 // and the run positions of the first and last cell of the level (-1 if the
@@ -520,10 +520,10 @@ __device__ __forceinline__ void interp_fast(double (&u)[K], const double (&c)[K 
   x.swap(c[1], c[K / 2 - 2], l2, r1);
   interp_ring<K>(u, c, cbase, l2, l1, r0, r1);
 }
-// The same with one exchange of two cells per side.
+// The same with one exchange of two cells per side (halves of >= 4 W).
 template <int K>
-__device__ __forceinline__ void interp_fast(double (&u)[K], const double (&c)[K / 2],
-                                            const double* __restrict__ cbase, Xch4& x4) {
+__device__ __forceinline__ void interp_fast1(double (&u)[K], const double (&c)[K / 2],
+                                             const double* __restrict__ cbase, Xch4& x4) {
   double l2, l1, r0, r1;
   x4.swap2(c[0], c[1], c[K / 2 - 2], c[K / 2 - 1], l2, l1, r0, r1);
   interp_ring<K>(u, c, cbase, l2, l1, r0, r1);

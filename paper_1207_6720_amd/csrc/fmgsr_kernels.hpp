@@ -264,14 +264,17 @@ __device__ void down_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4,
 // then restrict + smooth of the pre-smoothing leg), split tau: the coarse
 // right-hand side is the full weighting of the finer one (the Laplacian
 // part of tau is identically zero with I^ = average, I = full weighting).
-template <int K, bool F32>
-__global__ __launch_bounds__(kTileThreads) void k_down(VertArgs a) {
+// OCC workgroups per CU: 3 (at most 168 VGPRs, a few spilled; 51 KB of LDS)
+// for launches of many tiles, 2 (no spills; a second stage buffer lets the
+// rhs and the interpolation source share one barrier) for the latency-bound
+// small ones.
+template <int K, bool F32, int OCC>
+__global__ __launch_bounds__(kTileThreads, OCC) void k_down(VertArgs a) {
   __shared__ double st[kTileThreads * (K + 1)];
-  __shared__ double st2[kTileThreads * (K / 2 + 1)];
-  __shared__ double xb[4 * kTileThreads];
-  __shared__ double xb4[8 * kTileThreads];
-  Xch x{xb, 0};
-  Xch4 x4{xb4, 0};
+  __shared__ double st2[OCC == 2 ? kTileThreads * (K / 2 + 1) : 1];
+  __shared__ double xb[8 * kTileThreads];
+  Xch x{xb, 0, 4 * kTileThreads};
+  Xch4& x4 = x;  // one exchanger in both roles
   const int wcount = kTileThreads * K;
   const int64_t wlo0 = top_wlo(a);
   double u[K], f[K];
@@ -282,8 +285,13 @@ __global__ __launch_bounds__(kTileThreads) void k_down(VertArgs a) {
       const double* cb = a.src + (wlo0 >> 1);
       double tc[K / 2], c[K / 2];
       issue_loads<K / 2, true>(tc, cb, 0);
-      stage_two<K, K / 2>(st, tf, f, st2, tc, c);
-      interp_fast<K>(u, c, cb + threadIdx.x * (K / 2), x4);
+      if constexpr (OCC == 2) {
+        stage_two<K, K / 2>(st, tf, f, st2, tc, c);
+      } else {
+        stage_tmp<K, true>(st, tf, f, 0);
+        stage_tmp<K / 2, true>(st, tc, c, 0);
+      }
+      interp_fast1<K>(u, c, cb + threadIdx.x * (K / 2), x4);
     } else if (a.src_kind == kSrcRestrict) {
       const double2* fb = reinterpret_cast<const double2*>(a.src) + wlo0;
       double tu[K];
@@ -498,7 +506,7 @@ __device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4, d
 #pragma unroll
       for (int k = 0; k < K / 2; ++k) tc[k] = tp[k];
       stage_tmp<K / 2, true>(st, tc, cs, 0);
-      interp_fast<K>(u, cs, cb + threadIdx.x * (K / 2), x4);
+      interp_fast1<K>(u, cs, cb + threadIdx.x * (K / 2), x4);
       smooth_fast<K, F32>(u, f, a.nu_pre, x, x4);
       rebuilt = true;
     }
@@ -554,7 +562,7 @@ __device__ __forceinline__ void deep_tile(const VertArgs& a, double* st, double*
   issue_loads<KB / 2, true>(tc, a.coarse + (wlo0 >> L), 0);
   double cs[K / 2];
   stage_two<K, K / 2>(st, tf, f, st2, ts, cs);
-  interp_fast<K>(u, cs, cb + threadIdx.x * (K / 2), x4);
+  interp_fast1<K>(u, cs, cb + threadIdx.x * (K / 2), x4);
   deep_level<K, 0, L, F32, KB>(a, st, x, x4, f, u, tb, tc);
 }
 
@@ -599,8 +607,8 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
   __shared__ double st2[kTileThreads * (K / 2 + 1)];
   __shared__ double xb[4 * kTileThreads];
   __shared__ double xb4[8 * kTileThreads];
-  Xch x{xb, 0};
-  Xch4 x4{xb4, 0};
+  Xch x{xb, 0, 2 * kTileThreads};
+  Xch4 x4{xb4, 0, 4 * kTileThreads};
   const int wcount = kTileThreads * K;
   const int64_t wlo0 = top_wlo(a);
   double u[K], f[K];
@@ -680,7 +688,7 @@ template <int K>
 __global__ __launch_bounds__(kTileThreads) void k_forcing(VertArgs a) {
   __shared__ double st[kTileThreads * (K + 1)];
   __shared__ double xb[4 * kTileThreads];
-  Xch x{xb, 0};
+  Xch x{xb, 0, 2 * kTileThreads};
   const int64_t wlo0 = top_wlo(a);
   double f[K];
   if (window_interior(wlo0, kTileThreads * K, a.n)) {
@@ -759,7 +767,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
   extern __shared__ double sm[];
   const int W = blockDim.x;
   double* st = sm;                   // W (K+1)
-  Xch x{sm + W * (K + 1), 0};        // 4 W
+  Xch x{sm + W * (K + 1), 0, 2 * W};        // 4 W
   const int64_t n = a.n, nc = n >> 1;
   const int64_t seg = blockIdx.x;
   const int64_t core_lo = seg * a.s, core_hi = core_lo + a.s;
@@ -786,7 +794,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
     }
     half_scaled<K>(f, f, n);
     const RunBounds rb = run_bounds(g0, K, lo, hi, n);
-    Xch4 x4{st, 0};  // the stage is idle during the sweeps (8 W <= W (K + 1) doubles)
+    Xch4 x4{st, 0, 4 * W};  // the stage is idle during the sweeps (8 W <= W (K + 1) doubles)
     smooth_masked<K, F32>(u, f, a.nu, rb.jlo, rb.jhi, g0 + K >= lo && g0 + K < hi, x, x4);
     __syncthreads();  // last exchange read before the stage is reused
     double uc[K / 2];
@@ -853,7 +861,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
   extern __shared__ double sm[];
   const int W = blockDim.x;
   double* st = sm;
-  Xch x{sm + W * (K + 1), 0};
+  Xch x{sm + W * (K + 1), 0, 2 * W};
   const int64_t n = a.n, nc = n >> 1;
   const int64_t seg = blockIdx.x;
   const int64_t core_lo = seg * a.s, core_hi = core_lo + a.s;
@@ -874,7 +882,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
     const RunBounds rb = run_bounds(g0, K, lo, hi, n);
     const bool all = (rb.jlo == 0 && rb.jhi == K);
     const bool nb_upd = g0 + K >= lo && g0 + K < hi;
-    Xch4 x4{st, 0};  // the stage is idle during the sweeps (8 W <= W (K + 1) doubles)
+    Xch4 x4{st, 0, 4 * W};  // the stage is idle during the sweeps (8 W <= W (K + 1) doubles)
     for (int it = 0; it < a.nu; ++it) {
       if (all) {
 #pragma unroll
@@ -1029,7 +1037,7 @@ __device__ void sr2_up_interior(const Seg2Args& a, double* st, Xch& x) {
   stage_tmp<K1 / 2, false>(st, tc, c2, a.win1 / 2 + 2);
   interp_fast<K1>(u0, c2, cb + threadIdx.x * (K1 / 2), x);
   half_scaled<K1>(F1, F1, n1);
-  Xch4 x4{st, 0};  // the stage is idle during the sweeps (8 W <= W (K + 1) doubles)
+  Xch4 x4{st, 0, 4 * W};  // the stage is idle during the sweeps (8 W <= W (K + 1) doubles)
 #pragma unroll
   for (int j = 0; j < K1; ++j) v1[j] = u0[j];
   for (int r = -a.R; r <= a.R; ++r) {
@@ -1106,7 +1114,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr2(Seg2Args a) {
   extern __shared__ double sm[];
   const int W = blockDim.x;
   double* st = sm;                   // W (K+1)
-  Xch x{sm + W * (K + 1), 0};        // 4 W
+  Xch x{sm + W * (K + 1), 0, 2 * W};        // 4 W
   const int64_t n = a.n, n1 = n >> 1, n2 = n >> 2;
   const int64_t seg = blockIdx.x;
   const int64_t s1 = a.s >> 1;
