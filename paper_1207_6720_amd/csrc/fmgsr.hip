@@ -131,6 +131,9 @@ bool sr_up_fits(int nu, int d, int64_t halo) {
 // (a full chip of them and more); smaller ones are bound by one workgroup's
 // latency, which its spills would lengthen.
 constexpr int64_t kDownWideTiles = 768;
+// Deep up launches of at least this many tiles run their interior tiles on
+// the three-workgroup kernel (one more launch for the edge tiles).
+constexpr int64_t kUpWideTiles = 768;
 
 // Up kernel that rebuilds its top level's pre-smoothed iterate (Pi of the
 // level below's FMG iterate, then the down leg's nu1 sweeps) instead of
@@ -420,9 +423,44 @@ struct Ctx {
     if (a.sr_top && functionals) a.part = P;
     const int64_t blocks = (a.n + a.core - 1) / a.core;
     ProfScope ps("k_up", bytes, st);
-    if (p->f32) hipLaunchKernelGGL((k_up<kRun, true>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
-    else hipLaunchKernelGGL((k_up<kRun, false>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+    int64_t b_lo = 0, b_hi = -1;
+    if (deep && !p->f32 && blocks >= kUpWideTiles) interior_tiles(a, &b_lo, &b_hi);
+    if (b_hi >= b_lo) {
+      // interior tiles on the three-workgroup kernel, the edge tiles on k_up
+      VertArgs w = a;
+      w.tile0 = b_lo;
+      hipLaunchKernelGGL((k_up_wide<kRun, false>), dim3((unsigned)(b_hi - b_lo + 1)), dim3(kTileThreads), 0,
+                         st, w);
+      VertArgs e = a;
+      e.gap_at = b_lo;
+      e.gap = b_hi - b_lo + 1;
+      hipLaunchKernelGGL((k_up<kRun, false>), dim3((unsigned)(blocks - e.gap)), dim3(kTileThreads), 0, st, e);
+    } else if (p->f32) {
+      hipLaunchKernelGGL((k_up<kRun, true>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+    } else {
+      hipLaunchKernelGGL((k_up<kRun, false>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+    }
     check();
+  }
+
+  // The tiles whose window lies inside the level (window_interior on the
+  // device), [b_lo, b_hi]; empty when b_hi < b_lo.
+  static void interior_tiles(const VertArgs& a, int64_t* b_lo, int64_t* b_hi) {
+    const int64_t wc = (int64_t)kTileThreads * kRun;
+    auto inside = [&](int64_t b) {
+      const int64_t wlo = b * a.core - a.halo;
+      return b >= 0 && wlo >= kInteriorMargin && wlo + wc + kInteriorMargin <= a.n;
+    };
+    int64_t lo = (kInteriorMargin + a.halo + a.core - 1) / a.core;
+    int64_t hi = (a.n - wc - kInteriorMargin + a.halo) >= 0 ? (a.n - wc - kInteriorMargin + a.halo) / a.core : -1;
+    // the closed forms, checked against the predicate itself
+    if (hi < lo || !inside(lo) || inside(lo - 1) || !inside(hi) || inside(hi + 1)) {
+      *b_lo = 0;
+      *b_hi = -1;
+      return;
+    }
+    *b_lo = lo;
+    *b_hi = hi;
   }
 
   // Forcing of levels src_level-1 .. src_level-levels from level src_level.

@@ -174,6 +174,9 @@ struct VertArgs {
                          // or nullptr
   double* out[kMaxFuse];        // down: U of each level (null: not stored);
                                 // up: out[0] = top result
+  // tile of workgroup b: tile0 + b, plus gap from b = gap_at on (a launch
+  // over a subset of the tiles); tile: the result, set by the kernel
+  int64_t tile0, gap_at, gap, tile;
   int deep;              // a down / up pair over the same levels whose up
                          // kernel rebuilds, on interior tiles, the pre-smoothed
                          // iterates of levels 0..levels-2 from src (down:
@@ -193,13 +196,13 @@ __device__ __forceinline__ TileGeom tile_geom(const VertArgs& a, int i, int K) {
   TileGeom g;
   g.n = a.n >> i;
   const int64_t W = blockDim.x;
-  g.wlo = ((int64_t)blockIdx.x * a.core - a.halo) >> i;
+  g.wlo = (a.tile * a.core - a.halo) >> i;
   const int64_t whi = g.wlo + W * K;
   g.g0 = g.wlo + (int64_t)threadIdx.x * K;
   g.lo = g.wlo <= 0 ? 0 : g.wlo + 1;
   g.hi = whi >= g.n ? g.n : whi - 1;
-  g.clo = ((int64_t)blockIdx.x * a.core) >> i;
-  const int64_t c1 = ((int64_t)blockIdx.x * a.core + a.core) >> i;
+  g.clo = (a.tile * a.core) >> i;
+  const int64_t c1 = (a.tile * a.core + a.core) >> i;
   g.chi = c1 < g.n ? c1 : g.n;
   return g;
 }
@@ -221,9 +224,14 @@ __device__ void down_level(const VertArgs& a, double* st, Xch& x, double (&u)[K]
 
 constexpr int64_t kInteriorMargin = 4 << kMaxFuse;  // cells kept from the domain ends
 
+__device__ __forceinline__ int64_t tile_index(const VertArgs& a) {
+  const int64_t b = blockIdx.x;
+  return a.tile0 + b + (b >= a.gap_at ? a.gap : 0);
+}
+
 // Window of this workgroup on the top level: [wlo, wlo + W K).
 __device__ __forceinline__ int64_t top_wlo(const VertArgs& a) {
-  return (int64_t)blockIdx.x * a.core - a.halo;
+  return a.tile * a.core - a.halo;
 }
 __device__ __forceinline__ bool window_interior(int64_t wlo, int64_t cells, int64_t n) {
   return wlo >= kInteriorMargin && wlo + cells + kInteriorMargin <= n;
@@ -276,6 +284,7 @@ __global__ __launch_bounds__(kTileThreads, OCC) void k_down(VertArgs a) {
   Xch x{xb, 0, 4 * kTileThreads};
   Xch4& x4 = x;  // one exchanger in both roles
   const int wcount = kTileThreads * K;
+  a.tile = tile_index(a);
   const int64_t wlo0 = top_wlo(a);
   double u[K], f[K];
   if (window_interior(wlo0, wcount, a.n)) {
@@ -550,7 +559,9 @@ __device__ void deep_level(const VertArgs& a, double* st, Xch& x, Xch4& x4, doub
   correct_fast<K, F32>(a, x, x4, f, u, c);
 }
 
-template <int K, int L, bool F32>
+// kSt2: stage the rhs and the interpolation source at once through st and
+// st2; else one after the other through st.
+template <int K, int L, bool F32, bool kSt2>
 __device__ __forceinline__ void deep_tile(const VertArgs& a, double* st, double* st2, Xch& x,
                                           Xch4& x4, double (&f)[K], double (&u)[K], int64_t wlo0) {
   constexpr int KB = K >> (L - 1);
@@ -561,7 +572,12 @@ __device__ __forceinline__ void deep_tile(const VertArgs& a, double* st, double*
   issue_loads<KB, true>(tb, a.pre[L - 1] + (wlo0 >> (L - 1)), 0);
   issue_loads<KB / 2, true>(tc, a.coarse + (wlo0 >> L), 0);
   double cs[K / 2];
-  stage_two<K, K / 2>(st, tf, f, st2, ts, cs);
+  if constexpr (kSt2) {
+    stage_two<K, K / 2>(st, tf, f, st2, ts, cs);
+  } else {
+    stage_tmp<K, true>(st, tf, f, 0);
+    stage_tmp<K / 2, true>(st, ts, cs, 0);
+  }
   interp_fast1<K>(u, cs, cb + threadIdx.x * (K / 2), x4);
   deep_level<K, 0, L, F32, KB>(a, st, x, x4, f, u, tb, tc);
 }
@@ -569,7 +585,7 @@ __device__ __forceinline__ void deep_tile(const VertArgs& a, double* st, double*
 // Sums of the core cells [a, b) of this thread's run (run-local indices),
 // in cell order, then over each wavefront by a fixed shuffle tree, then over
 // the wavefronts in order; thread 0 writes (sum u, sum u^2) of the
-// workgroup's core (an SR segment or a vertical tile) to part[2 blockIdx.x].
+// workgroup's core (an SR segment or a vertical tile) to part[2 slot].
 // The order never depends on scheduling.
 __device__ __forceinline__ void wave_sum2(double& s1, double& s2) {
   for (int o = 32; o > 0; o >>= 1) {
@@ -580,7 +596,7 @@ __device__ __forceinline__ void wave_sum2(double& s1, double& s2) {
 
 template <int K>
 __device__ __forceinline__ void segment_sums(const double (&u)[K], int a, int b, double* st,
-                                             double* __restrict__ part) {
+                                             double* __restrict__ part, int64_t slot) {
   double s1 = 0.0, s2 = 0.0;
 #pragma unroll
   for (int j = 0; j < K; ++j)
@@ -593,8 +609,8 @@ __device__ __forceinline__ void segment_sums(const double (&u)[K], int a, int b,
   if (threadIdx.x == 0) {
     double t1 = st[0], t2 = st[32];
     for (int i = 1; i < nw; ++i) { t1 = t1 + st[i]; t2 = t2 + st[32 + i]; }
-    part[2 * (int64_t)blockIdx.x] = t1;
-    part[2 * (int64_t)blockIdx.x + 1] = t2;
+    part[2 * slot] = t1;
+    part[2 * slot + 1] = t2;
   }
 }
 
@@ -610,12 +626,13 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
   Xch x{xb, 0, 2 * kTileThreads};
   Xch4 x4{xb4, 0, 4 * kTileThreads};
   const int wcount = kTileThreads * K;
+  a.tile = tile_index(a);
   const int64_t wlo0 = top_wlo(a);
   double u[K], f[K];
   if (window_interior(wlo0, wcount, a.n)) {
     if (a.deep) {
-      if (a.levels == 4) deep_tile<K, 4, F32>(a, st, st2, x, x4, f, u, wlo0);
-      else deep_tile<K, 3, F32>(a, st, st2, x, x4, f, u, wlo0);
+      if (a.levels == 4) deep_tile<K, 4, F32, true>(a, st, st2, x, x4, f, u, wlo0);
+      else deep_tile<K, 3, F32, true>(a, st, st2, x, x4, f, u, wlo0);
     } else {
       double tf[K], tp[K];
       issue_loads<K, true>(tf, a.rhs + wlo0, 0);
@@ -634,7 +651,7 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
                         false);  // segment_sums opens with a barrier
     if (a.part) {
       const int e0 = (int)threadIdx.x * K;
-      segment_sums<K>(u, (int)a.halo - e0, (int)(a.halo + a.core) - e0, st, a.part);
+      segment_sums<K>(u, (int)a.halo - e0, (int)(a.halo + a.core) - e0, st, a.part, a.tile);
     }
     return;
   }
@@ -645,7 +662,29 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
   if (a.part) {
     const int64_t c0 = G.clo - G.g0, c1 = G.chi - G.g0;
     segment_sums<K>(u, (int)(c0 < 0 ? 0 : (c0 > K ? K : c0)), (int)(c1 < 0 ? 0 : (c1 > K ? K : c1)),
-                    st, a.part);
+                    st, a.part, a.tile);
+  }
+}
+
+// Interior tiles of a deep up launch alone (the edge tiles take k_up): 166
+// VGPRs and 51 KB of LDS, so three workgroups share a CU.
+template <int K, bool F32>
+__global__ __launch_bounds__(kTileThreads, 3) void k_up_wide(VertArgs a) {
+  __shared__ double st[kTileThreads * (K + 1)];
+  __shared__ double xb[8 * kTileThreads];
+  Xch x{xb, 0, 4 * kTileThreads};
+  Xch4& x4 = x;  // one exchanger in both roles
+  a.tile = tile_index(a);
+  const int64_t wlo0 = top_wlo(a);
+  if (!window_interior(wlo0, kTileThreads * K, a.n)) return;  // the host launches interior tiles only
+  double u[K], f[K];
+  if (a.levels == 4) deep_tile<K, 4, F32, false>(a, st, st, x, x4, f, u, wlo0);
+  else deep_tile<K, 3, F32, false>(a, st, st, x, x4, f, u, wlo0);
+  if (a.out[0])
+    store_run_fast<K>(st, u, a.out[0] + wlo0, (int)a.halo, (int)(a.halo + a.core), false);
+  if (a.part) {
+    const int e0 = (int)threadIdx.x * K;
+    segment_sums<K>(u, (int)a.halo - e0, (int)(a.halo + a.core) - e0, st, a.part, a.tile);
   }
 }
 
@@ -689,6 +728,7 @@ __global__ __launch_bounds__(kTileThreads) void k_forcing(VertArgs a) {
   __shared__ double st[kTileThreads * (K + 1)];
   __shared__ double xb[4 * kTileThreads];
   Xch x{xb, 0, 2 * kTileThreads};
+  a.tile = tile_index(a);
   const int64_t wlo0 = top_wlo(a);
   double f[K];
   if (window_interior(wlo0, kTileThreads * K, a.n)) {
@@ -907,7 +947,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
     if (a.out) store_run_fast<K>(st, u, a.out + wlo, (int)a.pad, (int)(a.pad + a.s));
     if (a.part) {
       const int e0 = (int)threadIdx.x * K;
-      segment_sums<K>(u, (int)a.pad - e0, (int)(a.pad + a.s) - e0, st, a.part);
+      segment_sums<K>(u, (int)a.pad - e0, (int)(a.pad + a.s) - e0, st, a.part, blockIdx.x);
     }
     return;
   }
@@ -938,7 +978,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
   if (a.part) {
     const int64_t c0 = core_lo - g0, c1 = (core_hi < n ? core_hi : n) - g0;
     segment_sums<K>(u, (int)(c0 < 0 ? 0 : (c0 > K ? K : c0)), (int)(c1 < 0 ? 0 : (c1 > K ? K : c1)),
-                    st, a.part);
+                    st, a.part, blockIdx.x);
   }
 }
 
@@ -1103,7 +1143,7 @@ __device__ void sr2_up_interior(const Seg2Args& a, double* st, Xch& x) {
     if (a.out) store_run_fast<K>(st, u, a.out + wlo, (int)a.pad, (int)(a.pad + a.s));
     if (a.part) {
       const int e0 = (int)threadIdx.x * K;
-      segment_sums<K>(u, (int)a.pad - e0, (int)(a.pad + a.s) - e0, st, a.part);
+      segment_sums<K>(u, (int)a.pad - e0, (int)(a.pad + a.s) - e0, st, a.part, blockIdx.x);
     }
   }
 }
@@ -1189,7 +1229,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr2(Seg2Args a) {
     if (a.part) {
       const int64_t c0 = core_lo - g0, c1 = (core_hi < n ? core_hi : n) - g0;
       segment_sums<K>(u, (int)(c0 < 0 ? 0 : (c0 > K ? K : c0)),
-                      (int)(c1 < 0 ? 0 : (c1 > K ? K : c1)), st, a.part);
+                      (int)(c1 < 0 ? 0 : (c1 > K ? K : c1)), st, a.part, blockIdx.x);
     }
   }
 }
