@@ -424,17 +424,22 @@ struct Ctx {
     const int64_t blocks = (a.n + a.core - 1) / a.core;
     ProfScope ps("k_up", bytes, st);
     int64_t b_lo = 0, b_hi = -1;
-    if (deep && !p->f32 && blocks >= kUpWideTiles) interior_tiles(a, &b_lo, &b_hi);
+    if (deep && blocks >= kUpWideTiles) interior_tiles(a, &b_lo, &b_hi);
     if (b_hi >= b_lo) {
       // interior tiles on the three-workgroup kernel, the edge tiles on k_up
       VertArgs w = a;
       w.tile0 = b_lo;
-      hipLaunchKernelGGL((k_up_wide<kRun, false>), dim3((unsigned)(b_hi - b_lo + 1)), dim3(kTileThreads), 0,
-                         st, w);
       VertArgs e = a;
       e.gap_at = b_lo;
       e.gap = b_hi - b_lo + 1;
-      hipLaunchKernelGGL((k_up<kRun, false>), dim3((unsigned)(blocks - e.gap)), dim3(kTileThreads), 0, st, e);
+      const dim3 gw((unsigned)(b_hi - b_lo + 1)), ge((unsigned)(blocks - e.gap)), tb(kTileThreads);
+      if (p->f32) {
+        hipLaunchKernelGGL((k_up_wide<kRun, true>), gw, tb, 0, st, w);
+        hipLaunchKernelGGL((k_up<kRun, true>), ge, tb, 0, st, e);
+      } else {
+        hipLaunchKernelGGL((k_up_wide<kRun, false>), gw, tb, 0, st, w);
+        hipLaunchKernelGGL((k_up<kRun, false>), ge, tb, 0, st, e);
+      }
     } else if (p->f32) {
       hipLaunchKernelGGL((k_up<kRun, true>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
     } else {
@@ -629,15 +634,17 @@ struct Ctx {
       // one SR level with both passes inside the vertical kernels: a deep
       // pair when both SR-topped kernels walk the same levels
       const int dsr_n = std::min(P.d_srup, M - C);
-      const bool deep_sr = fused_down && P.fuse_up && !P.f32 && dsr_n == std::min(P.d_down, M - C) &&
+      // with FP32 relaxation only where the interior tiles take k_up_wide:
+      // the general up kernel then runs one wavefront per SIMD and has no
+      // latency left to hide the extra sweeps in
+      const bool deep_ok = !P.f32 || (nl(t) + tile_core() - 1) / tile_core() >= kUpWideTiles;
+      const bool deep_sr = fused_down && P.fuse_up && deep_ok && dsr_n == std::min(P.d_down, M - C) &&
                            deep_fits(P.nu1, P.nu2, dsr_n, kTileHalo, true);
       // the top up kernel rebuilds level t's pre-smoothed iterate, and with
       // a deep pair the next levels' as well
       const bool rebuild = !sr && rebuild_top(P, t);
       const int dtop_n = std::min(P.d_down, t - C);
-      // (not with FP32 relaxation: its up kernel runs one wavefront per SIMD
-      // and has no latency left to hide the extra sweeps in)
-      const bool deep_stored = rebuild && !P.f32 && dtop_n == std::min(P.d_up, t - C) &&
+      const bool deep_stored = rebuild && deep_ok && dtop_n == std::min(P.d_up, t - C) &&
                                deep_fits(P.nu1, P.nu2, dtop_n, kTileHalo, false);
       int top = t;  // highest stored level of this step
       int dtop = t;  // top of the vertical down leg

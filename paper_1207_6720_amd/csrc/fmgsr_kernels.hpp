@@ -667,9 +667,10 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
 }
 
 // Interior tiles of a deep up launch alone (the edge tiles take k_up): 166
-// VGPRs and 51 KB of LDS, so three workgroups share a CU.
+// VGPRs and 51 KB of LDS, so three workgroups share a CU (FP32 relaxation:
+// 182 VGPRs, two).
 template <int K, bool F32>
-__global__ __launch_bounds__(kTileThreads, 3) void k_up_wide(VertArgs a) {
+__global__ __launch_bounds__(kTileThreads, F32 ? 2 : 3) void k_up_wide(VertArgs a) {
   __shared__ double st[kTileThreads * (K + 1)];
   __shared__ double xb[8 * kTileThreads];
   Xch x{xb, 0, 4 * kTileThreads};
