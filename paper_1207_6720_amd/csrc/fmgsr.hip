@@ -17,6 +17,13 @@
 // every launch free of read/write overlap between workgroups.  The finest
 // SR level (t = M, sr_levels >= 1) is never stored: its down pass writes only
 // I^ of the smoothed cores (Uh) and its up pass streams the cores to u_out.
+// With split tau and one SR level both SR passes are the top levels of the
+// first down and the last up kernel.  The top up kernel of a step rebuilds
+// the pre-smoothed iterates the down kernel made on its levels above the
+// bottom one (Pi of V^{t-1} and the same sweeps in the same window), so
+// those are not stored ("deep pairs").  Launches of many tiles run their
+// interior tiles at three workgroups per CU (k_down's register-capped
+// variant; k_up_wide, with the edge tiles in a second launch of k_up).
 // With sr_levels = k >= 2 the levels M-k+1 .. M-1 are SR levels too (the
 // semantics of Sec. 4's runs with two and three SR levels): wherever they
 // are visited, their pre-smoothing is the block smoother (segment kernels

@@ -11,7 +11,9 @@
 // up kernel walks the same levels bottom-up and writes only its top level.
 // Windows overlap by a halo that absorbs the cells made stale by the window
 // edge (the host sizes it), so every core value equals what a sweep over
-// the whole level computes: same operations on the same operands.
+// the whole level computes: same operations on the same operands.  The
+// same holds for the pre-smoothed iterates an up kernel rebuilds in its
+// window instead of reading them (src / deep in VertArgs).
 #pragma once
 
 #include <hip/hip_runtime.h>

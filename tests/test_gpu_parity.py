@@ -101,6 +101,12 @@ CASES = [
     (1 << 15, 16, 1, 0, (10, 1), 0, "split", (0.0, 0.0), 26),
     (1 << 14, 15, 16, 8, (8, 3), 1, "split", (0.0, 0.0), 27),
     (1 << 13, 14, 8, 9, (5, 2), 1, "split", (-0.4, 0.2), 28),
+    # top levels of more than 768 tiles: interior tiles on the
+    # three-workgroup kernels, edge tiles on the general ones (deep pairs
+    # with four and with three levels, one SR level and none, N0 = 5)
+    (1 << 22, 23, 1024, 8, (1, 1), 1, "split", (0.0, 0.0), 44),
+    (1 << 22, 23, 1, 0, (3, 2), 0, "split", (0.2, -0.3), 45),
+    (5 << 20, 21, 1280, 8, (2, 1), 1, "split", (0.0, 0.0), 46),
 ]
 
 
