@@ -125,8 +125,8 @@ def main():
     ap.add_argument("--sr-levels", type=int, default=1, choices=[0, 1, 2, 3],
                     help="Poisson workloads: number of SR levels (2 and 3: the finest levels "
                          "below the top are SR levels too, split tau only)")
-    ap.add_argument("--cpu-log2n", type=int, default=24)
-    ap.add_argument("--cpu-runs", type=int, default=2)
+    ap.add_argument("--cpu-log2n", type=int, default=25)
+    ap.add_argument("--cpu-runs", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 2^27 doubles (1 GiB read + 1 GiB "
@@ -382,9 +382,10 @@ def run_batched(args, dev):
     cpu = None
     if not args.no_cpu_baseline:
         import oracle  # CPU baseline only
-        # bounded sample: problems in batch order up to ~2^22 cells (c3), or
-        # one problem (c4), forward (+ adjoint) by the oracle, single thread
-        budget = (1 << 22) if not adjoint else rb.sizes[0]
+        # bounded sample of about ten seconds of oracle work: problems in
+        # batch order up to ~2e8 cells (c3), or 48 problems (c4), forward
+        # (+ adjoint) by the oracle, single thread
+        budget = (3 << 26) if not adjoint else 48 * int(rb.sizes[0])
         idx, tot = oracle_sample(rb, None, None, segs, budget)
         t0 = time.perf_counter()
         for j in idx:
