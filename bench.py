@@ -383,9 +383,9 @@ def run_batched(args, dev):
     if not args.no_cpu_baseline:
         import oracle  # CPU baseline only
         # bounded sample of about ten seconds of oracle work: problems in
-        # batch order up to ~2e8 cells (c3), or 48 problems (c4), forward
-        # (+ adjoint) by the oracle, single thread
-        budget = (3 << 26) if not adjoint else 48 * int(rb.sizes[0])
+        # batch order up to ~2e8 cells (c3), or the 64 problems (c4),
+        # forward (+ adjoint) by the oracle, single thread
+        budget = (3 << 26) if not adjoint else 64 * int(rb.sizes[0])
         idx, tot = oracle_sample(rb, None, None, segs, budget)
         t0 = time.perf_counter()
         for j in idx:
