@@ -77,9 +77,10 @@ __device__ __forceinline__ double relax(double fj, double l, double r, int64_t g
 }
 
 // ---------------------------------------------------------------------------
-// Neighbour exchange: each thread publishes its first and last value and
-// reads its left neighbour's last and right neighbour's first.  Two LDS
-// buffers are used alternately, so one barrier per exchange suffices.
+// Neighbour exchange through LDS: each thread publishes a few values of its
+// run (its first and last, or four for the one-exchange sweeps and the FMG
+// interpolation) and reads its neighbours'.  Two halves of the buffer are
+// used alternately, so one barrier per exchange suffices.
 // ---------------------------------------------------------------------------
 struct Xch {
   double* buf;  // two halves of `half` doubles
