@@ -17,7 +17,7 @@
  * With that ghost rule the boundary row of L has diagonal 3 (Sec. 4, and
  * the appendix's operator assembly).
  *
- * Readings of the paper taken here (each is listed in the design doc):
+ * Readings of the paper taken here:
  *  R1  "levels" counts grids; the coarsest has N0 = n >> (levels-1) cells.
  *  R2  Solution restriction I^ = two-cell average (Sec. 2.4, Eq. 3 allows it
  *      to differ from the rhs restriction).  rhs/residual restriction I =
