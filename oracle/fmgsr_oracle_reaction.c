@@ -69,6 +69,9 @@ typedef struct {
   int32_t nu1, nu2;     /* inner sweeps of the pre / post smoother            */
   int32_t nsr;          /* 0: plain FMG-FAS; 1: the finest level uses SR      */
   int32_t tau_mode;     /* 0: split (R16), 1: literal Eq. 7                   */
+  int32_t tau_assembled; /* 0: tau of the SR level per patch, from each
+                            segment's extended iterate (Fig. 3 step 4);
+                            1: assembled from the global iterate             */
 } orc_rx_options;
 
 static double h2_of(int64_t n) { return 1.0 / ((double)n * (double)n); }
@@ -328,6 +331,7 @@ static int rx_validate(int kind, int64_t n, int levels, int64_t S, int64_t b,
   if (n % ((int64_t)1 << M) != 0) return ORC_EINVAL;
   if (o->nu1 < 0 || o->nu2 < 0 || o->nsr < 0 || o->nsr > 1 || o->nsr > M) return ORC_EINVAL;
   if (o->tau_mode < 0 || o->tau_mode > 1) return ORC_EINVAL;
+  if (o->tau_assembled < 0 || o->tau_assembled > 1) return ORC_EINVAL;
   if (o->nsr == 1 && (S < 1 || n % S != 0 || (n / S) % 2 != 0)) return ORC_EINVAL;
   return M;
 }
@@ -415,7 +419,8 @@ int orc_rx_fmgsr_solve_ex(int kind, const double *f, const double *coef, double 
     int patches_level = sr_top ? t : -1;
     for (int m = k; m >= 0 && st == ORC_OK; --m) {
       orc_restrict_avg(lv[m + 1].u, lv[m + 1].n, lv[m].uhat);
-      if (patches_level == m + 1) coarse_rhs_patches(kind, o->tau_mode, lv, m, patches, S, b, gL, gR);
+      if (patches_level == m + 1 && !o->tau_assembled)
+        coarse_rhs_patches(kind, o->tau_mode, lv, m, patches, S, b, gL, gR);
       else coarse_rhs_global(kind, o->tau_mode, lv, m, gL, gR);
       patches_level = -1;
       memcpy(lv[m].u, lv[m].uhat, sizeof(double) * (size_t)lv[m].n);

@@ -36,14 +36,15 @@ def options(nu1=2, nu2=1, nsr=1, rhs_restrict="fw", tau="split", smoother="rb",
 class RxOptions(ctypes.Structure):
     """Mirror of ``orc_rx_options`` (see fmgsr_oracle_reaction.c)."""
     _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
-                ("nsr", ctypes.c_int32), ("tau_mode", ctypes.c_int32)]
+                ("nsr", ctypes.c_int32), ("tau_mode", ctypes.c_int32),
+                ("tau_assembled", ctypes.c_int32)]
 
 
 RX_KINDS = {"poisson": 0, "cubic": 1, "linear": 2}
 
 
-def rx_options(nu1=2, nu2=1, nsr=1, tau="split"):
-    return RxOptions(nu1, nu2, nsr, {"split": 0, "literal": 1}[tau])
+def rx_options(nu1=2, nu2=1, nsr=1, tau="split", tau_assembled=False):
+    return RxOptions(nu1, nu2, nsr, {"split": 0, "literal": 1}[tau], int(bool(tau_assembled)))
 
 
 def lib():

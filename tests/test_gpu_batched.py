@@ -1,8 +1,8 @@
 """GPU parity of the batched solver (one persistent launch, reaction operators,
 FP32 relaxation, adjoint) against the FP64 CPU oracle, through the C ABI.
 
-Bars: FP64 results within 1e-12 relative (2-norm per problem) of the oracle,
-bitwise where the coarsest level is one cell (identical expression trees
+Bars: FP64 results within 1e-12 relative of the oracle per problem, both in
+the 2-norm and cell by cell (max |d| <= 1e-12 max |u_ref|), bitwise where the coarsest level is one cell (identical expression trees
 and Newton steps); FP32 relaxation within a tenth of each problem's
 discretisation error (it must stay below it); gradients within 1e-12 of the
 oracle's FMG-SR adjoint."""
@@ -26,8 +26,17 @@ def dev():
     return torch.device("cuda:0")
 
 
-def rel(a, b):
+def rel_norm(a, b):
+    """2-norm relative difference (accuracy bars: discretisation error,
+    finite differences)."""
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def rel(a, b):
+    """Parity difference: the larger of the 2-norm ratio and the largest cell
+    difference over the largest |b| (both must meet the bar)."""
+    cell = np.abs(a - b).max() / max(np.abs(b).max(), 1e-300) if a.size else 0.0
+    return max(rel_norm(a, b), cell)
 
 
 def packed(rb, dev):
@@ -156,12 +165,12 @@ def test_fp32_relaxation_stays_below_discretisation_error(dev):
         ref = oracle.rx_fmgsr_solve("cubic", fs[j], ks[j], levels=rb.levels[j],
                                     segments=int(segs[j]), buffer=rb.buffer)
         ustar, _ = oracle.rx_newton("cubic", ks[j], fs[j])
-        disc = rel(ustar, es[j])
-        d32 = rel(a32[j], ref)
+        disc = rel_norm(ustar, es[j])
+        d32 = rel_norm(a32[j], ref)
         print(f"problem {j}: n={rb.sizes[j]} disc={disc:.2e} fp32-vs-oracle={d32:.2e}", flush=True)
         assert rel(a64[j], ref) <= TOL
         assert d32 <= 0.1 * disc
-        assert rel(a32[j], ustar) <= 0.5 * disc
+        assert rel_norm(a32[j], ustar) <= 0.5 * disc
 
 
 def test_adjoint_matches_oracle(dev):
@@ -194,8 +203,8 @@ def test_single_problem_entry_points(dev):
     gf, gk = fmgsr.adjoint(fd, kd, dJ, levels=levels, segments=4, buffer=8)  # forward recomputed
     rf, rk = oracle.rx_fmgsr_adjoint(k, u.cpu().numpy(), dJ.cpu().numpy(), levels=levels,
                                      segments=4, buffer=8)
-    assert rel(gf.cpu().numpy(), rf) <= 1e-11
-    assert rel(gk.cpu().numpy(), rk) <= 1e-11
+    assert rel(gf.cpu().numpy(), rf) <= TOL
+    assert rel(gk.cpu().numpy(), rk) <= TOL
 
 
 def test_graph_replays_match_eager(dev):
@@ -307,7 +316,8 @@ def test_autograd_and_central_differences(dev):
             ad_k.append(gkj @ dk)
         # agreement of the 32 directional derivatives as vectors (a single
         # direction can make its derivative small by cancellation)
-        ef, ek = rel(np.array(ad_f), np.array(fd_f)), rel(np.array(ad_k), np.array(fd_k))
+        ef, ek = (rel_norm(np.array(ad_f), np.array(fd_f)),
+                  rel_norm(np.array(ad_k), np.array(fd_k)))
         print(f"problem {j}: FD rel f {ef:.2e} kappa {ek:.2e}", flush=True)
         assert ef <= 1e-4 and ek <= 1e-4
 

@@ -163,6 +163,33 @@ def test_literal_tau_agrees_with_split():
         assert rel(b, a) <= 1e-13 * n
 
 
+@pytest.mark.parametrize("nu1", [1, 2, 3])
+def test_per_patch_tau_equals_assembled_when_the_buffer_covers_its_reach(nu1):
+    """Per-patch tau on the SR level (Fig. 3 step 4, from each segment's
+    extended iterate) against tau assembled from the global iterate.  The
+    split reaction tau I(kappa u^3) reads one fine cell beyond the core's
+    pairs, and the block smoother's patch equals the global red-black
+    iterate up to 2 nu1 - 1 cells in from the patch edge, so the two agree
+    bit for bit exactly when b >= 2 nu1; one cell less and they differ.
+    Literal tau (Eq. 7) also applies L_h there, reaching two cells beyond
+    the core: bitwise from b = 2 nu1 + 1.  The forcing is rough (seeded
+    normal values) so that a one-ulp difference in a patch cell is not
+    absorbed by the rounding of the restriction, as it can be for a smooth
+    one."""
+    n0, L = 39, 6
+    n = n0 << L
+    _, k, _, _ = problem(n, j=4)
+    f = np.random.default_rng(5).normal(size=n) * 1e4
+    kw = dict(levels=L + 1, segments=8, nu1=nu1, nu2=1)
+    for tau, need in (("split", 2 * nu1), ("literal", 2 * nu1 + 1)):
+        for b, equal in ((need, True), (need + 3, True), (need - 1, False), (0, False)):
+            patch = oracle.rx_fmgsr_solve("cubic", f, k, buffer=b, tau=tau, **kw)
+            glob = oracle.rx_fmgsr_solve("cubic", f, k, buffer=b, tau=tau, tau_assembled=True,
+                                         **kw)
+            assert np.array_equal(patch, glob) == equal, (tau, b)
+            assert rel(patch, glob) <= 1e-6
+
+
 def test_segment_order_does_not_matter():
     n = 39 << 6
     f, k, _, _ = problem(n)
