@@ -134,6 +134,17 @@ size_t fmgsr_workspace_bytes(int64_t n, int32_t levels, const fmgsr_options *opt
 size_t fmgsr_workspace_bytes_for(int64_t n, int32_t levels, int64_t n_segments, int32_t buffer,
                                  const fmgsr_options *opt);
 
+/* Largest dynamic LDS (bytes) one workgroup of fmgsr_solve requests for
+ * these sizes, segments and options (0 if invalid): the single-workgroup
+ * coarse core holds the level stack of the coarsest levels (Fig. 1's exact
+ * solve and the V-cycle bottoms), the segment kernels a register stage and
+ * exchange buffer per thread.  fmgsr_solve grants those kernels 160 KiB and
+ * returns FMGSR_EINVAL, before enqueuing anything, when this figure exceeds
+ * the grant or the device's opt-in limit per workgroup; FMGSR_EDEVICE when
+ * the grant itself failed. */
+size_t fmgsr_launch_lds_bytes(int64_t n, int32_t levels, int64_t n_segments, int32_t buffer,
+                              const fmgsr_options *opt);
+
 /*
  * fmgsr_solve -- one FMG-FAS-SR iteration (Fig. 3) for -u'' = f.
  *

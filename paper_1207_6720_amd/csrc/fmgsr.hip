@@ -82,6 +82,26 @@ bool is_device_ptr(const void* ptr) {
   return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
+hipError_t device_lds_limit(size_t* bytes) {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static size_t cache[kMaxDev] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  if (dev >= 0 && dev < kMaxDev && cache[dev]) {
+    *bytes = cache[dev];
+    return hipSuccess;
+  }
+  int v = 0;
+  e = hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev);
+  if (e != hipSuccess) return e;
+  *bytes = (size_t)(v > 0 ? v : 0);
+  if (dev >= 0 && dev < kMaxDev) cache[dev] = *bytes;
+  return hipSuccess;
+}
+
 }  // namespace fmgsr
 
 namespace fmgsr {
@@ -338,6 +358,56 @@ size_t plan_bytes(const Plan& p) {
   return uh ? p.total : std::max<size_t>(p.off_Uh, kAlign);
 }
 
+// Dynamic LDS (bytes) of one workgroup of each kernel that takes it: the
+// coarse core holds its level stack (iterates, right-hand sides, correction)
+// and the cyclic-reduction buffers; the segment kernels a stage of K + 1 and
+// an exchange of 4 doubles per thread.
+size_t core_lds(const Plan& p) {
+  const int64_t ntot = p.n0 * (((int64_t)1 << (p.C + 1)) - 1);
+  const int64_t esz = (p.C > 0) ? (p.n0 << (p.C - 1)) : 0;
+  return (size_t)(2 * ntot + esz + 8 * p.n0) * sizeof(double);
+}
+size_t seg_lds(int threads) { return (size_t)threads * (kSegRun + 1 + 4) * sizeof(double); }
+
+// The largest dynamic LDS any launch of this plan requests (segment kernels
+// counted whenever the plan has SR levels).
+size_t plan_lds(const Plan& p) {
+  size_t m = core_lds(p);
+  if (p.nsr >= 1) m = std::max(m, seg_lds(p.seg_threads));
+  if (p.nsr >= 2) m = std::max(m, seg_lds(p.seg2_threads));
+  return m;
+}
+
+// Dynamic LDS the kernels above are granted (hipFuncAttributeMaxDynamicSharedMemorySize).
+constexpr size_t kDynLds = 160 * 1024;
+
+// Grants the dynamic-LDS attribute to every kernel that takes dynamic LDS
+// (once per process; a failure is remembered and reported by every solve),
+// then checks that this plan's largest request fits both the grant and the
+// current device's opt-in limit, so an oversized request becomes an error
+// code instead of a launch the device cannot honour.
+fmgsr_status check_lds(const Plan& p) {
+  static std::once_flag once;
+  static hipError_t granted = hipSuccess;
+  std::call_once(once, [] {
+    const void* ks[] = {(const void*)k_coarse_core,
+                        (const void*)k_sr_down<kSegRun, false>, (const void*)k_sr_up<kSegRun, false>,
+                        (const void*)k_sr_down<kSegRun, true>, (const void*)k_sr_up<kSegRun, true>,
+                        (const void*)k_sr2<kSegRun, false, false>, (const void*)k_sr2<kSegRun, false, true>,
+                        (const void*)k_sr2<kSegRun, true, false>, (const void*)k_sr2<kSegRun, true, true>};
+    for (const void* k : ks) {
+      const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds);
+      if (e != hipSuccess && granted == hipSuccess) granted = e;
+    }
+    (void)hipGetLastError();
+  });
+  if (granted != hipSuccess) return FMGSR_EDEVICE;
+  size_t limit = 0;
+  if (device_lds_limit(&limit) != hipSuccess) return FMGSR_EDEVICE;
+  const size_t need = plan_lds(p);
+  return (need <= kDynLds && need <= limit) ? FMGSR_OK : FMGSR_EINVAL;
+}
+
 struct Ctx {
   const Plan* p;
   hipStream_t st;
@@ -516,8 +586,7 @@ struct Ctx {
     a.rhs_top = rhs_top;
     a.out = (p->M >= 1) ? lv(V, p->C) : u_out;
     const int64_t ntot = p->n0 * (((int64_t)1 << (p->C + 1)) - 1);
-    const int64_t esz = (p->C > 0) ? (p->n0 << (p->C - 1)) : 0;
-    const size_t lds = (size_t)(2 * ntot + esz + 8 * p->n0) * sizeof(double);
+    const size_t lds = core_lds(*p);
     const int64_t nC = p->n0 << p->C;
     double bytes = (double)ntot * 8.0 + (double)nC * 8.0;  // forcing levels, result
     if (mode == 1) bytes += (double)nC * 8.0 * (src_kind == kSrcRestrict ? 3.0 : 2.0);
@@ -555,7 +624,7 @@ struct Ctx {
     // tau), up writes n
     const double src = direct ? nb : nb * 0.5;
     const double bytes = up ? nb * 2.5 : nb + src + nb * 0.5 + (q_out ? nb * 0.5 : 0.0);
-    const size_t lds = (size_t)threads * (kSegRun + 1 + 4) * sizeof(double);
+    const size_t lds = seg_lds(threads);
     ProfScope ps(up ? "k_sr_up" : "k_sr_down", bytes, st);
     const dim3 g((unsigned)p->S), b(threads);
     if (up && p->f32) hipLaunchKernelGGL((k_sr_up<kSegRun, true>), g, b, lds, st, a);
@@ -594,7 +663,7 @@ struct Ctx {
     // V^{M-2} n/4, F^{M-1} n/2 and f n read; down writes n/2, up writes n
     const double bytes = nb * 1.75 + (up ? (u_out ? nb : 0.0) : nb * 0.5);
     const int threads = p->seg2_threads;
-    const size_t lds = (size_t)threads * (kSegRun + 1 + 4) * sizeof(double);
+    const size_t lds = seg_lds(threads);
     ProfScope ps(up ? "k_sr2_up" : "k_sr2_down", bytes, st);
     const dim3 g((unsigned)p->S), b(threads);
     if (up && p->f32) hipLaunchKernelGGL((k_sr2<kSegRun, true, true>), g, b, lds, st, a);
@@ -769,6 +838,17 @@ size_t fmgsr_workspace_bytes_for(int64_t n, int32_t levels, int64_t n_segments, 
   return plan_bytes(p);
 }
 
+size_t fmgsr_launch_lds_bytes(int64_t n, int32_t levels, int64_t n_segments, int32_t buffer,
+                              const fmgsr_options* opt) {
+  fmgsr_options o;
+  if (opt) o = *opt;
+  else fmgsr_default_options(&o);
+  Plan p;
+  if (make_plan(n, levels, o, &p) != FMGSR_OK) return 0;
+  if (plan_segments(n_segments, buffer, &p) != FMGSR_OK) return 0;
+  return plan_lds(p);
+}
+
 fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_left,
                          double g_right, int64_t n, int32_t levels, int64_t n_segments,
                          int32_t buffer, const fmgsr_options* opt, double* u_out,
@@ -797,6 +877,7 @@ fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_lef
   }
   if (!is_device_ptr(f) || (u_out ? !is_device_ptr(u_out) : !o.functionals)) return FMGSR_EINVAL;
   if ((const void*)f == (const void*)u_out) return FMGSR_EINVAL;
+  if (const fmgsr_status lst = check_lds(p); lst != FMGSR_OK) return lst;
   hipStream_t stream = (hipStream_t)hip_stream;
   char* ws = (char*)o.workspace;
   bool own = false;
@@ -809,17 +890,6 @@ fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_lef
     }
     own = true;
   }
-  static std::once_flag attr_once;
-  std::call_once(attr_once, [] {
-    (void)hipFuncSetAttribute((const void*)k_coarse_core, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
-    for (const void* k : {(const void*)k_sr_down<kSegRun, false>, (const void*)k_sr_up<kSegRun, false>,
-                          (const void*)k_sr_down<kSegRun, true>, (const void*)k_sr_up<kSegRun, true>,
-                          (const void*)k_sr2<kSegRun, false, false>, (const void*)k_sr2<kSegRun, false, true>,
-                          (const void*)k_sr2<kSegRun, true, false>, (const void*)k_sr2<kSegRun, true, true>})
-      (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipGetLastError();
-  });
   Ctx c;
   c.p = &p;
   c.st = stream;

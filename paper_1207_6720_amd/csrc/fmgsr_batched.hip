@@ -1101,6 +1101,12 @@ fmgsr_status build_plan(fmgsr_batch_s* b, int T, int K, int halve, int group_cap
   b->region = std::max(T * (K + 1), 11 * b->n0max);
   b->lds = sizeof(double) * ((size_t)b->region + 32 + 4 * (size_t)T);
   if (b->lds > 160 * 1024) return FMGSR_EINVAL;
+  size_t lds_limit = 0;  // the device's opt-in limit per workgroup
+  if (fmgsr::device_lds_limit(&lds_limit) != hipSuccess) {
+    (void)hipGetLastError();
+    return FMGSR_EDEVICE;
+  }
+  if (b->lds > lds_limit) return FMGSR_EINVAL;
   const void* kp = kernel_ptr(b->op, b->prec, K);
   if (hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds) != hipSuccess) {
     (void)hipGetLastError();

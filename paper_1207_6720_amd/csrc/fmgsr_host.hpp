@@ -1,5 +1,6 @@
 // fmgsr_host.hpp -- host-side pieces shared by the library's entry points:
-// per-launch event timing (fmgsr_profile_*) and the device-pointer check.
+// per-launch event timing (fmgsr_profile_*), the device-pointer check and
+// the device's LDS limit.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,5 +27,9 @@ struct ProfScope {
 
 // True for device (or managed) memory; host pointers are rejected.
 bool is_device_ptr(const void* ptr);
+
+// Largest LDS one workgroup may use on the current device after opting in
+// (hipDeviceAttributeSharedMemPerBlockOptin), queried once per device.
+hipError_t device_lds_limit(size_t* bytes);
 
 }  // namespace fmgsr

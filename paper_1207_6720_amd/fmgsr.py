@@ -69,6 +69,9 @@ def lib():
         L.fmgsr_workspace_bytes_for.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
                                                 ctypes.c_int32, ctypes.POINTER(Options)]
         L.fmgsr_workspace_bytes_for.restype = ctypes.c_size_t
+        L.fmgsr_launch_lds_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                             ctypes.c_int32, ctypes.POINTER(Options)]
+        L.fmgsr_launch_lds_bytes.restype = ctypes.c_size_t
         L.fmgsr_solve.argtypes = [ctypes.POINTER(Operator), ctypes.c_void_p, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
                                   ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p,
@@ -129,6 +132,13 @@ def workspace_bytes(n, levels, nu=(2, 1), sr_levels=1, tau="split", segments=Non
                                                ctypes.byref(o)))
 
 
+def launch_lds_bytes(n, levels, segments, buffer, nu=(2, 1), sr_levels=1, tau="split"):
+    """Largest dynamic LDS one workgroup of this solve requests."""
+    o = make_options(nu, sr_levels, tau)
+    return int(lib().fmgsr_launch_lds_bytes(int(n), int(levels), int(segments), int(buffer),
+                                            ctypes.byref(o)))
+
+
 def alloc_workspace(n, levels, device, **kw):
     nbytes = workspace_bytes(n, levels, **kw)
     if nbytes == 0:
@@ -136,10 +146,26 @@ def alloc_workspace(n, levels, device, **kw):
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
-def _check_vec(t, name):
+def _check_vec(t, name, numel=None, at_least=None, device=None):
+    """Reject anything the C ABI could not use safely: the library sees raw
+    pointers only, so a short array or a float32 one would be read and
+    written past its end on the device.  numel: exact element count;
+    at_least: minimum count (packed batch arrays); device: must match."""
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
             and t.is_contiguous() and t.dim() == 1):
         raise ValueError(f"{name} must be a contiguous 1-D float64 tensor on the GPU")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    if at_least is not None and t.numel() < at_least:
+        raise ValueError(f"{name} has {t.numel()} elements, the packed extent is {at_least}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+
+
+def _check_workspace(ws, device):
+    if not (isinstance(ws, torch.Tensor) and ws.is_cuda and ws.is_contiguous()
+            and ws.device == device):
+        raise ValueError("workspace must be a contiguous GPU tensor on the solve's device")
 
 
 def solve(f, g=(0.0, 0.0), levels=None, segments=1, buffer=0, nu=(2, 1), sr_levels=1,
@@ -154,9 +180,13 @@ def solve(f, g=(0.0, 0.0), levels=None, segments=1, buffer=0, nu=(2, 1), sr_leve
     synchronously as a batch of one.
     """
     _check_vec(f, "f")
-    if kappa is not None:
-        _check_vec(kappa, "kappa")
     n = f.numel()
+    if op not in OPS:
+        raise ValueError(f"unknown operator {op!r}")
+    if (op == "poisson") != (kappa is None):
+        raise ValueError("kappa is required for the reaction operators and refused for poisson")
+    if kappa is not None:
+        _check_vec(kappa, "kappa", numel=n, device=f.device)
     if levels is None:
         levels = n.bit_length()  # n a power of two -> N0 = 1
     if not write_u:
@@ -165,12 +195,12 @@ def solve(f, g=(0.0, 0.0), levels=None, segments=1, buffer=0, nu=(2, 1), sr_leve
         out = None
     elif out is None:
         out = torch.empty_like(f)
-    elif not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
-              and out.numel() == n):
-        raise ValueError("out must be a contiguous float64 GPU tensor of f's size")
-    if functionals is not None and not (functionals.is_cuda and functionals.dtype == torch.float64
-                                        and functionals.numel() >= 2):
-        raise ValueError("functionals must be a float64 GPU tensor with 2 elements")
+    else:
+        _check_vec(out, "out", numel=n, device=f.device)
+    if functionals is not None:
+        _check_vec(functionals, "functionals", at_least=2, device=f.device)
+    if workspace is not None:
+        _check_workspace(workspace, f.device)
     if stream is None:
         stream = torch.cuda.current_stream(f.device)
     o = make_options(nu, sr_levels, tau, workspace, precision)
@@ -225,10 +255,21 @@ class Batch:
     def _stream(self, stream, dev):
         return (stream or torch.cuda.current_stream(dev)).cuda_stream
 
+    def _coef(self, kappa, dev):
+        if self.op == "poisson":
+            if kappa is not None:
+                raise ValueError("a poisson plan takes no kappa")
+            return None
+        _check_vec(kappa, "kappa", at_least=self.total, device=dev)
+        return kappa
+
     def solve(self, f, kappa=None, out=None, stream=None):
-        _check_vec(f, "f")
+        _check_vec(f, "f", at_least=self.total)
+        kappa = self._coef(kappa, f.device)
         if out is None:
             out = torch.empty_like(f)
+        else:
+            _check_vec(out, "out", at_least=self.total, device=f.device)
         st = lib().fmgsr_batch_solve(self._h, f.data_ptr(),
                                      kappa.data_ptr() if kappa is not None else None,
                                      out.data_ptr(), self._stream(stream, f.device))
@@ -238,10 +279,20 @@ class Batch:
 
     def adjoint(self, kappa, u_fwd, dJdu, grad_f=None, grad_kappa=None, stream=None):
         """(grad_f, grad_kappa) of J with dJ/du = dJdu (fmgsr_batch_adjoint)."""
+        if self.op != "cubic":
+            raise ValueError("the adjoint needs a plan made for the cubic operator")
+        _check_vec(dJdu, "dJdu", at_least=self.total)
+        dev = dJdu.device
+        _check_vec(kappa, "kappa", at_least=self.total, device=dev)
+        _check_vec(u_fwd, "u_fwd", at_least=self.total, device=dev)
         if grad_f is None:
             grad_f = torch.empty_like(dJdu)
+        else:
+            _check_vec(grad_f, "grad_f", at_least=self.total, device=dev)
         if grad_kappa is None:
             grad_kappa = torch.empty_like(dJdu)
+        else:
+            _check_vec(grad_kappa, "grad_kappa", at_least=self.total, device=dev)
         st = lib().fmgsr_batch_adjoint(self._h, kappa.data_ptr(), u_fwd.data_ptr(),
                                        dJdu.data_ptr(), grad_f.data_ptr(), grad_kappa.data_ptr(),
                                        self._stream(stream, dJdu.device))
@@ -250,8 +301,12 @@ class Batch:
         return grad_f, grad_kappa
 
     def autotune(self, f, kappa=None, scratch=None, stream=None):
+        _check_vec(f, "f", at_least=self.total)
+        kappa = self._coef(kappa, f.device)
         if scratch is None:
             scratch = torch.empty_like(f)
+        else:
+            _check_vec(scratch, "scratch", at_least=self.total, device=f.device)
         ms = ctypes.c_double(0.0)
         st = lib().fmgsr_batch_autotune(self._h, f.data_ptr(),
                                         kappa.data_ptr() if kappa is not None else None,
@@ -276,9 +331,12 @@ class Batch:
 def adjoint(f, kappa, dJdu, g=(0.0, 0.0), levels=None, segments=0, buffer=8, nu=(2, 1),
             u_fwd=None, precision="fp64", stream=None):
     """(grad_f, grad_kappa) for one cubic problem (fmgsr_adjoint; synchronous)."""
-    for t, nm in ((f, "f"), (kappa, "kappa"), (dJdu, "dJdu")):
-        _check_vec(t, nm)
+    _check_vec(f, "f")
     n = f.numel()
+    for t, nm in ((kappa, "kappa"), (dJdu, "dJdu")):
+        _check_vec(t, nm, numel=n, device=f.device)
+    if u_fwd is not None:
+        _check_vec(u_fwd, "u_fwd", numel=n, device=f.device)
     if levels is None:
         levels = n.bit_length()
     gf, gk = torch.empty_like(f), torch.empty_like(f)

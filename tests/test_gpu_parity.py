@@ -401,3 +401,43 @@ def test_functionals_c2_functional_only(dev):
     got = fun.cpu().numpy()
     print("c2 functionals", got, ref, flush=True)
     assert np.all(np.abs(got - ref) <= 1e-13 * np.abs(ref))
+
+
+def test_binding_checks_extents_before_calling_the_library(dev):
+    """Short, float32 or misplaced arrays never reach the C ABI (which cannot
+    see extents): each raises ValueError in the binding."""
+    n = 1 << 10
+    f = torch.zeros(n, dtype=torch.float64, device=dev)
+    short = torch.zeros(n - 1, dtype=torch.float64, device=dev)
+    with pytest.raises(ValueError):
+        fmgsr.solve(f, levels=11, segments=4, buffer=4, out=short)
+    with pytest.raises(ValueError):
+        fmgsr.solve(f, levels=11, segments=4, buffer=4, op="cubic", kappa=short)
+    with pytest.raises(ValueError):
+        fmgsr.solve(f, levels=11, segments=4, buffer=4, op="cubic",
+                    kappa=torch.ones(n, dtype=torch.float32, device=dev))
+    with pytest.raises(ValueError):
+        fmgsr.solve(f, levels=11, segments=4, buffer=4, op="cubic")    # kappa missing
+    with pytest.raises(ValueError):
+        fmgsr.solve(f, levels=11, kappa=f)                             # kappa for poisson
+    with pytest.raises(ValueError):
+        fmgsr.adjoint(f, f, short, levels=11, segments=4)
+    with pytest.raises(ValueError):
+        fmgsr.adjoint(f, f, f, levels=11, segments=4, u_fwd=short)
+    plan = fmgsr.Batch((n, n), (6, 6), buffer=8, op="cubic")
+    both = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+    with pytest.raises(ValueError):
+        plan.solve(both[:-1], both)                                    # f short
+    with pytest.raises(ValueError):
+        plan.solve(both, both[: n])                                    # kappa short
+    with pytest.raises(ValueError):
+        plan.solve(both, None)                                         # kappa missing
+    with pytest.raises(ValueError):
+        plan.adjoint(both, both[:-1], both)                            # u_fwd short
+    with pytest.raises(ValueError):
+        plan.adjoint(both, both, both, grad_kappa=both.float())        # float32 gradient
+    with pytest.raises(ValueError):
+        plan.autotune(both, both, scratch=both[:-1])
+    pois = fmgsr.Batch((n,), (6,), buffer=8, op="poisson")
+    with pytest.raises(ValueError):
+        pois.adjoint(f, f, f)                                          # adjoint of poisson

@@ -156,3 +156,53 @@ def test_two_sr_levels_store_neither_finest_level():
         saved = (n // 2 + n // 2 - n // 4) * 8
         assert abs((one - two) - saved) <= 3 * 256, (n, one - two, saved)
         assert three == two
+
+
+def test_binding_rejects_host_and_float32_arrays():
+    """The binding checks every tensor before any library call: the C ABI
+    sees raw pointers only, so a host array or a float32 coefficient would be
+    read as device FP64 data of the wrong extent."""
+    import torch
+    f64 = torch.zeros(64, dtype=torch.float64)
+    f32 = torch.zeros(64, dtype=torch.float32)
+    with pytest.raises(ValueError):
+        F.solve(f64, levels=7)                              # host memory
+    with pytest.raises(ValueError):
+        F.solve(f32, levels=7)                              # float32
+    with pytest.raises(ValueError):
+        F.adjoint(f64, f64, f64, levels=7)                  # host memory
+    with pytest.raises(ValueError):
+        F._check_vec(torch.zeros(2, 32, dtype=torch.float64), "f")  # not 1-D
+    with pytest.raises(ValueError):
+        F._check_vec(torch.zeros(64, dtype=torch.float64)[::2], "f")  # not contiguous
+
+
+def test_launch_lds_fits_the_grant_for_every_geometry():
+    """Every kernel with dynamic LDS is granted 160 KiB (MI355X: 160 KiB per
+    workgroup); a solve checks its largest request against the grant and the
+    device limit before enqueuing.  The coarse core's request is its level
+    stack: iterates and right-hand sides of levels 0..C, the correction
+    buffer of level C-1 and 8 N0 doubles of cyclic reduction; the segment
+    kernels take 13 doubles per thread."""
+    grant = 160 * 1024
+    # N0 = 1: core levels up to 2048 cells (C = 11)
+    ntot, esz = 4095, 1024
+    assert F.launch_lds_bytes(1 << 28, 29, 1 << 16, 8) == (2 * ntot + esz + 8) * 8
+    # the largest coarsest grid (N0 = 1024): the core takes levels 0 and 1
+    # when a level lies above them (the finest level is never in the core)
+    assert F.launch_lds_bytes(4096, 3, 1, 0, sr_levels=0) == (2 * 3072 + 1024 + 8 * 1024) * 8
+    assert F.launch_lds_bytes(2048, 2, 1, 0, sr_levels=0) == (2 * 1024 + 8 * 1024) * 8
+    # widest segment window: 1024 threads of 8 cells
+    s = 8160  # + 2 x 10 pad cells: 1023 runs of 8
+    assert F.launch_lds_bytes(8 * s, 9, 8, 8) == max(1024 * 13 * 8,
+                                                     F.launch_lds_bytes(8 * s, 9, 1, 0, sr_levels=0))
+    worst = 0
+    for n0 in (1, 3, 5, 63, 64, 65, 255, 511, 1000, 1024):
+        for extra in range(0, 14):
+            n = n0 << extra
+            for sr, segs, buf in ((0, 1, 0), (1, 1, 8), (2, 1, 8)):
+                if sr > extra:
+                    continue
+                worst = max(worst, F.launch_lds_bytes(n, extra + 1, segs, buf, sr_levels=sr))
+    assert 0 < worst <= grant
+    assert F.launch_lds_bytes(1000, 11, 4, 4) == 0      # invalid sizes
