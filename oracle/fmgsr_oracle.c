@@ -258,9 +258,10 @@ static void smooth_set(double *u, const double *F, int64_t n, int64_t lo, int64_
  * If patches != NULL the extended iterates of every segment are returned
  * there, each as a window of width s + 2*pw (pw = max(b,2) + 1) centred on
  * the core, for per-patch tau (R6).  Window cells outside the domain are 0. */
-static int smooth_blocks(const double *v, const double *F, int64_t n, int64_t S,
-                         int64_t b, int nu, int smoother, const double *kaczmarz_c,
-                         double gL, double gR, double *out, double *patches, int order)
+static int smooth_blocks_range(const double *v, const double *F, int64_t n, int64_t S,
+                               int64_t b, int nu, int smoother, const double *kaczmarz_c,
+                               double gL, double gR, double *out, double *patches, int order,
+                               int64_t k_lo, int64_t k_hi)
 {
   int64_t s = n / S;
   int64_t pw = (b > 2 ? b : 2) + 1;
@@ -270,8 +271,8 @@ static int smooth_blocks(const double *v, const double *F, int64_t n, int64_t S,
   /* w holds the whole level so that cell indices stay global; only the
    * window around the current segment is refreshed from v each time. */
   memcpy(w, v, sizeof(double) * (size_t)n);
-  for (int64_t k = 0; k < S; ++k) {
-    int64_t i = order ? (S - 1 - k) : k;
+  for (int64_t k = k_lo; k < k_hi; ++k) {
+    int64_t i = order ? (k_hi - 1 - (k - k_lo)) : k;
     int64_t lo = i * s - b, hi = (i + 1) * s + b;
     if (lo < 0) lo = 0;
     if (hi > n) hi = n;
@@ -288,6 +289,15 @@ static int smooth_blocks(const double *v, const double *F, int64_t n, int64_t S,
   }
   free(w);
   return ORC_OK;
+}
+
+/* All S segments (the smoother of an SR level). */
+static int smooth_blocks(const double *v, const double *F, int64_t n, int64_t S,
+                         int64_t b, int nu, int smoother, const double *kaczmarz_c,
+                         double gL, double gR, double *out, double *patches, int order)
+{
+  return smooth_blocks_range(v, F, n, S, b, nu, smoother, kaczmarz_c, gL, gR, out, patches,
+                             order, 0, S);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -450,8 +460,9 @@ static int smooth_level(level_t *lv, int l, int M, int nu, const orc_options *o,
  *
  * order = 1 processes segments in reverse (block-order invariance test).
  */
-int orc_fmgsr_solve_ex(const double *f, double gL, double gR, int64_t n, int levels,
-                       int64_t S, int64_t b, const orc_options *o, double *u_out, int order)
+static int fmgsr_solve_core(const double *f, double gL, double gR, int64_t n, int levels,
+                            int64_t S, int64_t b, const orc_options *o, double *u_out,
+                            double *coarse_out, int order)
 {
   int M = validate(n, levels, S, b, o);
   if (M < 0) return M;
@@ -532,16 +543,67 @@ int orc_fmgsr_solve_ex(const double *f, double gL, double gR, int64_t n, int lev
     }
   }
   if (st == ORC_OK && M == 0) st = orc_coarse_solve(lv[0].Q, n, gL, gR, lv[0].u);
-  if (st == ORC_OK) memcpy(u_out, lv[M].u, sizeof(double) * (size_t)n);
+  if (st == ORC_OK && u_out) memcpy(u_out, lv[M].u, sizeof(double) * (size_t)n);
+  if (st == ORC_OK && coarse_out && M >= 1)
+    memcpy(coarse_out, lv[M - 1].u, sizeof(double) * (size_t)lv[M - 1].n);
   free(patches);
   free_levels(lv, M + 1);
   return st;
+}
+
+int orc_fmgsr_solve_ex(const double *f, double gL, double gR, int64_t n, int levels,
+                       int64_t S, int64_t b, const orc_options *o, double *u_out, int order)
+{
+  return fmgsr_solve_core(f, gL, gR, n, levels, S, b, o, u_out, NULL, order);
 }
 
 int orc_fmgsr_solve(const double *f, double gL, double gR, int64_t n, int levels,
                     int64_t S, int64_t b, const orc_options *o, double *u_out)
 {
   return orc_fmgsr_solve_ex(f, gL, gR, n, levels, S, b, o, u_out, 0);
+}
+
+/* The same iteration, also returning the level-(M-1) solution after the
+ * final V-cycle (coarse_out, n/2 cells; levels >= 2).  With an SR finest
+ * level that array and f determine the fine solution: the last step of the
+ * cycle rebuilds it from them alone (Eq. 5 and Fig. 5), which is the PDE
+ * compression of Sec. 2.4 that Sec. 3.2 proposes to store and expand on
+ * demand. */
+int orc_fmgsr_solve_keep(const double *f, double gL, double gR, int64_t n, int levels,
+                         int64_t S, int64_t b, const orc_options *o, double *u_out,
+                         double *coarse_out)
+{
+  if (levels < 2) return ORC_EINVAL;
+  return fmgsr_solve_core(f, gL, gR, n, levels, S, b, o, u_out, coarse_out, 0);
+}
+
+/* PDE decompression (Sec. 3.2, method 2): the fine solution on cells
+ * [lo, hi) from the stored level-(M-1) solution c (n/2 cells) and the fine
+ * forcing f.  This is the SR branch of the final post-smoothing step of
+ * Fig. 3 -- full update u = Pi c (Eq. 5), then nu2 times [Kaczmarz toward c,
+ * point sweep] on each extended patch with its exterior frozen (Fig. 5) --
+ * run only for the segments whose cores meet [lo, hi).  With the solve's S,
+ * b and options the result equals the solve's finest level on [lo, hi).
+ * out has hi - lo cells. */
+int orc_fmgsr_decompress(const double *c, const double *f, double gL, double gR, int64_t n,
+                         int64_t S, int64_t b, const orc_options *o, int64_t lo, int64_t hi,
+                         double *out)
+{
+  if (!o || n < 2 || n % 2 != 0 || S < 1 || n % S != 0 || (n / S) % 2 != 0 || b < 0 ||
+      o->nu2 < 0 || lo < 0 || hi > n || lo > hi)
+    return ORC_EINVAL;
+  if (lo == hi) return ORC_OK;
+  int64_t s = n / S;
+  double *ubar = (double *)malloc(sizeof(double) * (size_t)n);
+  double *u = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!ubar || !u) { free(ubar); free(u); return ORC_ENOMEM; }
+  orc_interp_fmg(c, n / 2, gL, gR, ubar);
+  int st = smooth_blocks_range(ubar, f, n, S, b, o->nu2, o->smoother, c, gL, gR, u, NULL, 0,
+                               lo / s, (hi - 1) / s + 1);
+  if (st == ORC_OK) memcpy(out, u + lo, sizeof(double) * (size_t)(hi - lo));
+  free(ubar);
+  free(u);
+  return st;
 }
 
 /* Additive block smoother as a stand-alone entry (tests of R4). */

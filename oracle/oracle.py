@@ -69,6 +69,12 @@ def lib():
         L.orc_fmgsr_solve_ex.argtypes = [_ptr, _dbl, _dbl, _i64, ctypes.c_int, _i64, _i64,
                                          ctypes.POINTER(Options), _ptr, ctypes.c_int]
         L.orc_fmgsr_solve_ex.restype = ctypes.c_int
+        L.orc_fmgsr_solve_keep.argtypes = [_ptr, _dbl, _dbl, _i64, ctypes.c_int, _i64, _i64,
+                                           ctypes.POINTER(Options), _ptr, _ptr]
+        L.orc_fmgsr_solve_keep.restype = ctypes.c_int
+        L.orc_fmgsr_decompress.argtypes = [_ptr, _ptr, _dbl, _dbl, _i64, _i64, _i64,
+                                           ctypes.POINTER(Options), _i64, _i64, _ptr]
+        L.orc_fmgsr_decompress.restype = ctypes.c_int
         L.orc_fas_vcycle.argtypes = [_ptr, _ptr, _dbl, _dbl, _i64, ctypes.c_int,
                                      ctypes.POINTER(Options)]
         L.orc_fas_vcycle.restype = ctypes.c_int
@@ -196,6 +202,36 @@ def fmgsr_solve(f, gL=0.0, gR=0.0, levels=None, segments=1, buffer=0, order=0, *
                                   ctypes.byref(o), out.ctypes.data_as(_ptr), order)
     if st != 0:
         raise ValueError(f"orc_fmgsr_solve failed with status {st}")
+    return out
+
+
+def fmgsr_solve_keep(f, gL=0.0, gR=0.0, levels=None, segments=1, buffer=0, **opt):
+    """One FMG-FAS(-SR) iteration returning (u, c): the finest level and the
+    level-(M-1) solution of the final V-cycle (the PDE-compressed form)."""
+    f, pf = _c(f)
+    n = f.size
+    if levels is None:
+        levels = int(np.log2(n)) + 1
+    o = options(**opt)
+    out = np.empty_like(f)
+    c = np.empty(n // 2)
+    st = lib().orc_fmgsr_solve_keep(pf, gL, gR, n, levels, segments, buffer, ctypes.byref(o),
+                                    out.ctypes.data_as(_ptr), c.ctypes.data_as(_ptr))
+    if st != 0:
+        raise ValueError(f"orc_fmgsr_solve_keep failed with status {st}")
+    return out, c
+
+
+def fmgsr_decompress(c, f, lo, hi, gL=0.0, gR=0.0, segments=1, buffer=0, **opt):
+    """Fine solution on [lo, hi) expanded from the level-(M-1) solution c."""
+    c, pc = _c(c)
+    f, pf = _c(f)
+    o = options(**opt)
+    out = np.empty(max(hi - lo, 0))
+    st = lib().orc_fmgsr_decompress(pc, pf, gL, gR, f.size, segments, buffer, ctypes.byref(o),
+                                    lo, hi, out.ctypes.data_as(_ptr))
+    if st != 0:
+        raise ValueError(f"orc_fmgsr_decompress failed with status {st}")
     return out
 
 

@@ -147,8 +147,9 @@ def make_segments(n, S, b):
 
 
 def fmgsr(f, levels, segments=1, buffer=0, nu1=2, nu2=1, nsr=1, tau="split",
-          rhs_restrict="fw", smoother="rb", block_all=0):
-    """Dense FMG-FAS-SR (one iteration), assembled tau on every level."""
+          rhs_restrict="fw", smoother="rb", block_all=0, keep_coarse=False):
+    """Dense FMG-FAS-SR (one iteration), assembled tau on every level.
+    keep_coarse: also return the level-(M-1) solution of the final cycle."""
     n = f.size
     M = levels - 1
     ns = [n >> (M - l) for l in range(M + 1)]
@@ -200,4 +201,16 @@ def fmgsr(f, levels, segments=1, buffer=0, nu1=2, nu2=1, nsr=1, tau="split",
                 u[m + 1] = u[m + 1] + Pl[m + 1] @ (u[m] - uh[m])
                 u[m + 1] = smooth(A[m + 1], u[m + 1], Q[m + 1], nu2, segs(m + 1),
                                   smoother=smoother)
-    return u[M]
+    return (u[M], u[M - 1]) if keep_coarse else u[M]
+
+
+def decompress(c, f, lo, hi, segments, buffer, nu2=1):
+    """Fine solution on [lo, hi) from the level-(M-1) solution c: the final
+    SR update (FMG interpolation, then nu2 x [Kaczmarz toward c, red-black
+    sweep] per extended patch) on the segments whose cores meet [lo, hi)."""
+    n = f.size
+    nc = n // 2
+    s = n // segments
+    segs = make_segments(n, segments, buffer)[lo // s:(hi - 1) // s + 1]
+    u = smooth(laplacian(n), fmg_interp(nc) @ c, f, nu2, segs, kacz=(restriction_avg(nc), c))
+    return u[lo:hi]
