@@ -43,7 +43,9 @@ typedef enum {
   FMGSR_EINVAL = -1,   /* argument out of range; nothing enqueued            */
   FMGSR_ENOMEM = -2,   /* workspace allocation failed or workspace too small */
   FMGSR_EDEVICE = -3,  /* a HIP runtime call or kernel launch failed         */
-  FMGSR_ENOTSUP = -4   /* valid request this library does not implement     */
+  FMGSR_ENOTSUP = -4,  /* valid request this library does not implement     */
+  FMGSR_ENONFINITE = -5 /* fmgsr_options.check_finite: NaN or Inf in the
+                           input (nothing solved) or in the result          */
 } fmgsr_status;
 
 /* How tau (Eq. 7) enters the coarse right-hand side (Eq. 6).
@@ -82,6 +84,15 @@ enum { FMGSR_OP_POISSON = 0, FMGSR_OP_CUBIC_REACTION = 1, FMGSR_OP_LINEAR_REACTI
  * discretisation error by 2.4x). */
 enum { FMGSR_FP64 = 0, FMGSR_FP32_RELAX = 1 };
 
+/* Restriction I of right-hand sides and residuals (Eq. 6, Eq. 7).
+ * FULLWEIGHT: full weighting, 1/2 of the transposed linear prolongation (the
+ *   appendix's commented alternative); with the average solution restriction
+ *   I^ it satisfies L_H I^ = I L_h exactly, which split tau relies on.
+ * AVERAGE: the two-cell average, the appendix's choice for both
+ *   restrictions (the paper's own transfer pair, Sec. 4); literal tau only
+ *   (FMGSR_EINVAL with split tau, where that identity fails). */
+enum { FMGSR_R_FULLWEIGHT = 0, FMGSR_R_AVERAGE = 1 };
+
 typedef struct {
   int32_t kind;          /* FMGSR_OP_*                                        */
   const double *kappa;   /* fmgsr_solve / fmgsr_adjoint: [n] coefficient at
@@ -116,6 +127,23 @@ typedef struct {
                             bit).  With functionals set, u_out may be NULL and
                             the fine solution is never written.  Needs a
                             segment core of at least 4 cells.                 */
+  double *coarse_out;    /* fmgsr_solve with sr_levels = 1: NULL, or a device
+                            array [n/2] that receives the level-(M-1)
+                            solution of the final V-cycle, from which the SR
+                            up pass rebuilds the finest level (Eq. 5, Fig. 5).
+                            With f it is the PDE-compressed solution (Sec. 2.4)
+                            that fmgsr_decompress expands on demand (Sec. 3.2,
+                            method 2).  With coarse_out set, u_out (and
+                            functionals) may be NULL: the SR up pass is then
+                            skipped.  Other sr_levels: FMGSR_ENOTSUP.         */
+  int32_t rhs_restriction; /* FMGSR_R_FULLWEIGHT (default) or FMGSR_R_AVERAGE */
+  int32_t check_finite;  /* 0 (default), or 1: fmgsr_solve scans f before
+                            solving and returns FMGSR_ENONFINITE, having
+                            solved nothing, if it holds a NaN or Inf, and
+                            scans the results (u_out, coarse_out,
+                            functionals) afterwards, returning
+                            FMGSR_ENONFINITE if one is not finite.  The call
+                            then synchronises hip_stream (not capturable).   */
 } fmgsr_options;
 
 /* Defaults: V(2,1), sr_levels = 1, split tau, FP64, library-managed
@@ -138,10 +166,10 @@ size_t fmgsr_workspace_bytes_for(int64_t n, int32_t levels, int64_t n_segments, 
  * these sizes, segments and options (0 if invalid): the single-workgroup
  * coarse core holds the level stack of the coarsest levels (Fig. 1's exact
  * solve and the V-cycle bottoms), the segment kernels a register stage and
- * exchange buffer per thread.  fmgsr_solve grants those kernels 160 KiB and
- * returns FMGSR_EINVAL, before enqueuing anything, when this figure exceeds
- * the grant or the device's opt-in limit per workgroup; FMGSR_EDEVICE when
- * the grant itself failed. */
+ * exchange buffer per thread.  fmgsr_solve grants each of those kernels the
+ * device's per-workgroup LDS limit (at most 160 KiB) less the kernel's static
+ * LDS, and returns FMGSR_EINVAL, before enqueuing anything, when a request
+ * exceeds its kernel's grant; FMGSR_EDEVICE when a grant itself failed. */
 size_t fmgsr_launch_lds_bytes(int64_t n, int32_t levels, int64_t n_segments, int32_t buffer,
                               const fmgsr_options *opt);
 
@@ -181,6 +209,33 @@ fmgsr_status fmgsr_solve(const fmgsr_operator *op, const double *f, double g_lef
                          double g_right, int64_t n, int32_t levels, int64_t n_segments,
                          int32_t buffer, const fmgsr_options *opt, double *u_out,
                          void *hip_stream);
+
+/*
+ * fmgsr_decompress -- PDE decompression (Sec. 3.2, method 2): the finest-level
+ * solution on cells [lo, hi), expanded from the stored level-(M-1) solution
+ * (fmgsr_options.coarse_out of a solve with one SR level) by the SR up pass
+ * of the segments whose cores meet [lo, hi): full update Pi c (Eq. 5), then
+ * nu2 x [Kaczmarz projection onto I^ u = c (Eq. 8, Fig. 5), red-black sweep]
+ * on each extended patch with its exterior frozen.  Only local data is read:
+ * the covering segments' patches of f and their coarse image.
+ *
+ *   coarse      [n/2] level-(M-1) solution (device).
+ *   f           [n] finest right-hand side of the solve (device).
+ *   g_left, g_right, n, n_segments, buffer
+ *               as in the solve (n_segments divides n, even core).
+ *   opt         nu2 and precision as in the solve (NULL = defaults); other
+ *               fields ignored.
+ *   lo, hi      0 <= lo <= hi <= n; hi == lo enqueues nothing.
+ *   u_out       [hi - lo] receives u[lo..hi) (device).
+ *
+ * With the solve's segments, buffer and options the result equals that
+ * solve's u_out on [lo, hi) bit for bit.  Asynchronous on hip_stream;
+ * allocates nothing.
+ */
+fmgsr_status fmgsr_decompress(const double *coarse, const double *f, double g_left,
+                              double g_right, int64_t n, int64_t n_segments, int32_t buffer,
+                              const fmgsr_options *opt, int64_t lo, int64_t hi, double *u_out,
+                              void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Batched solves: many independent problems of uneven size in ONE persistent

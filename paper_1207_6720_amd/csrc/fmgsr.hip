@@ -39,6 +39,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "fmgsr.h"
@@ -213,6 +214,9 @@ struct Plan {
   int d_down = 1, d_up = 1;
   int d_srup = 0;  // levels of an up kernel topped by the SR level (0: none fit)
   bool functionals = false;
+  // the final level-(M-1) solution goes to the caller (PDE compression)
+  bool keep_coarse = false;
+  int ravg = 0;  // literal tau with the two-cell average as rhs restriction
   // one SR level whose segment passes are exact as the top level of the
   // vertical kernels (set with the segments)
   bool fuse_down = false, fuse_up = false;
@@ -224,8 +228,8 @@ struct Plan {
   int R = 1;
   int seg2_threads = 0;
   // workspace layout (byte offsets)
-  size_t off_F = 0, off_U = 0, off_V = 0, off_Uh = 0, off_Q = 0, off_Utop = 0, off_P = 0,
-         total = 0;
+  size_t off_flag = 0, off_F = 0, off_U = 0, off_V = 0, off_Uh = 0, off_Q = 0, off_Utop = 0,
+         off_P = 0, total = 0;
 };
 
 // Geometry, options and workspace layout (segment arguments excluded).
@@ -242,8 +246,18 @@ fmgsr_status make_plan(int64_t n, int32_t levels, const fmgsr_options& o, Plan* 
   if (o.tau_mode != FMGSR_TAU_SPLIT && o.tau_mode != FMGSR_TAU_LITERAL) return FMGSR_EINVAL;
   if (o.precision != FMGSR_FP64 && o.precision != FMGSR_FP32_RELAX) return FMGSR_EINVAL;
   if (o.reserved != 0) return FMGSR_EINVAL;
+  if (o.check_finite != 0 && o.check_finite != 1) return FMGSR_EINVAL;
+  if (o.rhs_restriction != FMGSR_R_FULLWEIGHT && o.rhs_restriction != FMGSR_R_AVERAGE)
+    return FMGSR_EINVAL;
+  // split tau rests on L_H I^ = I L_h, which holds for full weighting only
+  if (o.rhs_restriction == FMGSR_R_AVERAGE && o.tau_mode != FMGSR_TAU_LITERAL) return FMGSR_EINVAL;
+  p->ravg = (o.rhs_restriction == FMGSR_R_AVERAGE);
   p->f32 = (o.precision == FMGSR_FP32_RELAX);
   p->functionals = (o.functionals != nullptr);
+  p->keep_coarse = (o.coarse_out != nullptr);
+  if (p->keep_coarse && M < 1) return FMGSR_EINVAL;
+  // the compressed form is the level below the one SR level
+  if (p->keep_coarse && o.sr_levels != 1) return FMGSR_ENOTSUP;
   // literal tau differentiates the iterate (L_h u), amplifying the FP32
   // rounding of the relaxation by ~n^2 into every coarse right-hand side
   if (p->f32 && o.tau_mode == FMGSR_TAU_LITERAL) return FMGSR_ENOTSUP;
@@ -271,6 +285,7 @@ fmgsr_status make_plan(int64_t n, int32_t levels, const fmgsr_options& o, Plan* 
   const size_t hierV = two ? (size_t)lvl_off_ws(n0, M - 1) * sizeof(double) : hier;
   const size_t hierU = two ? hierV + (size_t)(n >> 2) * sizeof(double) : hier;
   size_t off = 0;
+  p->off_flag = off; off = align_up(off + sizeof(int));  // non-finite flag
   p->off_F = off; off = align_up(off + hier);
   p->off_U = off; off = align_up(off + hierU);
   p->off_V = off; off = align_up(off + hierV);
@@ -314,7 +329,9 @@ fmgsr_status plan_segments(int64_t n_segments, int32_t buffer, Plan* p) {
   // SR down / up passes are exact as the top level of a vertical kernel.
   p->fuse_down = p->nsr == 1 && !p->literal && buffer >= 2 * (int64_t)p->nu1 - 1 &&
                  p->d_down >= 2 && p->M - 1 > p->C;
-  p->fuse_up = p->fuse_down && buffer >= 2 * (int64_t)p->nu2 &&
+  // (kept coarse solution: the up leg stores level M-1 and the segment pass
+  // expands it)
+  p->fuse_up = p->fuse_down && buffer >= 2 * (int64_t)p->nu2 && !p->keep_coarse &&
                std::min(p->d_srup, p->M - p->C) >= 2;
   if (p->nsr >= 2) {
     // level-(M-1) margin: pad/2 + 2 cells for Pi's reach from the level-M
@@ -378,34 +395,68 @@ size_t plan_lds(const Plan& p) {
   return m;
 }
 
-// Dynamic LDS the kernels above are granted (hipFuncAttributeMaxDynamicSharedMemorySize).
-constexpr size_t kDynLds = 160 * 1024;
+// Upper bound of the LDS one workgroup may hold on gfx950 (static + dynamic).
+constexpr size_t kMaxLds = 160 * 1024;
+
+// Dynamic LDS a kernel may be granted: the device's per-workgroup limit
+// (capped at kMaxLds) less the kernel's own static LDS.  The runtime refuses
+// a grant that, added to the static part, exceeds the limit (the coarse core
+// keeps a small static table, so a flat 160 KiB grant is refused for it).
+size_t lds_grant(size_t limit, size_t static_bytes) {
+  const size_t cap = std::min(limit, kMaxLds);
+  return static_bytes < cap ? cap - static_bytes : 0;
+}
 
 // Grants the dynamic-LDS attribute to every kernel that takes dynamic LDS
-// (once per process; a failure is remembered and reported by every solve),
-// then checks that this plan's largest request fits both the grant and the
-// current device's opt-in limit, so an oversized request becomes an error
-// code instead of a launch the device cannot honour.
+// (once per device; each call's return code is checked and a failure is
+// remembered and reported by every solve on that device), then checks that
+// this plan's requests fit the grants, so an oversized request becomes an
+// error code instead of a launch the device cannot honour.
 fmgsr_status check_lds(const Plan& p) {
-  static std::once_flag once;
-  static hipError_t granted = hipSuccess;
-  std::call_once(once, [] {
-    const void* ks[] = {(const void*)k_coarse_core,
-                        (const void*)k_sr_down<kSegRun, false>, (const void*)k_sr_up<kSegRun, false>,
-                        (const void*)k_sr_down<kSegRun, true>, (const void*)k_sr_up<kSegRun, true>,
-                        (const void*)k_sr2<kSegRun, false, false>, (const void*)k_sr2<kSegRun, false, true>,
-                        (const void*)k_sr2<kSegRun, true, false>, (const void*)k_sr2<kSegRun, true, true>};
-    for (const void* k : ks) {
-      const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds);
-      if (e != hipSuccess && granted == hipSuccess) granted = e;
-    }
+  constexpr int kMaxDev = 64;
+  struct Grants {
+    bool done = false;
+    hipError_t err = hipSuccess;
+    size_t core = 0, seg = 0;
+  };
+  static std::mutex mu;
+  static Grants grants[kMaxDev];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) {
     (void)hipGetLastError();
-  });
-  if (granted != hipSuccess) return FMGSR_EDEVICE;
-  size_t limit = 0;
-  if (device_lds_limit(&limit) != hipSuccess) return FMGSR_EDEVICE;
-  const size_t need = plan_lds(p);
-  return (need <= kDynLds && need <= limit) ? FMGSR_OK : FMGSR_EINVAL;
+    return FMGSR_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  Grants& g = grants[dev];
+  if (!g.done) {
+    g.done = true;
+    size_t limit = 0;
+    g.err = device_lds_limit(&limit);
+    auto grant = [&](const void* k, size_t* granted) {
+      if (g.err != hipSuccess) return;
+      hipFuncAttributes fa;
+      g.err = hipFuncGetAttributes(&fa, k);
+      if (g.err != hipSuccess) return;
+      const size_t v = lds_grant(limit, fa.sharedSizeBytes);
+      g.err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)v);
+      if (g.err == hipSuccess) *granted = std::min(*granted, v);
+    };
+    size_t core = SIZE_MAX, seg = SIZE_MAX;
+    grant((const void*)k_coarse_core, &core);
+    const void* segk[] = {(const void*)k_sr_down<kSegRun, false>, (const void*)k_sr_up<kSegRun, false>,
+                          (const void*)k_sr_down<kSegRun, true>, (const void*)k_sr_up<kSegRun, true>,
+                          (const void*)k_sr2<kSegRun, false, false>, (const void*)k_sr2<kSegRun, false, true>,
+                          (const void*)k_sr2<kSegRun, true, false>, (const void*)k_sr2<kSegRun, true, true>};
+    for (const void* k : segk) grant(k, &seg);
+    if (g.err != hipSuccess) (void)hipGetLastError();
+    g.core = core;
+    g.seg = seg;
+  }
+  if (g.err != hipSuccess) return FMGSR_EDEVICE;
+  if (core_lds(p) > g.core) return FMGSR_EINVAL;
+  if (p.nsr >= 1 && seg_lds(p.seg_threads) > g.seg) return FMGSR_EINVAL;
+  if (p.nsr >= 2 && seg_lds(p.seg2_threads) > g.seg) return FMGSR_EINVAL;
+  return FMGSR_OK;
 }
 
 struct Ctx {
@@ -415,6 +466,7 @@ struct Ctx {
   const double* f;
   double* u_out;
   double* functionals = nullptr;  // [2] device: h sum u, h sum u^2 of the result
+  double* coarse_out = nullptr;   // [n/2] device: the final level-(M-1) solution
   double *F, *U, *V, *Uh, *Q, *Utop;
   double* P;  // per-tile functional partials
   fmgsr_status err = FMGSR_OK;
@@ -549,6 +601,7 @@ struct Ctx {
   void forcing_launch(int src_level, int levels) {
     VertArgs a = vargs(src_level, levels, 0);
     a.rhs = forcing(src_level);
+    a.ravg = p->ravg;
     double bytes = (double)a.n * 8.0;
     for (int i = 0; i < levels; ++i) {
       a.out[i] = lv(F, src_level - 1 - i);
@@ -565,11 +618,12 @@ struct Ctx {
     const int thr = 256;
     ProfScope ps("k_tau_literal", (double)nc * 8.0 * 5.0, st);  // u, F: 2 nc each; out: nc
     hipLaunchKernelGGL(k_tau_literal, dim3((unsigned)((nc + thr - 1) / thr)), dim3(thr), 0, st,
-                       ufine, Ffine, nc, gL, gR, out);
+                       ufine, Ffine, nc, gL, gR, p->ravg, out);
     check();
   }
 
-  void core_launch(int mode, int src_kind, const double* src, const double* rhs_top) {
+  void core_launch(int mode, int src_kind, const double* src, const double* rhs_top,
+                   double* out = nullptr) {
     CoreArgs a;
     std::memset(&a, 0, sizeof(a));
     a.top = p->C;
@@ -579,12 +633,13 @@ struct Ctx {
     a.nu1 = p->nu1;
     a.nu2 = p->nu2;
     a.literal = p->literal;
+    a.ravg = p->ravg;
     a.mode = mode;
     a.src_kind = src_kind;
     for (int l = 0; l <= p->C; ++l) a.F[l] = forcing(l);
     a.src = src;
     a.rhs_top = rhs_top;
-    a.out = (p->M >= 1) ? lv(V, p->C) : u_out;
+    a.out = out ? out : (p->M >= 1) ? lv(V, p->C) : u_out;
     const int64_t ntot = p->n0 * (((int64_t)1 << (p->C + 1)) - 1);
     const size_t lds = core_lds(*p);
     const int64_t nC = p->n0 << p->C;
@@ -617,6 +672,10 @@ struct Ctx {
     a.f = forcing(l);
     a.out = out;
     a.q_out = q_out;
+    a.ravg = p->ravg;
+    a.seg0 = 0;
+    a.out_lo = 0;
+    a.out_hi = a.n;
     const int64_t thr = (a.win + kSegRun - 1) / kSegRun;
     const int threads = finest ? p->seg_threads : (int)((thr + 63) / 64 * 64);
     const double nb = (double)a.n * 8.0;
@@ -701,6 +760,11 @@ struct Ctx {
       // with two or more SR levels, level M-1 is never stored either: the
       // finest passes rebuild it from V^{M-2}
       const bool two = (P.nsr >= 2);
+      // post-smoothed iterate of level l in this step: the final step's
+      // level-(M-1) solution goes to the caller's array when it is kept
+      auto Vout = [&](int l) -> double* {
+        return (t == M && l == M - 1 && coarse_out) ? coarse_out : lv(V, l);
+      };
       // One SR level with split tau and b >= 2 nu1 - 1: the block smoother's
       // cores equal global red-black sweeps bit for bit, so the SR down pass
       // (Pi, sweeps, I^ of the cores) is the top level of an ordinary
@@ -748,11 +812,11 @@ struct Ctx {
       }
       // coarse core: V-cycle bottom from level C
       if (sr && !fused_down && C == top) {
-        core_launch(1, kSrcDirect, H(C), rhs_of(C));
+        core_launch(1, kSrcDirect, H(C), rhs_of(C), Vout(C));
       } else {
         const double* uf = U_of(C + 1);
         if (P.literal) tau_launch(uf, rhs_of(C + 1), C, lv(Q, C));
-        core_launch(1, kSrcRestrict, uf, rhs_of(C));
+        core_launch(1, kSrcRestrict, uf, rhs_of(C), Vout(C));
       }
       // One SR level, split tau, b >= 2 nu2, no functionals: the SR up pass
       // (Pi + compatible relaxation) equals the unsegmented one on the cores
@@ -769,7 +833,7 @@ struct Ctx {
         const int hi = his[k];
         const int d = std::min(P.d_up, hi - C);
         const int lo = hi - d + 1;
-        double* out = (hi == top && !sr) ? ((t == M) ? u_out : lv(V, t)) : lv(V, hi);
+        double* out = (hi == top && !sr) ? ((t == M) ? u_out : lv(V, t)) : Vout(hi);
         const double* rsrc = (rebuild && hi == t) ? lv(V, t - 1) : nullptr;
         up_launch(hi, d, rhs_of(hi), lv(V, lo - 1), U_of(hi), out, rsrc, false,
                   deep_stored && hi == t);
@@ -788,8 +852,10 @@ struct Ctx {
         // full update and compatible relaxation on each SR level, upwards
         for (int l = sr_lo; l <= t; ++l) {
           if (two && l == M - 1) continue;  // rebuilt by the finest passes
+          // compression only: the kept level-(M-1) solution is the result
+          if (l == M && !u_out && !functionals) continue;
           if (two && l == M) seg2_launch(true);
-          else seg_launch(l, true, lv(V, l - 1), nullptr, l == M ? u_out : lv(V, l), nullptr);
+          else seg_launch(l, true, Vout(l - 1), nullptr, l == M ? u_out : lv(V, l), nullptr);
         }
         if (functionals && t == M) {
           ProfScope ps("k_functionals", (double)P.S * 16.0 + 16.0, st);
@@ -849,6 +915,117 @@ size_t fmgsr_launch_lds_bytes(int64_t n, int32_t levels, int64_t n_segments, int
   return plan_lds(p);
 }
 
+}  // extern "C"
+
+namespace fmgsr {
+namespace {
+
+// NaN / Inf scan of device arrays for check_finite: clears the workspace
+// flag, scans each array, copies the flag back and synchronises the stream.
+fmgsr_status scan_finite(const std::vector<std::pair<const double*, int64_t>>& arrays, int* flag,
+                         hipStream_t stream) {
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, stream, flag);
+  for (const auto& arr : arrays) {
+    const int64_t blocks = std::min<int64_t>((arr.second + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0,
+                       stream, arr.first, arr.second, flag);
+  }
+  int h = 0;
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return FMGSR_EDEVICE;
+  }
+  return h ? FMGSR_ENONFINITE : FMGSR_OK;
+}
+
+// fmgsr_solve for the Poisson operator.  static_ws: a workspace the library
+// owns (static_bytes bytes), used instead of the caller's workspace or a
+// stream-ordered allocation.
+fmgsr_status solve_poisson(const double* f, double g_left, double g_right, int64_t n,
+                           int32_t levels, int64_t n_segments, int32_t buffer,
+                           const fmgsr_options& o, double* u_out, void* hip_stream,
+                           char* static_ws, size_t static_bytes) {
+  Plan p;
+  fmgsr_status st = make_plan(n, levels, o, &p);
+  if (st == FMGSR_OK) st = plan_segments(n_segments, buffer, &p);
+  if (st != FMGSR_OK) return st;
+  // on-the-fly functionals (SR level only); u_out may then be NULL: the fine
+  // solution never reaches HBM
+  if (o.functionals) {
+    if (p.nsr < 1 || p.s < 4 || !is_device_ptr(o.functionals)) return FMGSR_EINVAL;
+  }
+  if (o.coarse_out) {
+    if (!is_device_ptr(o.coarse_out) || (const void*)o.coarse_out == (const void*)f ||
+        o.coarse_out == u_out)
+      return FMGSR_EINVAL;
+  }
+  if (!is_device_ptr(f) || (u_out ? !is_device_ptr(u_out) : !(o.functionals || o.coarse_out)))
+    return FMGSR_EINVAL;
+  if ((const void*)f == (const void*)u_out) return FMGSR_EINVAL;
+  if (const fmgsr_status lst = check_lds(p); lst != FMGSR_OK) return lst;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  char* ws = (char*)o.workspace;
+  bool own = false;
+  if (static_ws) {
+    if (plan_bytes(p) > static_bytes) return FMGSR_ENOMEM;
+    ws = static_ws;
+  } else if (ws) {
+    if (o.workspace_bytes < plan_bytes(p) || !is_device_ptr(ws)) return FMGSR_ENOMEM;
+  } else {
+    if (hipMallocAsync((void**)&ws, plan_bytes(p), stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return FMGSR_ENOMEM;
+    }
+    own = true;
+  }
+  // check_finite: scan f before solving (nothing is solved if it fails)
+  int* flag = (int*)(ws + p.off_flag);
+  if (o.check_finite) {
+    const fmgsr_status fst = scan_finite({{f, n}}, flag, stream);
+    if (fst != FMGSR_OK) {
+      if (own && hipFreeAsync(ws, stream) != hipSuccess) (void)hipGetLastError();
+      return fst;
+    }
+  }
+  Ctx c;
+  c.p = &p;
+  c.st = stream;
+  c.gL = g_left;
+  c.gR = g_right;
+  c.f = f;
+  c.u_out = u_out;
+  c.functionals = o.functionals;
+  c.coarse_out = o.coarse_out;
+  c.F = (double*)(ws + p.off_F);
+  c.U = (double*)(ws + p.off_U);
+  c.V = (double*)(ws + p.off_V);
+  c.Uh = (double*)(ws + p.off_Uh);
+  c.Q = (double*)(ws + p.off_Q);
+  c.Utop = (double*)(ws + p.off_Utop);
+  c.P = (double*)(ws + p.off_P);
+  c.run();
+  // check_finite: scan the results
+  if (c.err == FMGSR_OK && o.check_finite) {
+    std::vector<std::pair<const double*, int64_t>> outs;
+    if (u_out) outs.push_back({u_out, n});
+    if (o.coarse_out) outs.push_back({o.coarse_out, n / 2});
+    if (o.functionals) outs.push_back({o.functionals, 2});
+    c.err = scan_finite(outs, flag, stream);
+  }
+  if (own && hipFreeAsync(ws, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    if (c.err == FMGSR_OK) c.err = FMGSR_EDEVICE;
+  }
+  return c.err;
+}
+
+}  // namespace
+}  // namespace fmgsr
+
+extern "C" {
+
 fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_left,
                          double g_right, int64_t n, int32_t levels, int64_t n_segments,
                          int32_t buffer, const fmgsr_options* opt, double* u_out,
@@ -866,51 +1043,66 @@ fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_lef
   fmgsr_options o;
   if (opt) o = *opt;
   else fmgsr_default_options(&o);
+  return solve_poisson(f, g_left, g_right, n, levels, n_segments, buffer, o, u_out, hip_stream,
+                       nullptr, 0);
+}
+
+fmgsr_status fmgsr_decompress(const double* coarse, const double* f, double g_left,
+                              double g_right, int64_t n, int64_t n_segments, int32_t buffer,
+                              const fmgsr_options* opt, int64_t lo, int64_t hi, double* u_out,
+                              void* hip_stream) {
+  fmgsr_options o;
+  if (opt) o = *opt;
+  else fmgsr_default_options(&o);
+  if (n < 2 || (n & 1) || o.nu2 < 0 || o.nu2 > 16) return FMGSR_EINVAL;
+  if (o.precision != FMGSR_FP64 && o.precision != FMGSR_FP32_RELAX) return FMGSR_EINVAL;
+  if (lo < 0 || hi > n || lo > hi) return FMGSR_EINVAL;
+  // the finest level as the one SR level of a hierarchy: its segment
+  // geometry (core, window, threads) exactly as in the solve.  No coarse
+  // core runs here, so the plan's core is a single cell (its LDS request
+  // must not count).
   Plan p;
-  fmgsr_status st = make_plan(n, levels, o, &p);
-  if (st == FMGSR_OK) st = plan_segments(n_segments, buffer, &p);
-  if (st != FMGSR_OK) return st;
-  // on-the-fly functionals (SR level only); u_out may then be NULL: the fine
-  // solution never reaches HBM
-  if (o.functionals) {
-    if (p.nsr < 1 || p.s < 4 || !is_device_ptr(o.functionals)) return FMGSR_EINVAL;
-  }
-  if (!is_device_ptr(f) || (u_out ? !is_device_ptr(u_out) : !o.functionals)) return FMGSR_EINVAL;
-  if ((const void*)f == (const void*)u_out) return FMGSR_EINVAL;
+  p.n = n;
+  p.n0 = 1;
+  p.M = 1;
+  p.C = 0;
+  p.nu1 = 0;
+  p.nu2 = o.nu2;
+  p.nsr = 1;
+  p.f32 = (o.precision == FMGSR_FP32_RELAX);
+  if (const fmgsr_status st = plan_segments(n_segments, buffer, &p); st != FMGSR_OK) return st;
+  if (!is_device_ptr(coarse) || !is_device_ptr(f) || !is_device_ptr(u_out)) return FMGSR_EINVAL;
+  if ((const void*)u_out == (const void*)f || (const void*)u_out == (const void*)coarse)
+    return FMGSR_EINVAL;
+  if (lo == hi) return FMGSR_OK;
   if (const fmgsr_status lst = check_lds(p); lst != FMGSR_OK) return lst;
+  SegArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.gL = g_left;
+  a.gR = g_right;
+  a.nu = o.nu2;
+  a.s = p.s;
+  a.buffer = p.b;
+  a.pad = p.pad;
+  a.win = (int)(p.s + 2 * p.pad);
+  a.coarse = coarse;
+  a.f = f;
+  a.out = u_out;
+  a.seg0 = lo / p.s;
+  a.out_lo = lo;
+  a.out_hi = hi;
+  const int64_t segs = (hi - 1) / p.s - a.seg0 + 1;
   hipStream_t stream = (hipStream_t)hip_stream;
-  char* ws = (char*)o.workspace;
-  bool own = false;
-  if (ws) {
-    if (o.workspace_bytes < plan_bytes(p) || !is_device_ptr(ws)) return FMGSR_ENOMEM;
-  } else {
-    if (hipMallocAsync((void**)&ws, plan_bytes(p), stream) != hipSuccess) {
-      (void)hipGetLastError();
-      return FMGSR_ENOMEM;
-    }
-    own = true;
-  }
-  Ctx c;
-  c.p = &p;
-  c.st = stream;
-  c.gL = g_left;
-  c.gR = g_right;
-  c.f = f;
-  c.u_out = u_out;
-  c.functionals = o.functionals;
-  c.F = (double*)(ws + p.off_F);
-  c.U = (double*)(ws + p.off_U);
-  c.V = (double*)(ws + p.off_V);
-  c.Uh = (double*)(ws + p.off_Uh);
-  c.Q = (double*)(ws + p.off_Q);
-  c.Utop = (double*)(ws + p.off_Utop);
-  c.P = (double*)(ws + p.off_P);
-  c.run();
-  if (own && hipFreeAsync(ws, stream) != hipSuccess) {
-    (void)hipGetLastError();
-    if (c.err == FMGSR_OK) c.err = FMGSR_EDEVICE;
-  }
-  return c.err;
+  const size_t lds = seg_lds(p.seg_threads);
+  // covering patches of f, their coarse image (Pi's reach included), u_out
+  const double bytes = 8.0 * ((double)segs * (double)(p.s + 2 * p.b) +
+                              (double)segs * (double)(p.s / 2 + p.b / 2 + 4) + (double)(hi - lo));
+  ProfScope ps("k_sr_up", bytes, stream);
+  const dim3 g((unsigned)segs), b(p.seg_threads);
+  if (p.f32) hipLaunchKernelGGL((k_sr_up<kSegRun, true>), g, b, lds, stream, a);
+  else hipLaunchKernelGGL((k_sr_up<kSegRun, false>), g, b, lds, stream, a);
+  return hipGetLastError() == hipSuccess ? FMGSR_OK : FMGSR_EDEVICE;
 }
 
 fmgsr_status fmgsr_profile_enable(const char* filter) {
@@ -964,6 +1156,7 @@ const char* fmgsr_status_string(int32_t status) {
     case FMGSR_ENOMEM: return "FMGSR_ENOMEM: workspace allocation failed or too small";
     case FMGSR_EDEVICE: return "FMGSR_EDEVICE: HIP runtime or launch failure";
     case FMGSR_ENOTSUP: return "FMGSR_ENOTSUP: not implemented by this library";
+    case FMGSR_ENONFINITE: return "FMGSR_ENONFINITE: NaN or Inf in the input or the result";
     default: return "unknown fmgsr status";
   }
 }

@@ -1220,7 +1220,12 @@ fmgsr_status fmgsr_batch_create(int32_t batch, const int64_t* n_host, const int6
   if (o.nu1 < 0 || o.nu1 > 16 || o.nu2 < 0 || o.nu2 > 16) return FMGSR_EINVAL;
   if (o.precision != FMGSR_FP64 && o.precision != FMGSR_FP32_RELAX) return FMGSR_EINVAL;
   if (o.reserved != 0) return FMGSR_EINVAL;
-  if (o.tau_mode != FMGSR_TAU_SPLIT || o.functionals) return FMGSR_ENOTSUP;
+  if (o.check_finite != 0 && o.check_finite != 1) return FMGSR_EINVAL;
+  if (o.rhs_restriction != FMGSR_R_FULLWEIGHT && o.rhs_restriction != FMGSR_R_AVERAGE)
+    return FMGSR_EINVAL;
+  if (o.tau_mode != FMGSR_TAU_SPLIT || o.functionals || o.coarse_out || o.check_finite ||
+      o.rhs_restriction != FMGSR_R_FULLWEIGHT)
+    return FMGSR_ENOTSUP;
   auto* b = new (std::nothrow) fmgsr_batch_s;
   if (!b) return FMGSR_ENOMEM;
   b->batch = batch;

@@ -378,10 +378,17 @@ __device__ __forceinline__ void restrict_runs(const double (&u)[K], const double
   }
 }
 
-// Same full weighting for a right-hand side only.
+// Same full weighting for a right-hand side only.  avg (uniform per launch):
+// the two-cell average instead, the rhs restriction of the paper's appendix.
 template <int K>
 __device__ __forceinline__ void restrict_rhs_run(const double (&f)[K], double (&f1)[K / 2],
-                                                 int64_t g0, int64_t nf, Xch& x) {
+                                                 int64_t g0, int64_t nf, Xch& x,
+                                                 bool avg = false) {
+  if (avg) {
+#pragma unroll
+    for (int p = 0; p < K / 2; ++p) f1[p] = (f[2 * p] + f[2 * p + 1]) * 0.5;
+    return;
+  }
   double fl, fr;
   x.swap(f[0], f[K - 1], fl, fr);
   const RunBounds rb = run_bounds(g0, K, 0, nf, nf);
@@ -530,9 +537,15 @@ __device__ __forceinline__ void interp_fast1(double (&u)[K], const double (&c)[K
   interp_ring<K>(u, c, cbase, l2, l1, r0, r1);
 }
 
-// Full weighting of a run (no boundary cases).
+// Full weighting of a run (no boundary cases); avg as in restrict_rhs_run.
 template <int K>
-__device__ __forceinline__ void fw_fast(const double (&f)[K], double (&f1)[K / 2], Xch& x) {
+__device__ __forceinline__ void fw_fast(const double (&f)[K], double (&f1)[K / 2], Xch& x,
+                                        bool avg = false) {
+  if (avg) {
+#pragma unroll
+    for (int p = 0; p < K / 2; ++p) f1[p] = (f[2 * p] + f[2 * p + 1]) * 0.5;
+    return;
+  }
   double fl, fr;
   x.swap(f[0], f[K - 1], fl, fr);
 #pragma unroll

@@ -179,6 +179,7 @@ struct VertArgs {
   // tile of workgroup b: tile0 + b, plus gap from b = gap_at on (a launch
   // over a subset of the tiles); tile: the result, set by the kernel
   int64_t tile0, gap_at, gap, tile;
+  int ravg;              // forcing: rhs restriction = two-cell average
   int deep;              // a down / up pair over the same levels whose up
                          // kernel rebuilds, on interior tiles, the pre-smoothed
                          // iterates of levels 0..levels-2 from src (down:
@@ -703,7 +704,7 @@ __device__ void forcing_level(const VertArgs& a, double* st, Xch& x, const doubl
   if constexpr (I < kMaxFuse && K >= 2) {
     if (I < a.levels) {
       double f1[K / 2];
-      restrict_rhs_run<K>(f, f1, G.g0, G.n, x);
+      restrict_rhs_run<K>(f, f1, G.g0, G.n, x, a.ravg);
       forcing_level<K / 2, I + 1>(a, st, x, f1);
     }
   }
@@ -718,7 +719,7 @@ __device__ void forcing_level_fast(const VertArgs& a, double* st, Xch& x, double
   if constexpr (I < kMaxFuse && K >= 2) {
     if (I < a.levels) {
       double f1[K / 2];
-      fw_fast<K>(f, f1, x);
+      fw_fast<K>(f, f1, x, a.ravg);
       forcing_level_fast<K / 2, I + 1>(a, st, x, f1, wlo0);
     }
   }
@@ -756,17 +757,24 @@ __device__ __forceinline__ double fine_residual(const double* __restrict__ u,
   return F[k] - (2.0 * u[k] - (l + r)) * w;
 }
 
+// ravg: the rhs restriction is the two-cell average instead of full weighting.
 __global__ void k_tau_literal(const double* __restrict__ u, const double* __restrict__ F,
-                              int64_t nc, double gL, double gR, double* __restrict__ out) {
+                              int64_t nc, double gL, double gR, int ravg,
+                              double* __restrict__ out) {
   const int64_t J = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (J >= nc) return;
   const int64_t nf = 2 * nc;
   const double w = (double)nf * (double)nf, wc = (double)nc * (double)nc;
   const double r1 = fine_residual(u, F, 2 * J, nf, w, gL, gR);
   const double r2 = fine_residual(u, F, 2 * J + 1, nf, w, gL, gR);
-  const double rm = (J > 0) ? fine_residual(u, F, 2 * J - 1, nf, w, gL, gR) : -r1;
-  const double rp = (2 * J + 2 < nf) ? fine_residual(u, F, 2 * J + 2, nf, w, gL, gR) : -r2;
-  const double IR = ((rm + rp) + 3.0 * (r1 + r2)) * 0.125;
+  double IR;
+  if (ravg) {
+    IR = (r1 + r2) * 0.5;
+  } else {
+    const double rm = (J > 0) ? fine_residual(u, F, 2 * J - 1, nf, w, gL, gR) : -r1;
+    const double rp = (2 * J + 2 < nf) ? fine_residual(u, F, 2 * J + 2, nf, w, gL, gR) : -r2;
+    IR = ((rm + rp) + 3.0 * (r1 + r2)) * 0.125;
+  }
   const double u0 = (u[2 * J] + u[2 * J + 1]) * 0.5;
   const double ul = (J > 0) ? (u[2 * J - 2] + u[2 * J - 1]) * 0.5 : 2.0 * gL - u0;
   const double ur = (J < nc - 1) ? (u[2 * J + 2] + u[2 * J + 3]) * 0.5 : 2.0 * gR - u0;
@@ -793,9 +801,14 @@ struct SegArgs {
                          // level-n array (I^ of the finer SR level) instead of
                          // Pi coarse; nullptr otherwise
   const double* f;       // fine right-hand side
-  double* out;           // down: I^ of the smoothed cores [n/2]; up: u_out [n] or nullptr
+  double* out;           // down: I^ of the smoothed cores [n/2]; up: u_out or nullptr
   double* q_out;         // down, literal tau: coarse rhs [n/2] (else nullptr)
+  int ravg;              // literal tau: rhs restriction = two-cell average
   double* part;          // up: per-segment (sum u, sum u^2) of the core, or nullptr
+  // up: workgroup b runs segment seg0 + b and writes its core cells g in
+  // [out_lo, out_hi) to out[g - out_lo] (a solve: 0, 0, n; a decompression:
+  // the requested range)
+  int64_t seg0, out_lo, out_hi;
 };
 
 
@@ -884,9 +897,14 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
     q[p] = 0.0;
     if (g >= core_lo && g < core_hi) {
       const double ra = res(m), rb = res(m + 1);
-      const double rm = (J > 0) ? res(m - 1) : -ra;
-      const double rp = (2 * J + 2 < n) ? res(m + 2) : -rb;
-      const double IR = ((rm + rp) + 3.0 * (ra + rb)) * 0.125;
+      double IR;
+      if (a.ravg) {
+        IR = (ra + rb) * 0.5;
+      } else {
+        const double rm = (J > 0) ? res(m - 1) : -ra;
+        const double rp = (2 * J + 2 < n) ? res(m + 2) : -rb;
+        IR = ((rm + rp) + 3.0 * (ra + rb)) * 0.125;
+      }
       const double u0 = (w[m] + w[m + 1]) * 0.5;
       const double ul = (J > 0) ? (w[m - 2] + w[m - 1]) * 0.5 : 2.0 * gL - u0;
       const double ur = (J < nc - 1) ? (w[m + 2] + w[m + 3]) * 0.5 : 2.0 * gR - u0;
@@ -899,6 +917,24 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
 // Up pass (Fig. 3 SR branch): full update u = Pi c (Eq. 5), then nu times
 // [Kaczmarz projection onto I^ u = c (Eq. 8, Fig. 5), red-black sweep] on
 // the extended patch; the core streams to u_out.
+// Registers -> coalesced store of the window cells whose global index lies in
+// [lo, hi), cell g to out[g - out_lo].
+template <int K>
+__device__ __forceinline__ void store_run_at(double* st, const double (&v)[K], int64_t wlo,
+                                             int64_t lo, int64_t hi, double* __restrict__ out,
+                                             int64_t out_lo) {
+  const int W = blockDim.x;
+  run_to_stage<K>(st, v);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = threadIdx.x + k * W;
+    const int64_t g = wlo + e;
+    if (g >= lo && g < hi) out[g - out_lo] = st[sidx<K>(e)];
+  }
+  __syncthreads();
+}
+
 template <int K, bool F32>
 __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
   extern __shared__ double sm[];
@@ -906,7 +942,10 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
   double* st = sm;
   Xch x{sm + W * (K + 1), 0, 2 * W};
   const int64_t n = a.n, nc = n >> 1;
-  const int64_t seg = blockIdx.x;
+  const int64_t seg = a.seg0 + blockIdx.x;
+  // cells of this segment's core that are written
+  const int64_t wr_lo = seg * a.s > a.out_lo ? seg * a.s : a.out_lo;
+  const int64_t wr_hi = (seg + 1) * a.s < a.out_hi ? (seg + 1) * a.s : a.out_hi;
   const int64_t core_lo = seg * a.s, core_hi = core_lo + a.s;
   const int64_t wlo = core_lo - a.pad;
   const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
@@ -947,7 +986,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
       smooth_masked<K, F32>(u, f, 1, rb.jlo, rb.jhi, nb_upd, x, x4);
     }
     __syncthreads();  // last exchange read before the stage is reused
-    if (a.out) store_run_fast<K>(st, u, a.out + wlo, (int)a.pad, (int)(a.pad + a.s));
+    if (a.out) store_run_at<K>(st, u, wlo, wr_lo, wr_hi, a.out, a.out_lo);
     if (a.part) {
       const int e0 = (int)threadIdx.x * K;
       segment_sums<K>(u, (int)a.pad - e0, (int)(a.pad + a.s) - e0, st, a.part, blockIdx.x);
@@ -977,7 +1016,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
       rb_half<K, 1>(u, f, rb, h2, gL2, gR2, bdiv, x);
     }
   }
-  if (a.out) store_run<K>(st, u, wlo, core_lo, core_hi < n ? core_hi : n, a.out);
+  if (a.out) store_run_at<K>(st, u, wlo, wr_lo, wr_hi, a.out, a.out_lo);
   if (a.part) {
     const int64_t c0 = core_lo - g0, c1 = (core_hi < n ? core_hi : n) - g0;
     segment_sums<K>(u, (int)(c0 < 0 ? 0 : (c0 > K ? K : c0)), (int)(c1 < 0 ? 0 : (c1 > K ? K : c1)),
@@ -1270,6 +1309,25 @@ __global__ __launch_bounds__(1024) void k_functionals(const double* __restrict__
 // call site per phase) so that each phase issues few instructions.
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// Non-finite check (fmgsr_options.check_finite): a grid-stride scan that sets
+// *flag (cleared beforehand by k_clear_flag, not a memset, so the pair is
+// also safe inside a captured graph) when any of the n values is NaN or Inf.
+// Every thread that finds one writes the same value; no atomics are needed.
+// ---------------------------------------------------------------------------
+__global__ void k_clear_flag(int* flag) {
+  if (threadIdx.x == 0) flag[0] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_nonfinite(const double* __restrict__ x, int64_t n,
+                                                   int* flag) {
+  bool bad = false;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    bad |= !isfinite(x[i]);
+  if (bad) flag[0] = 1;
+}
+
 constexpr int kCoreThreads = 512;
 constexpr int64_t kCoreMaxCells = 2048;
 constexpr int64_t kMaxN0 = 1024;
@@ -1280,6 +1338,7 @@ struct CoreArgs {
   double gL, gR;
   int nu1, nu2;
   int literal;         // literal tau on the levels below C
+  int ravg;            // literal tau: rhs restriction = two-cell average
   int mode;            // 0: FMG on levels 0..C; 1: V-cycle from a level-C guess
   int src_kind;        // mode 1: kSrcRestrict (from level C+1) or kSrcDirect
   const double* F[12]; // forcing of levels 0..C (C <= 11)
@@ -1518,9 +1577,14 @@ __global__ __launch_bounds__(kCoreThreads) void k_coarse_core(CoreArgs a) {
             return qf[k] - (2.0 * uf[k] - (l + r)) * w;
           };
           const double r1 = res(2 * J), r2 = res(2 * J + 1);
-          const double rm = (J > 0) ? res(2 * J - 1) : -r1;
-          const double rp = (2 * J + 2 < nm) ? res(2 * J + 2) : -r2;
-          const double IR = ((rm + rp) + 3.0 * (r1 + r2)) * 0.125;
+          double IR;
+          if (a.ravg) {
+            IR = (r1 + r2) * 0.5;
+          } else {
+            const double rm = (J > 0) ? res(2 * J - 1) : -r1;
+            const double rp = (2 * J + 2 < nm) ? res(2 * J + 2) : -r2;
+            IR = ((rm + rp) + 3.0 * (r1 + r2)) * 0.125;
+          }
           const double ul = (J > 0) ? (uf[2 * J - 2] + uf[2 * J - 1]) * 0.5 : gL2 - u0;
           const double ur = (J < nc - 1) ? (uf[2 * J + 2] + uf[2 * J + 3]) * 0.5 : gR2 - u0;
           qc[J] = IR + (2.0 * u0 - (ul + ur)) * wc;

@@ -13,7 +13,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfmgsr.so")
 
 FMGSR_OK, FMGSR_EINVAL, FMGSR_ENOMEM, FMGSR_EDEVICE, FMGSR_ENOTSUP = 0, -1, -2, -3, -4
+FMGSR_ENONFINITE = -5
 TAU_MODES = {"split": 0, "literal": 1}
+RHS_RESTRICTIONS = {"fw": 0, "avg": 1}
 OPS = {"poisson": 0, "cubic": 1, "linear": 2}
 PRECISIONS = {"fp64": 0, "fp32relax": 1}
 
@@ -26,7 +28,8 @@ class Options(ctypes.Structure):
                 ("sr_levels", ctypes.c_int32), ("tau_mode", ctypes.c_int32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("functionals", ctypes.c_void_p)]
+                ("functionals", ctypes.c_void_p), ("coarse_out", ctypes.c_void_p),
+                ("rhs_restriction", ctypes.c_int32), ("check_finite", ctypes.c_int32)]
 
 
 class Operator(ctypes.Structure):
@@ -77,6 +80,11 @@ def lib():
                                   ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p,
                                   ctypes.c_void_p]
         L.fmgsr_solve.restype = ctypes.c_int
+        L.fmgsr_decompress.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_int64,
+                                       ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+        L.fmgsr_decompress.restype = ctypes.c_int
         L.fmgsr_status_string.argtypes = [ctypes.c_int32]
         L.fmgsr_status_string.restype = ctypes.c_char_p
         L.fmgsr_profile_enable.argtypes = [ctypes.c_char_p]
@@ -106,13 +114,16 @@ def lib():
     return _lib
 
 
-def make_options(nu=(2, 1), sr_levels=1, tau="split", workspace=None, precision="fp64"):
+def make_options(nu=(2, 1), sr_levels=1, tau="split", workspace=None, precision="fp64",
+                 rhs_restrict="fw", check_finite=False):
     o = Options()
     lib().fmgsr_default_options(ctypes.byref(o))
     o.nu1, o.nu2 = int(nu[0]), int(nu[1])
     o.sr_levels = int(sr_levels)
     o.tau_mode = TAU_MODES[tau]
     o.precision = PRECISIONS[precision]
+    o.rhs_restriction = RHS_RESTRICTIONS[rhs_restrict]
+    o.check_finite = int(bool(check_finite))
     if workspace is not None:
         o.workspace = workspace.data_ptr()
         o.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -120,12 +131,14 @@ def make_options(nu=(2, 1), sr_levels=1, tau="split", workspace=None, precision=
 
 
 def workspace_bytes(n, levels, nu=(2, 1), sr_levels=1, tau="split", segments=None, buffer=None,
-                    functionals=False):
+                    functionals=False, coarse_out=False, rhs_restrict="fw"):
     """Workspace bytes for any segments, or (segments and buffer given) for
     exactly these segments and buffer."""
-    o = make_options(nu, sr_levels, tau)
+    o = make_options(nu, sr_levels, tau, rhs_restrict=rhs_restrict)
     if functionals:
         o.functionals = ctypes.c_void_p(1)  # only its presence matters for the size
+    if coarse_out:
+        o.coarse_out = ctypes.c_void_p(1)
     if segments is None:
         return int(lib().fmgsr_workspace_bytes(int(n), int(levels), ctypes.byref(o)))
     return int(lib().fmgsr_workspace_bytes_for(int(n), int(levels), int(segments), int(buffer),
@@ -170,15 +183,28 @@ def _check_workspace(ws, device):
 
 def solve(f, g=(0.0, 0.0), levels=None, segments=1, buffer=0, nu=(2, 1), sr_levels=1,
           tau="split", out=None, workspace=None, stream=None, op="poisson", kappa=None,
-          precision="fp64", functionals=None, write_u=True):
+          precision="fp64", functionals=None, write_u=True, coarse_out=None, rhs_restrict="fw",
+          check_finite=False):
     """One FMG-FAS-SR iteration for -u'' (+ reaction) = f on [0,1] (see
     include/fmgsr.h).
 
-    f: contiguous float64 tensor on the GPU.  Returns u (same shape).  The
-    call is asynchronous on ``stream`` (default: torch's current stream);
-    the reaction operators (``op`` = "cubic" or "linear" with ``kappa``) run
-    synchronously as a batch of one.
+    f: contiguous float64 tensor on the GPU.  Returns u (same shape), or None
+    with ``write_u=False``.  The call is asynchronous on ``stream`` (default:
+    torch's current stream); the reaction operators (``op`` = "cubic" or
+    "linear" with ``kappa``) run synchronously as a batch of one.
+    coarse_out: float64 tensor of n/2 cells that receives the level-(M-1)
+    solution (the PDE-compressed form ``decompress`` expands).
+    rhs_restrict: "fw" (full weighting) or "avg" (two-cell average, literal
+    tau only).  check_finite: refuse a non-finite f or result with
+    FMGSR_ENONFINITE (synchronises the stream).
     """
+    return _solve("fmgsr_solve", f, g, levels, segments, buffer, nu, sr_levels, tau, out,
+                  workspace, stream, op, kappa, precision, functionals, write_u, coarse_out,
+                  rhs_restrict, check_finite)
+
+
+def _solve(entry, f, g, levels, segments, buffer, nu, sr_levels, tau, out, workspace, stream, op,
+           kappa, precision, functionals, write_u, coarse_out, rhs_restrict, check_finite):
     _check_vec(f, "f")
     n = f.numel()
     if op not in OPS:
@@ -190,8 +216,8 @@ def solve(f, g=(0.0, 0.0), levels=None, segments=1, buffer=0, nu=(2, 1), sr_leve
     if levels is None:
         levels = n.bit_length()  # n a power of two -> N0 = 1
     if not write_u:
-        if functionals is None:
-            raise ValueError("write_u=False needs a functionals tensor")
+        if functionals is None and coarse_out is None:
+            raise ValueError("write_u=False needs a functionals or a coarse_out tensor")
         out = None
     elif out is None:
         out = torch.empty_like(f)
@@ -199,20 +225,53 @@ def solve(f, g=(0.0, 0.0), levels=None, segments=1, buffer=0, nu=(2, 1), sr_leve
         _check_vec(out, "out", numel=n, device=f.device)
     if functionals is not None:
         _check_vec(functionals, "functionals", at_least=2, device=f.device)
+    if coarse_out is not None:
+        _check_vec(coarse_out, "coarse_out", numel=n // 2, device=f.device)
     if workspace is not None:
         _check_workspace(workspace, f.device)
     if stream is None:
         stream = torch.cuda.current_stream(f.device)
-    o = make_options(nu, sr_levels, tau, workspace, precision)
+    o = make_options(nu, sr_levels, tau, workspace, precision, rhs_restrict, check_finite)
     if functionals is not None:
         o.functionals = functionals.data_ptr()
+    if coarse_out is not None:
+        o.coarse_out = coarse_out.data_ptr()
     op = Operator(OPS[op], kappa.data_ptr() if kappa is not None else None)
-    st = lib().fmgsr_solve(ctypes.byref(op), f.data_ptr(), float(g[0]), float(g[1]), n,
-                           int(levels), int(segments), int(buffer), ctypes.byref(o),
-                           out.data_ptr() if out is not None else None,
-                           ctypes.c_void_p(stream.cuda_stream))
+    st = getattr(lib(), entry)(ctypes.byref(op), f.data_ptr(), float(g[0]), float(g[1]), n,
+                               int(levels), int(segments), int(buffer), ctypes.byref(o),
+                               out.data_ptr() if out is not None else None,
+                               ctypes.c_void_p(stream.cuda_stream))
     if st != FMGSR_OK:
-        raise FmgsrError(st, "fmgsr_solve")
+        raise FmgsrError(st, entry)
+    return out
+
+
+def decompress(coarse, f, lo=0, hi=None, g=(0.0, 0.0), segments=1, buffer=0, nu=(2, 1),
+               precision="fp64", out=None, stream=None):
+    """Finest-level solution on cells [lo, hi) expanded from the level-(M-1)
+    solution ``coarse`` (``solve(..., coarse_out=...)``) and f by the SR up
+    pass of the covering segments (fmgsr_decompress).  Returns a tensor of
+    hi - lo cells; asynchronous on ``stream``."""
+    _check_vec(f, "f")
+    n = f.numel()
+    _check_vec(coarse, "coarse", numel=n // 2, device=f.device)
+    hi = n if hi is None else int(hi)
+    lo = int(lo)
+    if not 0 <= lo <= hi <= n:
+        raise ValueError(f"range [{lo}, {hi}) is not inside [0, {n}]")
+    if out is None:
+        out = torch.empty(hi - lo, dtype=torch.float64, device=f.device)
+    else:
+        _check_vec(out, "out", numel=hi - lo, device=f.device)
+    if hi == lo:
+        return out
+    o = make_options(nu, 1, "split", None, precision)
+    s = (stream or torch.cuda.current_stream(f.device)).cuda_stream
+    st = lib().fmgsr_decompress(coarse.data_ptr(), f.data_ptr(), float(g[0]), float(g[1]), n,
+                                int(segments), int(buffer), ctypes.byref(o), lo, hi,
+                                out.data_ptr(), ctypes.c_void_p(s))
+    if st != FMGSR_OK:
+        raise FmgsrError(st, "fmgsr_decompress")
     return out
 
 

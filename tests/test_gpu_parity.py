@@ -18,6 +18,7 @@ torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
 from paper_1207_6720_amd import fmgsr, workloads as W  # noqa: E402
+from tests.parity_bars import literal_noise_bar  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -194,6 +195,35 @@ def test_several_sr_levels_rejections(dev):
         fmgsr.solve(f, levels=11, segments=4, buffer=4, sr_levels=2, tau="literal")
     with pytest.raises(fmgsr.FmgsrError):      # as many SR levels as grids
         fmgsr.solve(f, levels=11, segments=1, buffer=4, sr_levels=11)
+
+
+LITERAL_MULTICELL = [
+    # n, levels, segments, buffer, sr_levels, g
+    (5 << 12, 13, 5, 8, 1, (0.0, 0.0)),
+    (3 << 12, 13, 3, 4, 1, (0.5, -0.25)),
+    (5 << 10, 11, 1, 0, 0, (0.0, 0.0)),
+]
+
+
+@pytest.mark.parametrize("case", LITERAL_MULTICELL, ids=lambda c: f"n{c[0]}_L{c[1]}_sr{c[4]}")
+def test_literal_tau_multicell_coarsest(dev, case):
+    """Literal tau with a multi-cell coarsest grid: the two sides' coarsest
+    solvers round differently and literal tau turns that into noise of its
+    own size, so the bar is that noise as the oracle itself responds to a
+    rounding-level perturbation of f (tests/parity_bars.py), per cell and in
+    norm."""
+    n, levels, S, b, sr, g = case
+    print(f"literal multicell n={n} levels={levels} S={S} b={b} sr={sr}", flush=True)
+    f_host = rhs(n, 40)
+    kw = dict(g=g, levels=levels, segments=S, buffer=b, sr_levels=sr, tau="literal")
+    u = gpu_solve(dev, f_host, **kw)
+    ref = oracle_solve(f_host, **kw)
+    bar_norm, bar_cell = literal_noise_bar(f_host, levels, S, b, nsr=sr, g=g)
+    assert bar_norm < 1e-8 and bar_cell < 1e-8
+    assert np.all(np.isfinite(u))
+    assert np.linalg.norm(u - ref) <= bar_norm * np.linalg.norm(ref)
+    assert np.abs(u - ref).max() <= bar_cell * np.abs(ref).max()
+    print(f"  rel {np.linalg.norm(u - ref) / np.linalg.norm(ref):.2e} (bar {bar_norm:.2e})")
 
 
 def test_repeatable_and_workspace_reuse(dev):

@@ -178,13 +178,14 @@ def test_binding_rejects_host_and_float32_arrays():
 
 
 def test_launch_lds_fits_the_grant_for_every_geometry():
-    """Every kernel with dynamic LDS is granted 160 KiB (MI355X: 160 KiB per
-    workgroup); a solve checks its largest request against the grant and the
-    device limit before enqueuing.  The coarse core's request is its level
-    stack: iterates and right-hand sides of levels 0..C, the correction
-    buffer of level C-1 and 8 N0 doubles of cyclic reduction; the segment
-    kernels take 13 doubles per thread."""
-    grant = 160 * 1024
+    """Every kernel with dynamic LDS is granted the device's per-workgroup
+    LDS (MI355X: 160 KiB) less its own static LDS (a few hundred bytes at
+    most); a solve checks each request against its kernel's grant before
+    enqueuing.  The coarse core's request is its level stack: iterates and
+    right-hand sides of levels 0..C, the correction buffer of level C-1 and
+    8 N0 doubles of cyclic reduction; the segment kernels take 13 doubles
+    per thread."""
+    grant = 160 * 1024 - 1024
     # N0 = 1: core levels up to 2048 cells (C = 11)
     ntot, esz = 4095, 1024
     assert F.launch_lds_bytes(1 << 28, 29, 1 << 16, 8) == (2 * ntot + esz + 8) * 8
@@ -206,3 +207,34 @@ def test_launch_lds_fits_the_grant_for_every_geometry():
                 worst = max(worst, F.launch_lds_bytes(n, extra + 1, segs, buf, sr_levels=sr))
     assert 0 < worst <= grant
     assert F.launch_lds_bytes(1000, 11, 4, 4) == 0      # invalid sizes
+
+
+def test_option_validation_on_host():
+    """check_finite takes 0 or 1, the rhs restriction FULLWEIGHT or AVERAGE,
+    and the average restriction needs literal tau (split tau rests on
+    L_H I^ = I L_h, which only full weighting satisfies): an invalid
+    combination has no workspace size and is refused before anything runs."""
+    n, L = 1 << 12, 13
+    assert F.lib().fmgsr_status_string(F.FMGSR_ENONFINITE).decode().startswith("FMGSR_ENONFINITE")
+    o = F.make_options(check_finite=True)
+    assert F.lib().fmgsr_workspace_bytes(n, L, ctypes.byref(o)) > 0
+    o.check_finite = 2
+    assert F.lib().fmgsr_workspace_bytes(n, L, ctypes.byref(o)) == 0
+    assert F.workspace_bytes(n, L, tau="literal", rhs_restrict="avg") > 0
+    assert F.workspace_bytes(n, L, tau="split", rhs_restrict="avg") == 0
+    o = F.make_options()
+    o.rhs_restriction = 2
+    assert F.lib().fmgsr_workspace_bytes(n, L, ctypes.byref(o)) == 0
+    # the kept coarse solution needs exactly one SR level
+    assert F.workspace_bytes(n, L, coarse_out=True) > 0
+    assert F.workspace_bytes(n, L, sr_levels=2, coarse_out=True) == 0
+    assert F.workspace_bytes(n, L, sr_levels=0, coarse_out=True) == 0
+    # the batched engine supports none of these options
+    import numpy as np
+    sizes, levels = np.array([4096], dtype=np.int64), np.array([13], dtype=np.int32)
+    for kw in ({"check_finite": True}, {"tau": "literal", "rhs_restrict": "avg"}):
+        o = F.make_options(**kw)
+        h = ctypes.c_void_p()
+        st = F.lib().fmgsr_batch_create(1, sizes.ctypes.data, None, levels.ctypes.data, None, 8,
+                                        None, 1, ctypes.byref(o), ctypes.byref(h))
+        assert st == F.FMGSR_ENOTSUP and not h.value

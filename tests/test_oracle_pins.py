@@ -411,6 +411,30 @@ def test_literal_tau_agrees_with_split_on_small_grids(n):
     assert rel(a, b) < tol and rel(b, c) < tol
 
 
+@pytest.mark.parametrize("n,levels,S", [(5120, 11, 5), (1 << 14, 15, 16)])
+def test_literal_tau_results_carry_rounding_noise(n, levels, S):
+    """Eq. 7 evaluated as written forms I(L_h u) and L_H(I^ u), two
+    O(n^2 |u|) terms that cancel exactly: its value is rounding noise whose
+    bits depend on every bit of the iterate.  A perturbation of f at the
+    rounding level (4e-16 relative, far below anything the method resolves)
+    therefore moves the literal-tau result by about eps n^2-scaled noise
+    (measured 1e-12 .. 1e-10 here), while split tau moves by ~eps.  Two
+    correct implementations that round differently anywhere -- two exact
+    coarsest solvers, say -- differ by that much; the GPU parity bar for
+    literal tau with a multi-cell coarsest grid is derived from this
+    response (tests/test_gpu_parity.py, literal_bar)."""
+    rng = np.random.default_rng(3)
+    f = _problem(n, 5)[2]
+    f2 = f * (1.0 + 4e-16 * rng.standard_normal(n))
+    kw = dict(levels=levels, segments=S, buffer=8, nsr=1)
+    split = rel(oracle.fmgsr_solve(f, tau="split", **kw), oracle.fmgsr_solve(f2, tau="split", **kw))
+    for rr in ("fw", "avg"):
+        lit = rel(oracle.fmgsr_solve(f, tau="literal", rhs_restrict=rr, **kw),
+                  oracle.fmgsr_solve(f2, tau="literal", rhs_restrict=rr, **kw))
+        assert 1e-13 < lit < 1e-8, (rr, lit)
+    assert split < 1e-14
+
+
 def test_per_patch_tau_equals_assembled_when_buffer_is_wide():
     """Per-patch literal tau reads 2 cells past the core; with b >= 2 nu1 + 1
     it coincides bitwise with the assembled tau."""
