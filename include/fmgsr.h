@@ -210,6 +210,34 @@ fmgsr_status fmgsr_solve(const fmgsr_operator *op, const double *f, double g_lef
                          int32_t buffer, const fmgsr_options *opt, double *u_out,
                          void *hip_stream);
 
+/* Bytes of the static device scratch behind fmgsr_solve_noalloc (128 MiB on
+ * every GPU the library runs on, held until the process ends): enough for
+ * the workspace of n <= 2^22 with the default options. */
+#define FMGSR_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/*
+ * fmgsr_solve_noalloc -- fmgsr_solve for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It calls no hipMalloc, hipFree or other
+ * allocating routine: its workspace is a static device array of
+ * FMGSR_NOALLOC_SCRATCH_BYTES bytes, one per GPU, shared by every call on
+ * that GPU.
+ *
+ * Arguments and results as fmgsr_solve, for the Poisson operator (op NULL or
+ * FMGSR_OP_POISSON; the reaction kinds return FMGSR_ENOTSUP because their
+ * batched plan allocates).  opt->workspace must be NULL and
+ * opt->workspace_bytes 0 (else FMGSR_EINVAL).  Returns FMGSR_ENOMEM, before
+ * enqueuing anything, when the solve's workspace
+ * (fmgsr_workspace_bytes_for) exceeds FMGSR_NOALLOC_SCRATCH_BYTES.
+ * Calls that overlap on one GPU (concurrent streams or host threads) race on
+ * the shared scratch: serialise them.  The scratch keeps the last call's
+ * contents; the solve writes every workspace cell before reading it.
+ */
+fmgsr_status fmgsr_solve_noalloc(const fmgsr_operator *op, const double *f, double g_left,
+                                 double g_right, int64_t n, int32_t levels, int64_t n_segments,
+                                 int32_t buffer, const fmgsr_options *opt, double *u_out,
+                                 void *hip_stream);
+
 /*
  * fmgsr_decompress -- PDE decompression (Sec. 3.2, method 2): the finest-level
  * solution on cells [lo, hi), expanded from the stored level-(M-1) solution

@@ -940,9 +940,9 @@ fmgsr_status scan_finite(const std::vector<std::pair<const double*, int64_t>>& a
   return h ? FMGSR_ENONFINITE : FMGSR_OK;
 }
 
-// fmgsr_solve for the Poisson operator.  static_ws: a workspace the library
-// owns (static_bytes bytes), used instead of the caller's workspace or a
-// stream-ordered allocation.
+// fmgsr_solve for the Poisson operator.  static_ws: the library's static
+// scratch (static_bytes bytes, fmgsr_solve_noalloc), used instead of the
+// caller's workspace or a stream-ordered allocation.
 fmgsr_status solve_poisson(const double* f, double g_left, double g_right, int64_t n,
                            int32_t levels, int64_t n_segments, int32_t buffer,
                            const fmgsr_options& o, double* u_out, void* hip_stream,
@@ -1021,6 +1021,36 @@ fmgsr_status solve_poisson(const double* f, double g_left, double g_right, int64
   return c.err;
 }
 
+// ---------------------------------------------------------------------------
+// Static scratch of fmgsr_solve_noalloc: one array per device (each GPU the
+// library runs on holds it until the process ends).  In host code the
+// symbol's name is only a stand-in; its device address is looked up once per
+// device with that device current and kept.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) unsigned char scratch[FMGSR_NOALLOC_SCRATCH_BYTES];
+
+fmgsr_status scratch_address(char** out) {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static char* addr[kMaxDev] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) {
+    (void)hipGetLastError();
+    return FMGSR_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) {
+      (void)hipGetLastError();
+      return FMGSR_EDEVICE;
+    }
+    addr[dev] = (char*)ptr;
+  }
+  *out = addr[dev];
+  return FMGSR_OK;
+}
+
 }  // namespace
 }  // namespace fmgsr
 
@@ -1045,6 +1075,24 @@ fmgsr_status fmgsr_solve(const fmgsr_operator* op, const double* f, double g_lef
   else fmgsr_default_options(&o);
   return solve_poisson(f, g_left, g_right, n, levels, n_segments, buffer, o, u_out, hip_stream,
                        nullptr, 0);
+}
+
+fmgsr_status fmgsr_solve_noalloc(const fmgsr_operator* op, const double* f, double g_left,
+                                 double g_right, int64_t n, int32_t levels, int64_t n_segments,
+                                 int32_t buffer, const fmgsr_options* opt, double* u_out,
+                                 void* hip_stream) {
+  if (op && (op->kind < FMGSR_OP_POISSON || op->kind > FMGSR_OP_LINEAR_REACTION)) return FMGSR_EINVAL;
+  // the reaction operators run through the batched engine, whose plan allocates
+  if (op && op->kind != FMGSR_OP_POISSON) return FMGSR_ENOTSUP;
+  if (op && op->kappa != nullptr) return FMGSR_EINVAL;
+  fmgsr_options o;
+  if (opt) o = *opt;
+  else fmgsr_default_options(&o);
+  if (o.workspace != nullptr || o.workspace_bytes != 0) return FMGSR_EINVAL;
+  char* ws = nullptr;
+  if (const fmgsr_status st = scratch_address(&ws); st != FMGSR_OK) return st;
+  return solve_poisson(f, g_left, g_right, n, levels, n_segments, buffer, o, u_out, hip_stream,
+                       ws, FMGSR_NOALLOC_SCRATCH_BYTES);
 }
 
 fmgsr_status fmgsr_decompress(const double* coarse, const double* f, double g_left,

@@ -80,6 +80,8 @@ def lib():
                                   ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p,
                                   ctypes.c_void_p]
         L.fmgsr_solve.restype = ctypes.c_int
+        L.fmgsr_solve_noalloc.argtypes = L.fmgsr_solve.argtypes
+        L.fmgsr_solve_noalloc.restype = ctypes.c_int
         L.fmgsr_decompress.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
                                        ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_int64,
@@ -200,6 +202,18 @@ def solve(f, g=(0.0, 0.0), levels=None, segments=1, buffer=0, nu=(2, 1), sr_leve
     """
     return _solve("fmgsr_solve", f, g, levels, segments, buffer, nu, sr_levels, tau, out,
                   workspace, stream, op, kappa, precision, functionals, write_u, coarse_out,
+                  rhs_restrict, check_finite)
+
+
+def solve_noalloc(f, g=(0.0, 0.0), levels=None, segments=1, buffer=0, nu=(2, 1), sr_levels=1,
+                  tau="split", out=None, stream=None, precision="fp64", functionals=None,
+                  write_u=True, rhs_restrict="fw", check_finite=False):
+    """``solve`` through ``fmgsr_solve_noalloc``: the library's static device
+    scratch serves as workspace, so the call allocates nothing on the device
+    (``out`` must then be given by callers that cannot allocate either).
+    Poisson operator only; calls that overlap on one GPU race."""
+    return _solve("fmgsr_solve_noalloc", f, g, levels, segments, buffer, nu, sr_levels, tau, out,
+                  None, stream, "poisson", None, precision, functionals, write_u, None,
                   rhs_restrict, check_finite)
 
 
