@@ -21,9 +21,11 @@
 // first down and the last up kernel.  The top up kernel of a step rebuilds
 // the pre-smoothed iterates the down kernel made on its levels above the
 // bottom one (Pi of V^{t-1} and the same sweeps in the same window), so
-// those are not stored ("deep pairs").  Launches of many tiles run their
-// interior tiles at three workgroups per CU (k_down's register-capped
-// variant; k_up_wide, with the edge tiles in a second launch of k_up).
+// those are not stored ("deep pairs").  The vertical kernels run
+// one-wavefront tiles whose exchanges are lane shifts.  Launches of many
+// tiles run their interior tiles at three wavefronts per SIMD (k_down's
+// register-capped variant; k_up_wide, with the edge tiles in a second launch
+// of k_up).
 // With sr_levels = k >= 2 the levels M-k+1 .. M-1 are SR levels too (the
 // semantics of Sec. 4's runs with two and three SR levels): wherever they
 // are visited, their pre-smoothing is the block smoother (segment kernels
@@ -155,13 +157,17 @@ bool sr_up_fits(int nu, int d, int64_t halo) {
   return halo >= inv;
 }
 
-// Down launches of at least this many tiles take the three-workgroup kernel
-// (a full chip of them and more); smaller ones are bound by one workgroup's
-// latency, which its spills would lengthen.
-constexpr int64_t kDownWideTiles = 768;
-// Deep up launches of at least this many tiles run their interior tiles on
-// the three-workgroup kernel (one more launch for the edge tiles).
-constexpr int64_t kUpWideTiles = 768;
+// Vertical kernels run one-wavefront tiles (64 threads x kRun cells, less
+// the halo): their neighbour exchanges are lane shifts, with no LDS round
+// trip and no workgroup barrier, and each wavefront walks its tile at its
+// own pace.
+constexpr int kVertThreads = 64;
+// Top levels of at least this many cells (768 tiles of the 256-thread shape)
+// take the three-wavefronts-per-SIMD down kernel, and deep up launches run
+// their interior tiles on k_up_wide (one more launch for the edge tiles);
+// smaller launches are bound by one tile's latency, which the down kernel's
+// spills would lengthen.
+constexpr int64_t kWideCells = 768 * ((int64_t)kRun * 256 - 2 * kTileHalo);
 
 // Up kernel that rebuilds its top level's pre-smoothed iterate (Pi of the
 // level below's FMG iterate, then the down leg's nu1 sweeps) instead of
@@ -292,7 +298,7 @@ fmgsr_status make_plan(int64_t n, int32_t levels, const fmgsr_options& o, Plan* 
   p->off_Q = off; off = align_up(off + (p->literal ? hier : 0));
   p->off_Utop = off; off = align_up(off + (p->nsr == 0 && M >= 1 ? (size_t)n * sizeof(double) : 0));
   // per-tile functional partials of the SR-topped up kernel (2 per tile)
-  const int64_t tile_core = (int64_t)kRun * kTileThreads - 2 * kTileHalo;
+  const int64_t tile_core = (int64_t)kRun * kVertThreads - 2 * kTileHalo;
   p->off_P = off;
   off = align_up(off + (p->nsr >= 1 ? (size_t)(2 * ((n + tile_core - 1) / tile_core) + 2) * sizeof(double) : 0));
   // Uh last: plan_bytes() leaves it out when the segments never use it
@@ -479,9 +485,11 @@ struct Ctx {
     if (hipGetLastError() != hipSuccess) err = FMGSR_EDEVICE;
   }
 
-  static int64_t tile_core() { return (int64_t)kRun * kTileThreads - 2 * kTileHalo; }
+  // Core cells of a tile of T threads (kRun cells each, less the halo on
+  // both sides).
+  static int64_t tile_core(int T) { return (int64_t)kRun * T - 2 * kTileHalo; }
 
-  VertArgs vargs(int top, int levels, int nu) const {
+  VertArgs vargs(int top, int levels, int nu, int T = kVertThreads) const {
     VertArgs a;
     std::memset(&a, 0, sizeof(a));
     a.n = nl(top);
@@ -489,7 +497,7 @@ struct Ctx {
     a.gR = gR;
     a.nu = nu;
     a.levels = levels;
-    a.core = tile_core();
+    a.core = tile_core(T);
     a.halo = kTileHalo;
     return a;
   }
@@ -513,13 +521,14 @@ struct Ctx {
     const double nb = (double)a.n * 8.0;
     bytes += nb + (src_kind == kSrcInterp ? nb * 0.5 : src_kind == kSrcRestrict ? nb * 2.0 : nb);
     const int64_t blocks = (a.n + a.core - 1) / a.core;
+    const bool wide = a.n >= kWideCells;
     ProfScope ps("k_down", bytes, st);
-    const dim3 g((unsigned)blocks), b(kTileThreads);
-    const bool wide = blocks >= kDownWideTiles;
-    if (p->f32 && wide) hipLaunchKernelGGL((k_down<kRun, true, 3>), g, b, 0, st, a);
-    else if (p->f32) hipLaunchKernelGGL((k_down<kRun, true, 2>), g, b, 0, st, a);
-    else if (wide) hipLaunchKernelGGL((k_down<kRun, false, 3>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((k_down<kRun, false, 2>), g, b, 0, st, a);
+    constexpr int T = kVertThreads;
+    const dim3 g((unsigned)blocks), b(T);
+    if (p->f32 && wide) hipLaunchKernelGGL((k_down<kRun, true, 3, T>), g, b, 0, st, a);
+    else if (p->f32) hipLaunchKernelGGL((k_down<kRun, true, 2, T>), g, b, 0, st, a);
+    else if (wide) hipLaunchKernelGGL((k_down<kRun, false, 3, T>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_down<kRun, false, 2, T>), g, b, 0, st, a);
     check();
   }
 
@@ -553,34 +562,41 @@ struct Ctx {
     const int64_t blocks = (a.n + a.core - 1) / a.core;
     ProfScope ps("k_up", bytes, st);
     int64_t b_lo = 0, b_hi = -1;
-    if (deep && blocks >= kUpWideTiles) interior_tiles(a, &b_lo, &b_hi);
+    if (deep && a.n >= kWideCells) interior_tiles(a, kVertThreads, &b_lo, &b_hi);
+    up_kernels<kVertThreads>(a, blocks, b_lo, b_hi);
+    check();
+  }
+
+  // The up launch of tile shape T: interior tiles [b_lo, b_hi] on the
+  // three-wavefronts-per-SIMD kernel and the edge tiles on k_up, or every
+  // tile on k_up when b_hi < b_lo.
+  template <int T>
+  void up_kernels(const VertArgs& a, int64_t blocks, int64_t b_lo, int64_t b_hi) {
     if (b_hi >= b_lo) {
-      // interior tiles on the three-workgroup kernel, the edge tiles on k_up
       VertArgs w = a;
       w.tile0 = b_lo;
       VertArgs e = a;
       e.gap_at = b_lo;
       e.gap = b_hi - b_lo + 1;
-      const dim3 gw((unsigned)(b_hi - b_lo + 1)), ge((unsigned)(blocks - e.gap)), tb(kTileThreads);
+      const dim3 gw((unsigned)(b_hi - b_lo + 1)), ge((unsigned)(blocks - e.gap)), tb(T);
       if (p->f32) {
-        hipLaunchKernelGGL((k_up_wide<kRun, true>), gw, tb, 0, st, w);
-        hipLaunchKernelGGL((k_up<kRun, true>), ge, tb, 0, st, e);
+        hipLaunchKernelGGL((k_up_wide<kRun, true, T>), gw, tb, 0, st, w);
+        hipLaunchKernelGGL((k_up<kRun, true, T>), ge, tb, 0, st, e);
       } else {
-        hipLaunchKernelGGL((k_up_wide<kRun, false>), gw, tb, 0, st, w);
-        hipLaunchKernelGGL((k_up<kRun, false>), ge, tb, 0, st, e);
+        hipLaunchKernelGGL((k_up_wide<kRun, false, T>), gw, tb, 0, st, w);
+        hipLaunchKernelGGL((k_up<kRun, false, T>), ge, tb, 0, st, e);
       }
     } else if (p->f32) {
-      hipLaunchKernelGGL((k_up<kRun, true>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+      hipLaunchKernelGGL((k_up<kRun, true, T>), dim3((unsigned)blocks), dim3(T), 0, st, a);
     } else {
-      hipLaunchKernelGGL((k_up<kRun, false>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+      hipLaunchKernelGGL((k_up<kRun, false, T>), dim3((unsigned)blocks), dim3(T), 0, st, a);
     }
-    check();
   }
 
   // The tiles whose window lies inside the level (window_interior on the
   // device), [b_lo, b_hi]; empty when b_hi < b_lo.
-  static void interior_tiles(const VertArgs& a, int64_t* b_lo, int64_t* b_hi) {
-    const int64_t wc = (int64_t)kTileThreads * kRun;
+  static void interior_tiles(const VertArgs& a, int T, int64_t* b_lo, int64_t* b_hi) {
+    const int64_t wc = (int64_t)T * kRun;
     auto inside = [&](int64_t b) {
       const int64_t wlo = b * a.core - a.halo;
       return b >= 0 && wlo >= kInteriorMargin && wlo + wc + kInteriorMargin <= a.n;
@@ -597,9 +613,11 @@ struct Ctx {
     *b_hi = hi;
   }
 
-  // Forcing of levels src_level-1 .. src_level-levels from level src_level.
+  // Forcing of levels src_level-1 .. src_level-levels from level src_level
+  // (256-thread tiles: a plain restriction chain has no exchange-bound
+  // phases, and its larger windows re-read fewer halo cells).
   void forcing_launch(int src_level, int levels) {
-    VertArgs a = vargs(src_level, levels, 0);
+    VertArgs a = vargs(src_level, levels, 0, kTileThreads);
     a.rhs = forcing(src_level);
     a.ravg = p->ravg;
     double bytes = (double)a.n * 8.0;
@@ -609,7 +627,8 @@ struct Ctx {
     }
     const int64_t blocks = (a.n + a.core - 1) / a.core;
     ProfScope ps("k_forcing", bytes, st);
-    hipLaunchKernelGGL(k_forcing<kRun>, dim3((unsigned)blocks), dim3(kTileThreads), 0, st, a);
+    hipLaunchKernelGGL((k_forcing<kRun, kTileThreads>), dim3((unsigned)blocks), dim3(kTileThreads), 0,
+                       st, a);
     check();
   }
 
@@ -777,7 +796,7 @@ struct Ctx {
       // with FP32 relaxation only where the interior tiles take k_up_wide:
       // the general up kernel then runs one wavefront per SIMD and has no
       // latency left to hide the extra sweeps in
-      const bool deep_ok = !P.f32 || (nl(t) + tile_core() - 1) / tile_core() >= kUpWideTiles;
+      const bool deep_ok = !P.f32 || nl(t) >= kWideCells;
       const bool deep_sr = fused_down && P.fuse_up && deep_ok && dsr_n == std::min(P.d_down, M - C) &&
                            deep_fits(P.nu1, P.nu2, dsr_n, kTileHalo, true);
       // the top up kernel rebuilds level t's pre-smoothed iterate, and with
@@ -842,7 +861,7 @@ struct Ctx {
         up_launch(M, dsr, f, lv(V, M - dsr), nullptr, u_out, deep_sr ? lv(V, M - 1) : nullptr,
                   true, deep_sr);
         if (functionals) {
-          const int64_t tiles = (p->n + tile_core() - 1) / tile_core();
+          const int64_t tiles = (p->n + tile_core(kVertThreads) - 1) / tile_core(kVertThreads);
           ProfScope ps("k_functionals", (double)tiles * 16.0 + 16.0, st);
           hipLaunchKernelGGL(k_functionals, dim3(1), dim3(1024), 0, st, this->P, tiles,
                              1.0 / (double)p->n, functionals);

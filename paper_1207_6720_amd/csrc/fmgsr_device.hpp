@@ -76,17 +76,45 @@ __device__ __forceinline__ double relax(double fj, double l, double r, int64_t g
   return (n == 1) ? num / 4.0 : num / 3.0;
 }
 
+// Whole-wavefront shift by one lane (DPP wave_shr:1 / wave_shl:1, GFX9):
+// from_left: lane i takes lane i-1's value, else lane i+1's; the lane without
+// a source gets 0.
+__device__ __forceinline__ double wave_shift(double v, bool from_left) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  int rlo, rhi;
+  if (from_left) {
+    rlo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xF, 0xF, false);
+    rhi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xF, 0xF, false);
+  } else {
+    rlo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xF, 0xF, false);
+    rhi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xF, 0xF, false);
+  }
+  return __hiloint2double(rhi, rlo);
+}
+
 // ---------------------------------------------------------------------------
-// Neighbour exchange through LDS: each thread publishes a few values of its
-// run (its first and last, or four for the one-exchange sweeps and the FMG
-// interpolation) and reads its neighbours'.  Two halves of the buffer are
-// used alternately, so one barrier per exchange suffices.
+// Neighbour exchange: each thread publishes a few values of its run (its
+// first and last, or four for the one-exchange sweeps and the FMG
+// interpolation) and reads its neighbours'.
+// Workgroups of several wavefronts go through LDS: two halves of the buffer
+// are used alternately, so one barrier per exchange suffices.  A workgroup
+// of one wavefront (`wave`) shifts the values across lanes in registers
+// (DPP) instead: no LDS and no barrier; the wave barrier only keeps the
+// compiler from moving the workgroup's LDS accesses across the exchange,
+// which the multi-wavefront barrier also orders.
 // ---------------------------------------------------------------------------
 struct Xch {
-  double* buf;  // two halves of `half` doubles
+  double* buf;  // two halves of `half` doubles (unused in wave mode)
   int sel;
   int half;     // >= 2 W for two-value exchanges, >= 4 W for four-value ones
+  bool wave = false;
   __device__ void swap(double first, double last, double& left_last, double& right_first) {
+    if (wave) {
+      __builtin_amdgcn_wave_barrier();
+      left_last = wave_shift(last, true);
+      right_first = wave_shift(first, false);
+      return;
+    }
     const int W = blockDim.x, t = threadIdx.x;
     double* b = buf + (sel ? half : 0);
     sel ^= 1;
@@ -98,6 +126,10 @@ struct Xch {
   }
   // one value only: the left neighbour's `mine` (0 for the first thread)
   __device__ double from_left(double mine) {
+    if (wave) {
+      __builtin_amdgcn_wave_barrier();
+      return wave_shift(mine, true);
+    }
     const int t = threadIdx.x;
     double* b = buf + (sel ? half : 0);
     sel ^= 1;
@@ -107,6 +139,10 @@ struct Xch {
   }
   // the right neighbour's `mine` (0 for the last thread)
   __device__ double from_right(double mine) {
+    if (wave) {
+      __builtin_amdgcn_wave_barrier();
+      return wave_shift(mine, false);
+    }
     const int W = blockDim.x, t = threadIdx.x;
     double* b = buf + (sel ? half : 0);
     sel ^= 1;
@@ -121,6 +157,14 @@ struct Xch {
   // the workgroup edges).
   __device__ void swap(double first, double second, double last, double extra, double& l_last,
                        double& r_first, double& r_second, double& r_extra) {
+    if (wave) {
+      __builtin_amdgcn_wave_barrier();
+      l_last = wave_shift(last, true);
+      r_first = wave_shift(first, false);
+      r_second = wave_shift(second, false);
+      r_extra = wave_shift(extra, false);
+      return;
+    }
     const int W = blockDim.x, t = threadIdx.x;
     double* b = buf + (sel ? half : 0);
     sel ^= 1;
@@ -139,6 +183,14 @@ struct Xch {
   // and the right neighbour's first two (r0 = its first)
   __device__ void swap2(double c0, double c1, double cl1, double cl, double& l2, double& l1,
                         double& r0, double& r1) {
+    if (wave) {
+      __builtin_amdgcn_wave_barrier();
+      l2 = wave_shift(cl1, true);
+      l1 = wave_shift(cl, true);
+      r0 = wave_shift(c0, false);
+      r1 = wave_shift(c1, false);
+      return;
+    }
     const int W = blockDim.x, t = threadIdx.x;
     double* b = buf + (sel ? half : 0);
     sel ^= 1;

@@ -271,22 +271,84 @@ __device__ void down_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Forcing hierarchy: up to kMaxFuse full-weighting restrictions per launch
+// ---------------------------------------------------------------------------
+
+template <int K, int I>
+__device__ void forcing_level(const VertArgs& a, double* st, Xch& x, const double (&f)[K]) {
+  // f holds level I (I >= 1 are written); the next level is its restriction
+  const TileGeom G = tile_geom(a, I, K);
+  if constexpr (I > 0)
+    if (a.out[I - 1]) store_run<K>(st, f, G.wlo, G.clo, G.chi, a.out[I - 1]);  // null: not stored
+  if constexpr (I < kMaxFuse && K >= 2) {
+    if (I < a.levels) {
+      double f1[K / 2];
+      restrict_rhs_run<K>(f, f1, G.g0, G.n, x, a.ravg);
+      forcing_level<K / 2, I + 1>(a, st, x, f1);
+    }
+  }
+}
+
+template <int K, int I>
+__device__ void forcing_level_fast(const VertArgs& a, double* st, Xch& x, double (&f)[K],
+                                   int64_t wlo0) {
+  if constexpr (I > 0)
+    if (a.out[I - 1])  // null: not stored (uniform per launch)
+      store_run_fast<K>(st, f, a.out[I - 1] + (wlo0 >> I), (int)(a.halo >> I),
+                        (int)((a.halo + a.core) >> I));
+  if constexpr (I < kMaxFuse && K >= 2) {
+    if (I < a.levels) {
+      double f1[K / 2];
+      fw_fast<K>(f, f1, x, a.ravg);
+      forcing_level_fast<K / 2, I + 1>(a, st, x, f1, wlo0);
+    }
+  }
+}
+
+// a.rhs: level with a.n cells; writes a.levels coarser levels into
+// out[0..levels) (out[i] = level i+1 below).
+// One forcing tile (a.tile set): load, then the restriction chain.
+template <int K, int T>
+__device__ __forceinline__ void forcing_tile(const VertArgs& a, double* st, Xch& x) {
+  const int64_t wlo0 = top_wlo(a);
+  double f[K];
+  if (window_interior(wlo0, T * K, a.n)) {
+    load_run_fast<K, true>(st, f, a.rhs + wlo0, 0);
+    forcing_level_fast<K, 0>(a, st, x, f, wlo0);
+    return;
+  }
+  const TileGeom G = tile_geom(a, 0, K);
+  load_run<K>(st, f, G.wlo, T * K, G.n, [&](int64_t g) { return a.rhs[g]; });
+  forcing_level<K, 0>(a, st, x, f);
+}
+
+template <int K, int T>
+__global__ __launch_bounds__(T) void k_forcing(VertArgs a) {
+  __shared__ double st[T * (K + 1)];
+  __shared__ double xb[T == 64 ? 1 : 4 * T];
+  Xch x{xb, 0, 2 * T, T == 64};
+  a.tile = tile_index(a);
+  forcing_tile<K, T>(a, st, x);
+}
+
 // Down leg over `levels` stored levels (Fig. 3 steps 1-2 on the top level,
 // then restrict + smooth of the pre-smoothing leg), split tau: the coarse
 // right-hand side is the full weighting of the finer one (the Laplacian
 // part of tau is identically zero with I^ = average, I = full weighting).
-// OCC workgroups per CU: 3 (at most 168 VGPRs, a few spilled; 51 KB of LDS)
-// for launches of many tiles, 2 (no spills; a second stage buffer lets the
-// rhs and the interpolation source share one barrier) for the latency-bound
-// small ones.
-template <int K, bool F32, int OCC>
-__global__ __launch_bounds__(kTileThreads, OCC) void k_down(VertArgs a) {
-  __shared__ double st[kTileThreads * (K + 1)];
-  __shared__ double st2[OCC == 2 ? kTileThreads * (K / 2 + 1) : 1];
-  __shared__ double xb[8 * kTileThreads];
-  Xch x{xb, 0, 4 * kTileThreads};
+// OCC wavefronts per SIMD: 3 (at most 168 VGPRs, a few spilled; 51 KB of LDS
+// per 256-thread workgroup) for launches of many tiles, 2 (no spills; a
+// second stage buffer lets the rhs and the interpolation source share one
+// barrier) for the latency-bound small ones.  T threads per workgroup: 256,
+// or one wavefront (64), whose exchanges are lane shifts.
+template <int K, bool F32, int OCC, int T>
+__global__ __launch_bounds__(T, OCC) void k_down(VertArgs a) {
+  __shared__ double st[T * (K + 1)];
+  __shared__ double st2[OCC == 2 ? T * (K / 2 + 1) : 1];
+  __shared__ double xb[T == 64 ? 1 : 8 * T];
+  Xch x{xb, 0, 4 * T, T == 64};
   Xch4& x4 = x;  // one exchanger in both roles
-  const int wcount = kTileThreads * K;
+  const int wcount = T * K;
   a.tile = tile_index(a);
   const int64_t wlo0 = top_wlo(a);
   double u[K], f[K];
@@ -309,7 +371,7 @@ __global__ __launch_bounds__(kTileThreads, OCC) void k_down(VertArgs a) {
       double tu[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const double2 q = fb[threadIdx.x + k * kTileThreads];
+        const double2 q = fb[threadIdx.x + k * T];
         tu[k] = (q.x + q.y) * 0.5;
       }
       stage_tmp<K, true>(st, tf, f, 0);
@@ -549,7 +611,7 @@ __device__ void deep_level(const VertArgs& a, double* st, Xch& x, Xch4& x4, doub
     static_assert(K / 2 == KB, "bottom run");
     double cb[KB / 2];
     half_scaled<KB>(f1, f1, a.n >> (I + 1));
-    stage_two<KB, KB / 2>(st, tb, c, st + kTileThreads * (KB + 1), tc, cb);
+    stage_two<KB, KB / 2>(st, tb, c, st + (int)blockDim.x * (KB + 1), tc, cb);
     correct_fast<KB, F32>(a, x, x4, f1, c, cb);
   }
   // c: the post-smoothed iterate of level I + 1
@@ -620,15 +682,15 @@ __device__ __forceinline__ void segment_sums(const double (&u)[K], int a, int b,
 // Up leg over `levels` stored levels, bottom-up (Fig. 3 post-smoothing leg,
 // Eq. 4); only the top level's core is written.  Lower right-hand sides are
 // the full weighting of the top one (split tau).
-template <int K, bool F32>
-__global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
-  __shared__ double st[kTileThreads * (K + 1)];
-  __shared__ double st2[kTileThreads * (K / 2 + 1)];
-  __shared__ double xb[4 * kTileThreads];
-  __shared__ double xb4[8 * kTileThreads];
-  Xch x{xb, 0, 2 * kTileThreads};
-  Xch4 x4{xb4, 0, 4 * kTileThreads};
-  const int wcount = kTileThreads * K;
+template <int K, bool F32, int T>
+__global__ __launch_bounds__(T) void k_up(VertArgs a) {
+  __shared__ double st[T * (K + 1)];
+  __shared__ double st2[T * (K / 2 + 1)];
+  __shared__ double xb[T == 64 ? 1 : 4 * T];
+  __shared__ double xb4[T == 64 ? 1 : 8 * T];
+  Xch x{xb, 0, 2 * T, T == 64};
+  Xch4 x4{xb4, 0, 4 * T, T == 64};
+  const int wcount = T * K;
   a.tile = tile_index(a);
   const int64_t wlo0 = top_wlo(a);
   double u[K], f[K];
@@ -642,7 +704,7 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
       if (a.src) {  // Pi source run of the rebuilt top level, in tp[0, K/2)
         const double* cb = a.src + (wlo0 >> 1);
 #pragma unroll
-        for (int k = 0; k < K / 2; ++k) tp[k] = cb[threadIdx.x + k * kTileThreads];
+        for (int k = 0; k < K / 2; ++k) tp[k] = cb[threadIdx.x + k * T];
       } else if (!a.sr_top) {
         issue_loads<K, true>(tp, a.pre[0] + wlo0, 0);
       }
@@ -670,17 +732,16 @@ __global__ __launch_bounds__(kTileThreads) void k_up(VertArgs a) {
 }
 
 // Interior tiles of a deep up launch alone (the edge tiles take k_up): 166
-// VGPRs and 51 KB of LDS, so three workgroups share a CU (FP32 relaxation:
-// 182 VGPRs, two).
-template <int K, bool F32>
-__global__ __launch_bounds__(kTileThreads, F32 ? 2 : 3) void k_up_wide(VertArgs a) {
-  __shared__ double st[kTileThreads * (K + 1)];
-  __shared__ double xb[8 * kTileThreads];
-  Xch x{xb, 0, 4 * kTileThreads};
+// VGPRs, so three wavefronts share a SIMD (FP32 relaxation: 182 VGPRs, two).
+template <int K, bool F32, int T>
+__global__ __launch_bounds__(T, F32 ? 2 : 3) void k_up_wide(VertArgs a) {
+  __shared__ double st[T * (K + 1)];
+  __shared__ double xb[T == 64 ? 1 : 8 * T];
+  Xch x{xb, 0, 4 * T, T == 64};
   Xch4& x4 = x;  // one exchanger in both roles
   a.tile = tile_index(a);
   const int64_t wlo0 = top_wlo(a);
-  if (!window_interior(wlo0, kTileThreads * K, a.n)) return;  // the host launches interior tiles only
+  if (!window_interior(wlo0, T * K, a.n)) return;  // the host launches interior tiles only
   double u[K], f[K];
   if (a.levels == 4) deep_tile<K, 4, F32, false>(a, st, st, x, x4, f, u, wlo0);
   else deep_tile<K, 3, F32, false>(a, st, st, x, x4, f, u, wlo0);
@@ -690,59 +751,6 @@ __global__ __launch_bounds__(kTileThreads, F32 ? 2 : 3) void k_up_wide(VertArgs 
     const int e0 = (int)threadIdx.x * K;
     segment_sums<K>(u, (int)a.halo - e0, (int)(a.halo + a.core) - e0, st, a.part, a.tile);
   }
-}
-
-// ---------------------------------------------------------------------------
-// Forcing hierarchy: up to kMaxFuse full-weighting restrictions per launch
-// ---------------------------------------------------------------------------
-
-template <int K, int I>
-__device__ void forcing_level(const VertArgs& a, double* st, Xch& x, const double (&f)[K]) {
-  // f holds level I (I >= 1 are written); the next level is its restriction
-  const TileGeom G = tile_geom(a, I, K);
-  if constexpr (I > 0) store_run<K>(st, f, G.wlo, G.clo, G.chi, a.out[I - 1]);
-  if constexpr (I < kMaxFuse && K >= 2) {
-    if (I < a.levels) {
-      double f1[K / 2];
-      restrict_rhs_run<K>(f, f1, G.g0, G.n, x, a.ravg);
-      forcing_level<K / 2, I + 1>(a, st, x, f1);
-    }
-  }
-}
-
-template <int K, int I>
-__device__ void forcing_level_fast(const VertArgs& a, double* st, Xch& x, double (&f)[K],
-                                   int64_t wlo0) {
-  if constexpr (I > 0)
-    store_run_fast<K>(st, f, a.out[I - 1] + (wlo0 >> I), (int)(a.halo >> I),
-                      (int)((a.halo + a.core) >> I));
-  if constexpr (I < kMaxFuse && K >= 2) {
-    if (I < a.levels) {
-      double f1[K / 2];
-      fw_fast<K>(f, f1, x, a.ravg);
-      forcing_level_fast<K / 2, I + 1>(a, st, x, f1, wlo0);
-    }
-  }
-}
-
-// a.rhs: level with a.n cells; writes a.levels coarser levels into
-// out[0..levels) (out[i] = level i+1 below).
-template <int K>
-__global__ __launch_bounds__(kTileThreads) void k_forcing(VertArgs a) {
-  __shared__ double st[kTileThreads * (K + 1)];
-  __shared__ double xb[4 * kTileThreads];
-  Xch x{xb, 0, 2 * kTileThreads};
-  a.tile = tile_index(a);
-  const int64_t wlo0 = top_wlo(a);
-  double f[K];
-  if (window_interior(wlo0, kTileThreads * K, a.n)) {
-    load_run_fast<K, true>(st, f, a.rhs + wlo0, 0);
-    forcing_level_fast<K, 0>(a, st, x, f, wlo0);
-    return;
-  }
-  const TileGeom G = tile_geom(a, 0, K);
-  load_run<K>(st, f, G.wlo, kTileThreads * K, G.n, [&](int64_t g) { return a.rhs[g]; });
-  forcing_level<K, 0>(a, st, x, f);
 }
 
 // ---------------------------------------------------------------------------
