@@ -292,17 +292,22 @@ __device__ __forceinline__ void run_to_stage(double* st, const double (&v)[K]) {
 // while e < wcount) into registers through the stage: v = val(global index)
 // for cells in [0, n), 0 elsewhere.  All K loads are issued unconditionally
 // (at a clamped, in-range index) before any is consumed, so their latencies
-// overlap; the validity test only selects the value.
+// overlap; the validity test only selects the value.  issue_run and
+// stage_run are its two halves, for callers that put several windows'
+// loads in flight at once.
 template <int K, class Fn>
-__device__ __forceinline__ void load_run(double* st, double (&v)[K], int64_t wlo, int wcount,
-                                         int64_t n, Fn val) {
+__device__ __forceinline__ void issue_run(double (&tmp)[K], int64_t wlo, int64_t n, Fn val) {
   const int W = blockDim.x;
-  double tmp[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int64_t g = wlo + threadIdx.x + k * W;
     tmp[k] = val(g < 0 ? 0 : (g >= n ? n - 1 : g));
   }
+}
+template <int K>
+__device__ __forceinline__ void stage_run(double* st, const double (&tmp)[K], double (&v)[K],
+                                          int64_t wlo, int wcount, int64_t n) {
+  const int W = blockDim.x;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int e = threadIdx.x + k * W;
@@ -312,6 +317,13 @@ __device__ __forceinline__ void load_run(double* st, double (&v)[K], int64_t wlo
   __syncthreads();
   stage_to_run<K>(st, v);
   __syncthreads();
+}
+template <int K, class Fn>
+__device__ __forceinline__ void load_run(double* st, double (&v)[K], int64_t wlo, int wcount,
+                                         int64_t n, Fn val) {
+  double tmp[K];
+  issue_run<K>(tmp, wlo, n, val);
+  stage_run<K>(st, tmp, v, wlo, wcount, n);
 }
 
 // Registers -> coalesced store of window cells whose global index lies in
@@ -341,19 +353,36 @@ __device__ __forceinline__ void interp_from_e(double (&u)[K], const double (&e)[
 // threads read them from HBM), so Pi is exact on the whole window.  Cells
 // beyond the domain use the Dirichlet reflections (nested for a one-cell
 // level), cells outside [0, n) are set to 0.
+// The coarse values the window-edge threads read from HBM for Pi: thread
+// 0's J0-2, J0-1 and the last thread's J0+K/2, J0+K/2+1 (clamped into the
+// level), issued by edge_issue ahead of their use.
+struct PiEdges {
+  double a, b;
+};
 template <int K>
-__device__ __forceinline__ void interp_from_run(double (&u)[K], const double (&c)[K / 2],
-                                                int64_t g0, int64_t n,
-                                                const double* __restrict__ cg, double gL,
-                                                double gR, Xch& x) {
+__device__ __forceinline__ PiEdges edge_issue(int64_t g0, int64_t n,
+                                              const double* __restrict__ cg) {
+  const int64_t nc = n >> 1;
+  const int64_t J0 = g0 >> 1;
+  auto at = [&](int64_t j) { return cg[j < 0 ? 0 : (j >= nc ? nc - 1 : j)]; };
+  PiEdges e{0.0, 0.0};
+  if (threadIdx.x == 0) { e.a = at(J0 - 2); e.b = at(J0 - 1); }
+  if (threadIdx.x == blockDim.x - 1) { e.a = at(J0 + K / 2); e.b = at(J0 + K / 2 + 1); }
+  return e;
+}
+
+// Pi from the run c and the edge values ed (edge_issue of the same g0).
+template <int K>
+__device__ __forceinline__ void interp_from_run_edges(double (&u)[K], const double (&c)[K / 2],
+                                                      int64_t g0, int64_t n, const PiEdges& ed,
+                                                      double gL, double gR, Xch& x) {
   const int64_t nc = n >> 1;
   const int64_t J0 = g0 >> 1;
   double l1, r0, l2, r1;
   x.swap(c[0], c[K / 2 - 1], l1, r0);
   x.swap(c[1], c[K / 2 - 2], l2, r1);
-  auto at = [&](int64_t j) { return cg[j < 0 ? 0 : (j >= nc ? nc - 1 : j)]; };
-  if (threadIdx.x == 0) { l2 = at(J0 - 2); l1 = at(J0 - 1); }
-  if (threadIdx.x == blockDim.x - 1) { r0 = at(J0 + K / 2); r1 = at(J0 + K / 2 + 1); }
+  if (threadIdx.x == 0) { l2 = ed.a; l1 = ed.b; }
+  if (threadIdx.x == blockDim.x - 1) { r0 = ed.a; r1 = ed.b; }
   double e[K / 2 + 4];  // coarse J0-2 .. J0+K/2+1
   e[0] = l2;
   e[1] = l1;
@@ -362,6 +391,14 @@ __device__ __forceinline__ void interp_from_run(double (&u)[K], const double (&c
   e[K / 2 + 2] = r0;
   e[K / 2 + 3] = r1;
   interp_from_e<K>(u, e, J0, nc, gL, gR);
+}
+
+template <int K>
+__device__ __forceinline__ void interp_from_run(double (&u)[K], const double (&c)[K / 2],
+                                                int64_t g0, int64_t n,
+                                                const double* __restrict__ cg, double gL,
+                                                double gR, Xch& x) {
+  interp_from_run_edges<K>(u, c, g0, n, edge_issue<K>(g0, n, cg), gL, gR, x);
 }
 
 // Pi of the coarse values e[m] = cell J0 - 2 + m (m < K/2 + 4) into the run
@@ -392,9 +429,12 @@ __device__ __forceinline__ void load_interp_run(double* st, double (&v)[K], int6
                                                 const double* __restrict__ c, double gL,
                                                 double gR, Xch& x) {
   // coarse cells under the window plus the two the last valid pairs reach
-  double cr[K / 2];
-  load_run<K / 2>(st, cr, wlo >> 1, (wcount + 1) / 2 + 2, n >> 1, [&](int64_t J) { return c[J]; });
-  interp_from_run<K>(v, cr, wlo + (int64_t)threadIdx.x * K, n, c, gL, gR, x);
+  const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
+  double tc[K / 2], cr[K / 2];
+  issue_run<K / 2>(tc, wlo >> 1, n >> 1, [&](int64_t J) { return c[J]; });
+  const PiEdges ed = edge_issue<K>(g0, n, c);
+  stage_run<K / 2>(st, tc, cr, wlo >> 1, (wcount + 1) / 2 + 2, n >> 1);
+  interp_from_run_edges<K>(v, cr, g0, n, ed, gL, gR, x);
 }
 
 // I^ of the finer level (pairs read as one 16-byte load) into the window.

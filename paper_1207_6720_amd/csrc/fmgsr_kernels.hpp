@@ -385,14 +385,31 @@ __global__ __launch_bounds__(T, OCC) void k_down(VertArgs a) {
     down_level_fast<K, 0, F32>(a, st, x, x4, u, f, wlo0);
     return;
   }
+  // edge tile: the rhs, the source and Pi's edge values in flight together
   const TileGeom G = tile_geom(a, 0, K);
-  load_run<K>(st, f, G.wlo, wcount, G.n, [&](int64_t g) { return a.rhs[g]; });
-  if (a.src_kind == kSrcInterp)
-    load_interp_run<K>(st, u, G.wlo, wcount, G.n, a.src, a.gL, a.gR, x);
-  else if (a.src_kind == kSrcRestrict)
-    load_restrict_run<K>(st, u, G.wlo, wcount, G.n, a.src);
-  else
-    load_run<K>(st, u, G.wlo, wcount, G.n, [&](int64_t g) { return a.src[g]; });
+  double tf[K];
+  issue_run<K>(tf, G.wlo, G.n, [&](int64_t g) { return a.rhs[g]; });
+  if (a.src_kind == kSrcInterp) {
+    double tc[K / 2], c[K / 2];
+    issue_run<K / 2>(tc, G.wlo >> 1, G.n >> 1, [&](int64_t J) { return a.src[J]; });
+    const PiEdges ed = edge_issue<K>(G.g0, G.n, a.src);
+    stage_run<K>(st, tf, f, G.wlo, wcount, G.n);
+    stage_run<K / 2>(st, tc, c, G.wlo >> 1, (wcount + 1) / 2 + 2, G.n >> 1);
+    interp_from_run_edges<K>(u, c, G.g0, G.n, ed, a.gL, a.gR, x);
+  } else {
+    double tu[K];
+    if (a.src_kind == kSrcRestrict) {
+      const double2* __restrict__ f2 = reinterpret_cast<const double2*>(a.src);
+      issue_run<K>(tu, G.wlo, G.n, [&](int64_t g) {
+        const double2 q = f2[g];
+        return (q.x + q.y) * 0.5;
+      });
+    } else {
+      issue_run<K>(tu, G.wlo, G.n, [&](int64_t g) { return a.src[g]; });
+    }
+    stage_run<K>(st, tf, f, G.wlo, wcount, G.n);
+    stage_run<K>(st, tu, u, G.wlo, wcount, G.n);
+  }
   down_level<K, 0, F32>(a, st, x, u, f);
 }
 
@@ -544,7 +561,7 @@ __device__ __forceinline__ void correct_fast(const VertArgs& a, Xch& x, Xch4& x4
 // coarser levels' loads are issued before descending, so every HBM read of
 // the kernel is outstanding at once.
 template <int K, int I, bool F32>
-__device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4, double (&f)[K],
+__device__ __forceinline__ void up_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4, double (&f)[K],
                               double (&u)[K], const double (&tp)[K], int64_t wlo0) {
   const int64_t wlo = wlo0 >> I;
   double c[K / 2];
@@ -597,7 +614,7 @@ __device__ void up_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4, d
 // iterate (tb) and the coarse iterate below it (tc) from HBM, loaded at the
 // start of the kernel.  u leaves with the level's post-smoothed iterate.
 template <int K, int I, int L, bool F32, int KB>
-__device__ void deep_level(const VertArgs& a, double* st, Xch& x, Xch4& x4, double (&f)[K],
+__device__ __forceinline__ void deep_level(const VertArgs& a, double* st, Xch& x, Xch4& x4, double (&f)[K],
                            double (&u)[K], const double (&tb)[KB], const double (&tc)[KB / 2]) {
   double f1[K / 2], c[K / 2];
   fw_fast<K>(f, f1, x);
