@@ -386,9 +386,34 @@ static int smooth_level(int kind, rlevel_t *lv, int l, int M, int nu, const orc_
  *   the coarsest level takes a Newton solve from I^ u^1; on the way up
  *   u^{m+1} += P(u^m - I^ u^{m+1}) (or, on the SR level, the full update
  *   Pi u^m and compatible relaxation), then nu2 sweeps. */
+static int rx_fmgsr_solve_core(int kind, const double *f, const double *coef, double gL,
+                               double gR, int64_t n, int levels, int64_t S, int64_t b,
+                               const orc_rx_options *o, double *u_out, int order,
+                               double *coarse_out);
+
 int orc_rx_fmgsr_solve_ex(int kind, const double *f, const double *coef, double gL, double gR,
                           int64_t n, int levels, int64_t S, int64_t b, const orc_rx_options *o,
                           double *u_out, int order)
+{
+  return rx_fmgsr_solve_core(kind, f, coef, gL, gR, n, levels, S, b, o, u_out, order, NULL);
+}
+
+/* The same iteration, also returning the level-(M-1) solution it ends with
+ * (the last step's post-smoothed iterate below the finest level, from which
+ * the finest level's full update and compatible relaxation are made;
+ * Sec. 2.4 keeps exactly this level).  coarse_out: n/2 values (M >= 1). */
+int orc_rx_fmgsr_solve_keep(int kind, const double *f, const double *coef, double gL, double gR,
+                            int64_t n, int levels, int64_t S, int64_t b, const orc_rx_options *o,
+                            double *u_out, double *coarse_out)
+{
+  if (levels < 2 || !coarse_out) return ORC_EINVAL;
+  return rx_fmgsr_solve_core(kind, f, coef, gL, gR, n, levels, S, b, o, u_out, 0, coarse_out);
+}
+
+static int rx_fmgsr_solve_core(int kind, const double *f, const double *coef, double gL,
+                               double gR, int64_t n, int levels, int64_t S, int64_t b,
+                               const orc_rx_options *o, double *u_out, int order,
+                               double *coarse_out)
 {
   int M = rx_validate(kind, n, levels, S, b, o);
   if (M < 0) return M;
@@ -445,6 +470,8 @@ int orc_rx_fmgsr_solve_ex(int kind, const double *f, const double *coef, double 
     }
   }
   if (st == ORC_OK) memcpy(u_out, lv[M].u, sizeof(double) * (size_t)n);
+  if (st == ORC_OK && coarse_out && M >= 1)
+    memcpy(coarse_out, lv[M - 1].u, sizeof(double) * (size_t)lv[M - 1].n);
   free(patches);
   free_rlevels(lv, M + 1);
   return st;

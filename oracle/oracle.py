@@ -87,6 +87,9 @@ def lib():
         L.orc_rx_fmgsr_solve_ex.argtypes = [_ci, _ptr, _ptr, _dbl, _dbl, _i64, _ci, _i64, _i64,
                                             ctypes.POINTER(RxOptions), _ptr, _ci]
         L.orc_rx_fmgsr_solve_ex.restype = _ci
+        L.orc_rx_fmgsr_solve_keep.argtypes = [_ci, _ptr, _ptr, _dbl, _dbl, _i64, _ci, _i64, _i64,
+                                              ctypes.POINTER(RxOptions), _ptr, _ptr]
+        L.orc_rx_fmgsr_solve_keep.restype = _ci
         L.orc_rx_fas_vcycle.argtypes = [_ci, _ptr, _ptr, _ptr, _dbl, _dbl, _i64, _ci,
                                         ctypes.POINTER(RxOptions)]
         L.orc_rx_fas_vcycle.restype = _ci
@@ -308,6 +311,26 @@ def rx_fmgsr_solve(kind, f, a=None, gL=0.0, gR=0.0, levels=None, segments=1, buf
     if st != 0:
         raise ValueError(f"orc_rx_fmgsr_solve failed with status {st}")
     return out
+
+
+def rx_fmgsr_solve_keep(kind, f, a=None, gL=0.0, gR=0.0, levels=None, segments=1, buffer=0,
+                        **opt):
+    """rx_fmgsr_solve, also returning the level-(M-1) solution the iteration
+    ends with (Sec. 2.4): (u, coarse)."""
+    f, pf = _c(f)
+    n = f.size
+    a, pa = _coef(kind, a, n)
+    if levels is None:
+        levels = int(np.log2(n)) + 1
+    o = rx_options(**opt)
+    out = np.empty_like(f)
+    coarse = np.empty(n // 2, dtype=np.float64)
+    st = lib().orc_rx_fmgsr_solve_keep(RX_KINDS[kind], pf, pa, gL, gR, n, levels, segments,
+                                       buffer, ctypes.byref(o), out.ctypes.data_as(_ptr),
+                                       coarse.ctypes.data_as(_ptr))
+    if st != 0:
+        raise ValueError(f"orc_rx_fmgsr_solve_keep failed with status {st}")
+    return out, coarse
 
 
 def rx_fas_vcycle(kind, u, f, a=None, gL=0.0, gR=0.0, levels=None, **opt):

@@ -210,6 +210,49 @@ def test_segments_change_the_result_only_slightly():
 
 
 # --------------------------------------------------------------------------
+# Kept level-(M-1) solution (PDE compression, Sec. 2.4)
+# --------------------------------------------------------------------------
+
+def test_kept_level_with_kappa_zero_is_the_poisson_oracles():
+    n = 1024
+    f = W.rhs_numpy(n, *W.modes("inv_k2", 8, 2))
+    kw = dict(levels=11, segments=8, buffer=4)
+    u_ref, c_ref = oracle.fmgsr_solve_keep(f, 0.2, -0.1, **kw)
+    u, c = oracle.rx_fmgsr_solve_keep("cubic", f, np.zeros(n), 0.2, -0.1, **kw)
+    assert np.array_equal(u, u_ref) and np.array_equal(c, c_ref)
+    assert np.array_equal(u, oracle.rx_fmgsr_solve("cubic", f, np.zeros(n), 0.2, -0.1, **kw))
+
+
+@pytest.mark.parametrize("n0,L,S,b", [(1, 9, 8, 4), (39, 6, 6, 3), (5, 8, 4, 1), (3, 2, 1, 2)])
+def test_kept_level_regenerates_the_solution(n0, L, S, b):
+    """Sec. 2.4: the finest level follows from the kept level and f alone.
+    Rebuilt here from the oracle's primitives (Pi of the kept level, then
+    per extended patch nu2 x [Kaczmarz onto the kept level, one nonlinear
+    sweep], Eq. 5 and Fig. 5), it must equal the iteration's own result."""
+    n = n0 << (L - 1)
+    f, k, _, _ = problem(n, seed=n0)
+    gL, gR = 0.3, -0.2
+    u, c = oracle.rx_fmgsr_solve_keep("cubic", f, k, gL, gR, levels=L, segments=S, buffer=b)
+    assert c.size == n // 2
+    v = oracle.interp_fmg(c, gL, gR)
+    s = n // S
+    out = np.empty(n)
+    for i in range(S):
+        lo, hi = max(i * s - b, 0), min((i + 1) * s + b, n)
+        w = v.copy()
+        for _ in range(1):  # nu2 = 1
+            w = oracle.kaczmarz(w, c, lo, hi)
+            w = oracle.rx_ngs_sweep("cubic", k, w, f, lo, hi, gL, gR)
+        out[i * s:(i + 1) * s] = w[i * s:(i + 1) * s]
+    assert np.array_equal(out, u)
+    # a different kept level gives a different fine level (the check is live)
+    v2 = oracle.interp_fmg(c * (1 + 1e-9), gL, gR)
+    w = oracle.rx_ngs_sweep("cubic", k, oracle.kaczmarz(v2, c, 0, min(s + b, n)), f, 0,
+                            min(s + b, n), gL, gR)
+    assert not np.array_equal(w[:s], u[:s])
+
+
+# --------------------------------------------------------------------------
 # Adjoint
 # --------------------------------------------------------------------------
 
