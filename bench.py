@@ -215,6 +215,9 @@ def main():
     ap.add_argument("--sr-levels", type=int, default=1, choices=[0, 1, 2, 3],
                     help="Poisson workloads: number of SR levels (2 and 3: the finest levels "
                          "below the top are SR levels too, split tau only)")
+    ap.add_argument("--adjoint-keep", default="u", choices=["u", "coarse"],
+                    help="c4: what the forward keeps for the adjoint: u, or only its "
+                         "level-(M-1) solution, with u_fwd rebuilt inside the adjoint")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 2^27 doubles (1 GiB read + 1 GiB "
@@ -415,21 +418,31 @@ def run_batched(args, dev):
         torch.cuda.synchronize()
         del src, dst
         log("copy calibration: 2^27 doubles copied")
+    keep_coarse = adjoint and args.adjoint_keep == "coarse"
+    coarse = None
     if adjoint:
         hvec = torch.cat([torch.full((n,), 1.0 / n, dtype=torch.float64, device=dev)
                           for n in rb.sizes])
         gf, gk, dJ = torch.empty_like(f), torch.empty_like(f), torch.empty_like(f)
+        if keep_coarse:
+            coarse = torch.empty(plan.coarse_total, dtype=torch.float64, device=dev)
 
     tuned_ms = plan.autotune(f, k, u, stream=stream)
     log(f"autotuned: {tuned_ms:.3f} ms per solve, {plan.query()['threads']} threads, "
         f"group {plan.query()['group']}")
 
     def step():
-        plan.solve(f, k, out=u, stream=stream)
+        if keep_coarse:
+            plan.solve_keep(f, k, coarse=coarse, out=u, stream=stream)
+        else:
+            plan.solve(f, k, out=u, stream=stream)
         if adjoint:
             torch.sub(u, ut, out=dJ)
             dJ.mul_(hvec).mul_(2.0)
-            plan.adjoint(k, u, dJ, gf, gk, stream=stream)
+            if keep_coarse:
+                plan.adjoint_compressed(k, f, coarse, dJ, gf, gk, stream=stream)
+            else:
+                plan.adjoint(k, u, dJ, gf, gk, stream=stream)
 
     torch.cuda.synchronize()
     mem_inputs = torch.cuda.memory_allocated(dev)
@@ -540,7 +553,8 @@ def run_batched(args, dev):
                    "batch": rb.batch, "total_unknowns": rb.total, "buffer": rb.buffer,
                    "nu": [2, 1], "smoother": "red-black nonlinear GS", "precision": args.precision,
                    "seed": rb.seed, "threads": q["threads"], "run": q["run"], "grid": q["grid"],
-                   "group": q["group"], "autotuned": True},
+                   "group": q["group"], "autotuned": True}
+                  | ({"adjoint_keep": args.adjoint_keep} if adjoint else {}),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "solve_model": {"algo_bytes_per_step": sum(v["algo_bytes"] for v in prof_all.values()),
@@ -548,7 +562,11 @@ def run_batched(args, dev):
         "accuracy": acc,
         "memory": {"inputs_and_workspace_bytes": mem_inputs,
                    "workspace_bytes": q["workspace_bytes"],
-                   "peak_allocated_bytes": torch.cuda.max_memory_allocated(dev)},
+                   "peak_allocated_bytes": torch.cuda.max_memory_allocated(dev)}
+                  | ({"adjoint_state_bytes": 8 * (plan.coarse_total if keep_coarse else rb.total),
+                      "adjoint_state": ("the forward's level-(M-1) solution (u_fwd rebuilt "
+                                        "inside the adjoint)" if keep_coarse else "u_fwd")}
+                     if adjoint else {}),
         "kernels": {kname: {"launches": v["launches"], "ms": round(v["total_ms"], 4),
                             "GBps": round(v["algo_bytes"] / max(v["total_ms"], 1e-9) / 1e6, 1)}
                     for kname, v in prof_all.items()},

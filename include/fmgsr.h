@@ -353,6 +353,38 @@ fmgsr_status fmgsr_batch_adjoint(fmgsr_batch plan, const double *kappa_packed,
                                  double *grad_f_packed, double *grad_kappa_packed,
                                  void *hip_stream);
 
+/* PDE compression of the batch (Sec. 2.4; Sec. 3.2): one FMG-FAS-SR
+ * iteration that also keeps every problem's level-(M-1) solution V^{M-1}
+ * (the last step's post-smoothed iterate below the SR level).  Problem j's
+ * n_j/2 values go to coarse_packed[offset_j/2 .. offset_j/2 + n_j/2)
+ * (integer division; problems of one grid keep nothing), so a packed
+ * coarse array of half the packed length holds back-to-back problems.
+ * u_packed as fmgsr_batch_solve, or NULL: then only V^{M-1} is produced
+ * and the SR up pass is skipped.  The kept array together with f and kappa
+ * determines the fine solution: fmgsr_batch_adjoint_compressed rebuilds it
+ * from them.  Asynchronous on hip_stream; EINVAL for a non-device or
+ * aliased array. */
+fmgsr_status fmgsr_batch_solve_keep(fmgsr_batch plan, const double *f_packed,
+                                    const double *kappa_packed, double *u_packed,
+                                    double *coarse_packed, void *hip_stream);
+
+/* fmgsr_batch_adjoint without u_fwd (Sec. 2.4: levels are recomputed, not
+ * stored): wherever the adjoint needs 3 kappa u_fwd^2 on the finest level
+ * (its forcing and both SR passes), u_fwd is rebuilt segment by segment by
+ * the forward's own SR up pass (Eq. 5, Fig. 5) from f_fwd_packed, kappa and
+ * coarse_fwd_packed (a fmgsr_batch_solve_keep of the same plan and inputs);
+ * a window's buffer cells come from the neighbouring segments' rebuilds.
+ * The rebuilt u_fwd equals the forward's bit for bit, so the gradients
+ * equal fmgsr_batch_adjoint's on that forward's u.  Costs seven forward SR
+ * up passes per adjoint; saves holding n doubles of u_fwd (the kept level
+ * is n/2).  ENOTSUP unless the plan is cubic and every problem's segment
+ * core is at least the window pad ((buffer + 2) rounded down to even). */
+fmgsr_status fmgsr_batch_adjoint_compressed(fmgsr_batch plan, const double *kappa_packed,
+                                            const double *f_fwd_packed,
+                                            const double *coarse_fwd_packed,
+                                            const double *dJdu_packed, double *grad_f_packed,
+                                            double *grad_kappa_packed, void *hip_stream);
+
 /* Project autotuner: times the plan's candidate launch shapes (workgroup
  * size 256 or 512, 4 or 8 cells per thread, workgroups per problem 1..16
  * when the batch is small) and segment sizes (the largest fitting core and
@@ -381,9 +413,13 @@ fmgsr_status fmgsr_solve_batched(int32_t batch, const int64_t *n_host, const int
                                  const fmgsr_options *opt, double *u_packed, void *hip_stream);
 
 /* Adjoint of one cubic problem (op->kind = FMGSR_OP_CUBIC_REACTION, op->kappa
- * [n]).  u_fwd = the forward solution, or NULL: it is then recomputed by one
- * FMG-FAS-SR iteration with f, g_left, g_right into a temporary buffer.
- * dJ_du [n]; outputs as fmgsr_batch_adjoint.  Synchronous. */
+ * [n]).  u_fwd = the forward solution, or NULL: the forward iteration with
+ * f, g_left, g_right is then run keeping only its level-(M-1) solution (a
+ * temporary of n/2 doubles) and the adjoint rebuilds u_fwd from it
+ * (fmgsr_batch_adjoint_compressed); where that does not apply (one grid,
+ * segment cores shorter than the window pad) u_fwd is computed into a
+ * temporary of n doubles.  dJ_du [n]; outputs as fmgsr_batch_adjoint.
+ * Synchronous. */
 fmgsr_status fmgsr_adjoint(const fmgsr_operator *op, const double *f, double g_left,
                            double g_right, int64_t n, int32_t levels, int64_t n_segments,
                            int32_t buffer, const fmgsr_options *opt, const double *u_fwd,

@@ -57,6 +57,7 @@ constexpr int kF64 = 0, kF32 = 1;
 constexpr int kMaxBatchN0 = 256;     // coarsest level solved in LDS
 constexpr int kMaxThreads = 512;
 constexpr int64_t kLvlAlign = 32;    // doubles: level arrays start 256-byte aligned
+constexpr int kMaxPad = 66;          // SR window pad for the largest buffer (64)
 
 enum Src : int { kZero = 0, kInterp = 1, kRestrict = 2, kDirect = 3 };
 
@@ -65,6 +66,7 @@ struct Prob {
   int64_t off;    // offset of the problem in the packed f / kappa / u arrays
   int64_t ws;     // offset (doubles) of its workspace slab
   int64_t seg;    // SR segment core (fine cells)
+  int64_t coff;   // offset of its level-(M-1) solution in a packed coarse array
   int32_t M;      // levels - 1
   int32_t n0;     // coarsest cells
   double gL, gR;
@@ -81,6 +83,9 @@ struct Args {
   double* u;             // packed result (adjoint: grad_f = lambda), may be null
   double* gk;            // adjoint: packed grad_kappa = -u^3 lambda, may be null
   double* ws;
+  double* vkeep;         // forward: packed level-(M-1) solution out, or null
+  const double* ffwd;    // adjoint without u_fwd: the forward's packed rhs
+  const double* vfwd;    // ... and its kept level-(M-1) solution
   int nu1, nu2, buffer, halo;
   int region;            // doubles of the LDS stage / coarse-solve region
   int adjoint;           // 1: homogeneous boundary values (adjoint solve)
@@ -118,10 +123,15 @@ struct Ctx {
   int member, G; // this workgroup's rank in the problem's group, group size
   int32_t* bar;  // the problem's barrier (count, generation)
   int32_t* status;
-  __device__ int64_t nl(int l) const { return n0 << l; }
-  __device__ int64_t off(int l) const { return lvl_off(n0, l); }
+  double* vk;          // forward: the last step's V^{M-1} goes here (null: workspace)
+  const double* ff;    // adjoint rebuild: forward rhs, kept V^{M-1} (null: u_fwd given)
+  const double* vf;
+  double gLf, gRf;     // forward boundary values
+  double* eb;          // LDS, 2 * kMaxPad doubles: window cells of neighbour patches
+  __device__ __forceinline__ int64_t nl(int l) const { return n0 << l; }
+  __device__ __forceinline__ int64_t off(int l) const { return lvl_off(n0, l); }
   // fine-level coefficient: kappa, or 3 kappa u_fwd^2 for the adjoint
-  __device__ double coef_fine(int64_t g) const {
+  __device__ __forceinline__ double coef_fine(int64_t g) const {
     if (!kap) return 0.0;
     if (uf) { const double v = uf[g]; return (3.0 * kap[g]) * (v * v); }
     return kap[g];
@@ -146,7 +156,26 @@ __device__ __forceinline__ Ctx make_ctx(const Prob& p, const Args& a) {
   c.member = 0;
   c.bar = nullptr;
   c.status = a.status;
+  c.vk = (a.vkeep && p.M >= 1) ? a.vkeep + p.coff : nullptr;
+  c.ff = a.ffwd ? a.ffwd + p.off : nullptr;
+  c.vf = (a.vfwd && p.M >= 1) ? a.vfwd + p.coff : nullptr;
+  c.gLf = p.gL;
+  c.gRf = p.gR;
+  c.eb = nullptr;
   return c;
+}
+
+// The forward problem's view for rebuilding u_fwd: its rhs, kappa as the
+// coefficient, its boundary values, no outputs.
+__device__ __forceinline__ Ctx forward_ctx(const Ctx& c) {
+  Ctx f = c;
+  f.f = c.ff;
+  f.uf = nullptr;
+  f.uo = nullptr;
+  f.gk = nullptr;
+  f.gL = c.gLf;
+  f.gR = c.gRf;
+  return f;
 }
 
 // ---------------------------------------------------------------------------
@@ -435,7 +464,7 @@ __device__ __forceinline__ Tiling tiling(int64_t n, int K, int halo) {
 // coarser V, I^ of the finer U, or a copy), nu1 sweeps with F, the core is
 // stored to U^l and (reaction operators) the coarse rhs to Q^{l-1}.
 template <int K, int OP, int PREC>
-__device__ void down_visit(const Ctx& c, const Args& ar, int l, int src_kind, const double* src,
+__device__ __forceinline__ void down_visit(const Ctx& c, const Args& ar, int l, int src_kind, const double* src,
                            const double* F, double* st, Xch& x) {
   const int64_t n = c.nl(l);
   const double* A = c.A + c.off(l);
@@ -489,14 +518,15 @@ __device__ void down_visit(const Ctx& c, const Args& ar, int l, int src_kind, co
 }
 
 // Up visit of stored level l: V^l = U^l + P(V^{l-1} - I^ U^l), nu2 sweeps.
+// Vout: where V^l goes (null: the workspace).
 template <int K, int OP, int PREC>
-__device__ void up_visit(const Ctx& c, const Args& ar, int l, const double* F, double* st,
-                         Xch& x) {
+__device__ __forceinline__ void up_visit(const Ctx& c, const Args& ar, int l, const double* F, double* st,
+                         Xch& x, double* Vout = nullptr) {
   const int64_t n = c.nl(l), nc = n >> 1;
   const double* A = c.A + c.off(l);
   const double* Up = c.U + c.off(l);
   const double* Vc = c.V + c.off(l - 1);
-  double* Vo = c.V + c.off(l);
+  double* Vo = Vout ? Vout : c.V + c.off(l);
   const Tiling tl = tiling(n, K, ar.halo);
   const int64_t first = (tl.ntiles == 1) ? 0 : c.member, stride = (tl.ntiles == 1) ? 1 : c.G;
   for (int64_t ti = first; ti < tl.ntiles; ti += stride) {
@@ -544,42 +574,152 @@ __device__ void up_visit(const Ctx& c, const Args& ar, int l, const double* F, d
   __syncthreads();
 }
 
+// SR up pass of segment i (Eq. 5, Fig. 5) on staged runs: ubar = Pi of the
+// coarse run cr (V^{M-1} under the window, Vc for the edge values), then
+// nu2 x [Kaczmarz projection of the patch's full pairs onto I^ ubar =
+// V^{M-1}, one sweep].
+template <int K, int OP, int PREC>
+__device__ __forceinline__ void sr_up_runs(const Ctx& c, const Args& ar, const double* Vc,
+                                           int64_t i, const double (&cr)[K / 2],
+                                           const double (&Fr)[K], const double (&a)[K],
+                                           double (&u)[K], Xch& x) {
+  const int64_t n = c.n, s = c.seg;
+  const int64_t pad = (ar.buffer + 2) & ~1;
+  const int64_t wlo = i * s - pad;
+  const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
+  interp_from_run<K>(u, cr, g0, n, Vc, c.gL, c.gR, x);
+  const int64_t lo = max(i * s - ar.buffer, (int64_t)0), hi = min((i + 1) * s + ar.buffer, n);
+  const SweepGeom sg = sweep_geom(g0, K, lo, hi, n, c.gL, c.gR);
+  for (int it = 0; it < ar.nu2; ++it) {
+#pragma unroll
+    for (int p = 0; p < K / 2; ++p) {
+      const int64_t g = g0 + 2 * p;
+      if (g >= lo && g + 1 < hi) {
+        const double r = cr[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
+        u[2 * p] = u[2 * p] + r;
+        u[2 * p + 1] = u[2 * p + 1] + r;
+      }
+    }
+    smooth<K, OP, PREC>(u, Fr, a, sg, 1, x);
+  }
+}
+
+// u_fwd on the window of segment j, exact on its core [j s, (j+1) s): the
+// forward's SR up pass of that segment again (cf = forward_ctx), from its
+// rhs, kappa and kept V^{M-1}.  Same window, same code, so the same bits.
+template <int K, int PREC>
+__device__ __forceinline__ void fwd_patch(const Ctx& cf, const Args& ar, int64_t j,
+                                          double (&w)[K], double* st, Xch& x) {
+  const int64_t n = cf.n, nc = n >> 1, s = cf.seg;
+  const int64_t pad = (ar.buffer + 2) & ~1;
+  const int wcount = (int)(s + 2 * pad);
+  const int64_t wlo = j * s - pad;
+  double Fr[K], a[K], cr[K / 2];
+  double tf[K], ta[K], tc[K / 2];
+  const Win wf = make_win(wlo, wcount, n);
+  const Win wc = make_win(wlo >> 1, (wcount + 1) / 2 + 2, nc);
+  ld_win<K / 2>(tc, cf.vf, wc);
+  ld_win<K>(tf, cf.f, wf);
+  ld_win<K>(ta, cf.kap, wf);
+  stage_win<K / 2>(st, tc, cr, wc);
+  stage_win<K>(st, tf, Fr, wf);
+  stage_win<K>(st, ta, a, wf);
+  sr_up_runs<K, kOpCubic, PREC>(cf, ar, cf.vf, j, cr, Fr, a, w, x);
+}
+
+// u_fwd on the whole window of segment i (inside the domain): the core
+// from patch i's own rebuild, the pad cells on each side from the
+// neighbouring patches' cores (they hold them since pad <= s), passed
+// through the LDS buffer c.eb.
+template <int K, int PREC>
+__device__ __forceinline__ void fwd_window(const Ctx& c, const Args& ar, int64_t i, double (&w)[K], double* st,
+                           Xch& x) {
+  const Ctx cf = forward_ctx(c);
+  const int64_t s = c.seg, S = c.n / s;
+  const int pad = (ar.buffer + 2) & ~1;
+  const int t0 = (int)threadIdx.x * K;  // window cell of w[0]
+  if (i > 0) {
+    // window i-1 cell e + s = window i cell e, e < pad
+    fwd_patch<K, PREC>(cf, ar, i - 1, w, st, x);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int e = t0 + j - (int)s;
+      if (e >= 0 && e < pad) c.eb[e] = w[j];
+    }
+  }
+  if (i + 1 < S) {
+    // window i+1 cell e - s = window i cell e, pad + s <= e < 2 pad + s
+    fwd_patch<K, PREC>(cf, ar, i + 1, w, st, x);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int e = t0 + j;  // = (window i cell) - s
+      if (e >= pad && e < 2 * pad) c.eb[e] = w[j];
+    }
+  }
+  fwd_patch<K, PREC>(cf, ar, i, w, st, x);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int e = t0 + j;
+    if (i > 0 && e < pad) w[j] = c.eb[e];
+    if (i + 1 < S && e >= pad + (int)s && e < 2 * pad + (int)s) w[j] = c.eb[e - (int)s];
+  }
+  __syncthreads();
+}
+
+// Inputs of the SR passes on segment i, as staged runs: the coarse run cr
+// of Vc, the rhs Fr and the coefficient a (kappa; for the adjoint 3 kappa
+// u_fwd^2, with u_fwd read from ufwd or rebuilt into w; Poisson: 0).
+template <int K, int OP, int PREC, bool RB>
+__device__ __forceinline__ void sr_inputs(const Ctx& c, const Args& ar, const double* Vc, int64_t i,
+                                          double (&cr)[K / 2], double (&Fr)[K], double (&a)[K],
+                                          double (&w)[K], double* st, Xch& x) {
+  const int64_t n = c.n, nc = n >> 1, s = c.seg;
+  const int64_t pad = (ar.buffer + 2) & ~1;
+  const int wcount = (int)(s + 2 * pad);
+  const int64_t wlo = i * s - pad;
+  if constexpr (RB) fwd_window<K, PREC>(c, ar, i, w, st, x);
+  double tf[K], ta[K], tw[K], tc[K / 2];
+  const Win wf = make_win(wlo, wcount, n);
+  const Win wc = make_win(wlo >> 1, (wcount + 1) / 2 + 2, nc);
+  ld_win<K / 2>(tc, Vc, wc);
+  ld_win<K>(tf, c.f, wf);
+  if constexpr (OP != kOpPoisson) {
+    ld_win<K>(ta, c.kap, wf);
+    if (c.uf) ld_win<K>(tw, c.uf, wf);
+  }
+  stage_win<K / 2>(st, tc, cr, wc);
+  stage_win<K>(st, tf, Fr, wf);
+  if constexpr (OP != kOpPoisson) {
+    if (c.uf) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) ta[k] = (3.0 * ta[k]) * (tw[k] * tw[k]);
+    }
+    stage_win<K>(st, ta, a, wf);
+    if constexpr (RB) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) a[j] = (3.0 * a[j]) * (w[j] * w[j]);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < K; ++j) a[j] = 0.0;
+  }
+}
+
 // SR down pass (Fig. 3 at the finest level, per segment): ubar = Pi V^{M-1}
 // on the extended patch, nu1 sweeps with the exterior frozen, I^ of the core
 // to Uh and (reaction operators) the core's coarse rhs to Q^{M-1}.
-template <int K, int OP, int PREC>
-__device__ void sr_down(const Ctx& c, const Args& ar, double* st, Xch& x) {
-  const int64_t n = c.n, nc = n >> 1, s = c.seg, S = n / s;
+template <int K, int OP, int PREC, bool RB>
+__device__ __forceinline__ void sr_down(const Ctx& c, const Args& ar, double* st, Xch& x) {
+  const int64_t n = c.n, s = c.seg, S = n / s;
   const int64_t pad = (ar.buffer + 2) & ~1;
-  const int wcount = (int)(s + 2 * pad);
   const double* Vc = c.V + c.off(c.M - 1);
   double* Qo = (OP != kOpPoisson) ? c.Q + c.off(c.M - 1) : nullptr;
   for (int64_t i = c.member; i < S; i += c.G) {
     const int64_t wlo = i * s - pad;
     const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
-    double u[K], Fr[K], a[K], cr[K / 2];
-    double tf[K], ta[K], tw[K], tc[K / 2];
-    const Win wf = make_win(wlo, wcount, n);
-    const Win wc = make_win(wlo >> 1, (wcount + 1) / 2 + 2, nc);
-    ld_win<K / 2>(tc, Vc, wc);
-    ld_win<K>(tf, c.f, wf);
-    if constexpr (OP != kOpPoisson) {
-      ld_win<K>(ta, c.kap, wf);
-      if (c.uf) ld_win<K>(tw, c.uf, wf);
-    }
-    stage_win<K / 2>(st, tc, cr, wc);
-    stage_win<K>(st, tf, Fr, wf);
-    if constexpr (OP != kOpPoisson) {
-      if (c.uf) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) ta[k] = (3.0 * ta[k]) * (tw[k] * tw[k]);
-      }
-      stage_win<K>(st, ta, a, wf);
-    }
-    else {
-#pragma unroll
-      for (int j = 0; j < K; ++j) a[j] = 0.0;
-    }
+    double u[K], Fr[K], a[K], cr[K / 2], w[K];
+    sr_inputs<K, OP, PREC, RB>(c, ar, Vc, i, cr, Fr, a, w, st, x);
     interp_from_run<K>(u, cr, g0, n, Vc, c.gL, c.gR, x);
     const int64_t lo = max(i * s - ar.buffer, (int64_t)0), hi = min((i + 1) * s + ar.buffer, n);
     const SweepGeom sg = sweep_geom(g0, K, lo, hi, n, c.gL, c.gR);
@@ -597,62 +737,28 @@ __device__ void sr_down(const Ctx& c, const Args& ar, double* st, Xch& x) {
   __syncthreads();
 }
 
-// SR up pass (Eq. 5, Fig. 5, per segment): ubar = Pi V^{M-1}, nu2 x
-// [Kaczmarz projection of the patch's full pairs onto I^ ubar = V^{M-1}, one
-// sweep], core to the output.  For the adjoint the output is lambda
-// (grad_f) and grad_kappa = -u_fwd^3 lambda.
-template <int K, int OP, int PREC>
-__device__ void sr_up(const Ctx& c, const Args& ar, double* st, Xch& x) {
-  const int64_t n = c.n, nc = n >> 1, s = c.seg, S = n / s;
+// SR up pass (Eq. 5, Fig. 5, per segment), core to the output.  V^{M-1} is
+// read from the kept array when the forward keeps it.  For the adjoint the
+// output is lambda (grad_f) and grad_kappa = -u_fwd^3 lambda.
+template <int K, int OP, int PREC, bool RB>
+__device__ __forceinline__ void sr_up(const Ctx& c, const Args& ar, double* st, Xch& x) {
+  const int64_t n = c.n, s = c.seg, S = n / s;
   const int64_t pad = (ar.buffer + 2) & ~1;
   const int wcount = (int)(s + 2 * pad);
-  const double* Vc = c.V + c.off(c.M - 1);
+  const double* Vc = c.vk ? c.vk : c.V + c.off(c.M - 1);
   for (int64_t i = c.member; i < S; i += c.G) {
     const int64_t wlo = i * s - pad;
-    const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
-    double u[K], Fr[K], a[K], cr[K / 2];
-    double tf[K], ta[K], tw[K], tc[K / 2];
-    const Win wf = make_win(wlo, wcount, n);
-    const Win wc = make_win(wlo >> 1, (wcount + 1) / 2 + 2, nc);
-    ld_win<K / 2>(tc, Vc, wc);
-    ld_win<K>(tf, c.f, wf);
-    if constexpr (OP != kOpPoisson) {
-      ld_win<K>(ta, c.kap, wf);
-      if (c.uf) ld_win<K>(tw, c.uf, wf);
-    }
-    stage_win<K / 2>(st, tc, cr, wc);
-    stage_win<K>(st, tf, Fr, wf);
-    if constexpr (OP != kOpPoisson) {
-      if (c.uf) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) ta[k] = (3.0 * ta[k]) * (tw[k] * tw[k]);
-      }
-      stage_win<K>(st, ta, a, wf);
-    }
-    else {
-#pragma unroll
-      for (int j = 0; j < K; ++j) a[j] = 0.0;
-    }
-    interp_from_run<K>(u, cr, g0, n, Vc, c.gL, c.gR, x);
-    const int64_t lo = max(i * s - ar.buffer, (int64_t)0), hi = min((i + 1) * s + ar.buffer, n);
-    const SweepGeom sg = sweep_geom(g0, K, lo, hi, n, c.gL, c.gR);
-    for (int it = 0; it < ar.nu2; ++it) {
-#pragma unroll
-      for (int p = 0; p < K / 2; ++p) {
-        const int64_t g = g0 + 2 * p;
-        if (g >= lo && g + 1 < hi) {
-          const double r = cr[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
-          u[2 * p] = u[2 * p] + r;
-          u[2 * p + 1] = u[2 * p + 1] + r;
-        }
-      }
-      smooth<K, OP, PREC>(u, Fr, a, sg, 1, x);
-    }
+    double u[K], Fr[K], a[K], cr[K / 2], w[K];
+    sr_inputs<K, OP, PREC, RB>(c, ar, Vc, i, cr, Fr, a, w, st, x);
+    sr_up_runs<K, OP, PREC>(c, ar, Vc, i, cr, Fr, a, u, x);
     if (c.uo) store_win<K>(st, u, c.uo, wlo, i * s, (i + 1) * s);
     if (c.gk) {
-      double tw2[K], w[K];
-      ld_win<K>(tw2, c.uf, wf);
-      stage_win<K>(st, tw2, w, wf);
+      if constexpr (!RB) {
+        const Win wf = make_win(wlo, wcount, n);
+        double tw2[K];
+        ld_win<K>(tw2, c.uf, wf);
+        stage_win<K>(st, tw2, w, wf);
+      }
 #pragma unroll
       for (int j = 0; j < K; ++j) w[j] = -(((w[j] * w[j]) * w[j]) * u[j]);
       store_win<K>(st, w, c.gk, wlo, i * s, (i + 1) * s);
@@ -661,10 +767,39 @@ __device__ void sr_up(const Ctx& c, const Args& ar, double* st, Xch& x) {
   __syncthreads();
 }
 
+// Adjoint without u_fwd: A^{M-1} = I^ (3 kappa u_fwd^2) on each segment's
+// core, u_fwd rebuilt by the forward's SR up pass of that segment (its core
+// is exact, and the pairs of the core are all the level-(M-1) cells it
+// covers).
+template <int K, int PREC>
+__device__ __forceinline__ void coef_top(const Ctx& c, const Args& ar, double* st, Xch& x) {
+  const int64_t n = c.n, s = c.seg, S = n / s;
+  const int64_t pad = (ar.buffer + 2) & ~1;
+  const int wcount = (int)(s + 2 * pad);
+  const Ctx cf = forward_ctx(c);
+  double* Ac = c.A + c.off(c.M - 1);
+  for (int64_t i = c.member; i < S; i += c.G) {
+    const int64_t wlo = i * s - pad;
+    double w[K], kr[K], ta[K], ac[K / 2];
+    fwd_patch<K, PREC>(cf, ar, i, w, st, x);
+    const Win wf = make_win(wlo, wcount, n);
+    ld_win<K>(ta, c.kap, wf);
+    stage_win<K>(st, ta, kr, wf);
+#pragma unroll
+    for (int p = 0; p < K / 2; ++p) {
+      const double a0 = (3.0 * kr[2 * p]) * (w[2 * p] * w[2 * p]);
+      const double a1 = (3.0 * kr[2 * p + 1]) * (w[2 * p + 1] * w[2 * p + 1]);
+      ac[p] = (a0 + a1) * 0.5;
+    }
+    store_win<K / 2>(st, ac, Ac, wlo >> 1, (i * s) >> 1, ((i + 1) * s) >> 1);
+  }
+  __syncthreads();
+}
+
 // Forcing of level l: R^l = I R^{l+1}, A^l = I^ A^{l+1} (R^M = f, A^M = the
 // fine coefficient), cells J = first*T + tid, stepping by stride*T.
 template <int OP>
-__device__ void forcing_level(const Ctx& c, int l, int first, int stride) {
+__device__ __forceinline__ void forcing_level(const Ctx& c, int l, int first, int stride) {
   const int T = blockDim.x;
   const int64_t nf = c.nl(l + 1), ncl = c.nl(l);
   const bool top = (l + 1 == c.M);
@@ -678,9 +813,11 @@ __device__ void forcing_level(const Ctx& c, int l, int first, int stride) {
     const double rp = (2 * J + 2 < nf) ? Ff[2 * J + 2] : -f1;
     Rc[J] = ((rm + rp) + 3.0 * (f0 + f1)) * 0.125;
     if constexpr (OP != kOpPoisson) {
-      const double a0 = top ? c.coef_fine(2 * J) : Af[2 * J];
-      const double a1 = top ? c.coef_fine(2 * J + 1) : Af[2 * J + 1];
-      Ac[J] = (a0 + a1) * 0.5;
+      if (!(top && c.vf)) {  // rebuilt u_fwd: coef_top writes A^{M-1}
+        const double a0 = top ? c.coef_fine(2 * J) : Af[2 * J];
+        const double a1 = top ? c.coef_fine(2 * J + 1) : Af[2 * J + 1];
+        Ac[J] = (a0 + a1) * 0.5;
+      }
     }
   }
   __syncthreads();
@@ -691,7 +828,7 @@ __device__ void forcing_level(const Ctx& c, int l, int first, int stride) {
 // barrier are released at agent scope and acquired after it.  The wait is
 // bounded; on expiry the status flag is set and false is returned (the
 // caller abandons the problem, so every wave still reaches its exit).
-__device__ bool group_sync(const Ctx& c) {
+__device__ __forceinline__ bool group_sync(const Ctx& c) {
   if (c.G == 1) {
     __syncthreads();
     return true;
@@ -737,7 +874,7 @@ __device__ bool group_sync(const Ctx& c) {
 // timeout.
 struct Phases {
   bool started = false, prev_solo = false, alive = true;
-  __device__ bool begin(const Ctx& c, bool solo) {
+  __device__ __forceinline__ bool begin(const Ctx& c, bool solo) {
     if (!alive) return false;
     if (c.G > 1 && started && !(prev_solo && solo)) alive = group_sync(c);
     started = true;
@@ -767,7 +904,7 @@ __device__ __forceinline__ void wg_max2(double& a, double& b, double* red) {
 // U^1) or kDirect (Uh).  F and A: rhs and coefficient (fine arrays when the
 // problem has one level).
 template <int OP>
-__device__ void coarse_visit(const Ctx& c, int src_kind, const double* src, const double* F,
+__device__ __forceinline__ void coarse_visit(const Ctx& c, int src_kind, const double* src, const double* F,
                              const double* A, bool fine, double* out, double* lds, double* red) {
   const int T = blockDim.x;
   const int64_t n = c.n0;
@@ -844,8 +981,8 @@ __device__ void coarse_visit(const Ctx& c, int src_kind, const double* src, cons
 
 // The whole FMG-FAS-SR iteration of one problem (by the group's member
 // c.member; levels of at most one window are run by member 0 alone).
-template <int K, int OP, int PREC>
-__device__ void solve_problem(const Ctx& c, const Args& ar, double* st, Xch& x, double* red) {
+template <int K, int OP, int PREC, bool RB>
+__device__ __forceinline__ void solve_problem(const Ctx& c, const Args& ar, double* st, Xch& x, double* red) {
   const int M = c.M;
   const int64_t W = (int64_t)blockDim.x * K;
   Phases ph;
@@ -853,17 +990,32 @@ __device__ void solve_problem(const Ctx& c, const Args& ar, double* st, Xch& x, 
     // one level: the exact (Newton) solve on the fine grid
     if (!ph.begin(c, true)) return;
     double* out = c.uo ? c.uo : c.U;
-    coarse_visit<OP>(c, kZero, nullptr, c.f, nullptr, true, out, st, red);
-    if (c.gk) {
-      for (int64_t i = threadIdx.x; i < c.n; i += blockDim.x) {
-        const double w = c.uf[i];
-        c.gk[i] = -(((w * w) * w) * out[i]);
+    Ctx ca = c;
+    if constexpr (RB) {
+      {
+        // adjoint without u_fwd: the forward's exact solve again, into the
+        // second half of the workspace slab
+        double* uw = c.U + lvl_size(c.n0, 0);
+        const Ctx cf = forward_ctx(c);
+        coarse_visit<kOpCubic>(cf, kZero, nullptr, cf.f, nullptr, true, uw, st, red);
+        ca.uf = uw;
+      }
+    }
+    coarse_visit<OP>(ca, kZero, nullptr, ca.f, nullptr, true, out, st, red);
+    if (ca.gk) {
+      for (int64_t i = threadIdx.x; i < ca.n; i += blockDim.x) {
+        const double w = ca.uf[i];
+        ca.gk[i] = -(((w * w) * w) * out[i]);
       }
     }
     __syncthreads();
     return;
   }
   for (int l = M - 1; l >= 0; --l) {
+    if constexpr (RB) {
+      // adjoint without u_fwd: A^{M-1} from the rebuilt u_fwd, per segment
+      if (l == M - 1 && ph.begin(c, false)) coef_top<K, PREC>(c, ar, st, x);
+    }
     const bool solo = c.nl(l) <= W;
     if (ph.begin(c, solo)) forcing_level<OP>(c, l, solo ? 0 : c.member, solo ? 1 : c.G);
   }
@@ -874,7 +1026,7 @@ __device__ void solve_problem(const Ctx& c, const Args& ar, double* st, Xch& x, 
     const bool sr = (t == M);
     int top;
     if (sr) {
-      if (ph.begin(c, false)) sr_down<K, OP, PREC>(c, ar, st, x);
+      if (ph.begin(c, false)) sr_down<K, OP, PREC, RB>(c, ar, st, x);
       top = M - 1;
     } else {
       top = t;
@@ -894,22 +1046,27 @@ __device__ void solve_problem(const Ctx& c, const Args& ar, double* st, Xch& x, 
       if (top >= 1) { sk = kRestrict; src = c.U + c.off(1); }
       else { sk = kDirect; src = c.Uh; }   // M == 1: level 0 is the top
       const double* F = (top == 0 && !sr) ? c.R : Fsrc;
-      if (ph.begin(c, true)) coarse_visit<OP>(c, sk, src, F, c.A, false, c.V, st, red);
+      // the last step's V^{M-1} (level 0 when M == 1) to the kept array
+      double* out = (sr && top == 0 && c.vk) ? c.vk : c.V;
+      if (ph.begin(c, true)) coarse_visit<OP>(c, sk, src, F, c.A, false, out, st, red);
     }
     for (int l = 1; l <= top; ++l) {
       const double* F = (l == top && !sr) ? c.R + c.off(l) : Fsrc + c.off(l);
-      if (ph.begin(c, c.nl(l) <= W)) up_visit<K, OP, PREC>(c, ar, l, F, st, x);
+      double* Vout = (sr && l == top) ? c.vk : nullptr;
+      if (ph.begin(c, c.nl(l) <= W)) up_visit<K, OP, PREC>(c, ar, l, F, st, x, Vout);
     }
-    if (sr && ph.begin(c, false)) sr_up<K, OP, PREC>(c, ar, st, x);
+    // compression only (a kept V^{M-1} and no fine output): no SR up pass
+    if (sr && (c.uo || c.gk) && ph.begin(c, false)) sr_up<K, OP, PREC, RB>(c, ar, st, x);
   }
 }
 
-template <int K, int OP, int PREC>
+// RB: the adjoint that rebuilds u_fwd (OP = linear with c = 3 kappa u_fwd^2).
+template <int K, int OP, int PREC, bool RB>
 __global__ __launch_bounds__(kMaxThreads) void k_batched(Args a) {
   extern __shared__ double lds[];
   double* st = lds;                                  // a.region >= T (K + 1) doubles
   double* red = lds + a.region;                      // 32 doubles
-  Xch x{red + 32, 0, 2 * (int)blockDim.x};  // 4 T doubles
+  Xch x{red + 32, 0, 2 * (int)blockDim.x};  // 4 T doubles, then 2 kMaxPad (Ctx::eb)
   __shared__ int next;
   for (;;) {
     // slot -> (queue position, member): the G members of a problem are
@@ -923,9 +1080,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_batched(Args a) {
     const int qp = a.order[p];
     const Prob pr = a.probs[qp];
     Ctx c = make_ctx(pr, a);
+    c.eb = red + 32 + 4 * (int)blockDim.x;
     c.member = slot % a.group;
     c.bar = a.bars + 2 * (int64_t)qp;
-    solve_problem<K, OP, PREC>(c, a, st, x, red);
+    solve_problem<K, OP, PREC, RB>(c, a, st, x, red);
   }
 }
 
@@ -952,6 +1110,7 @@ struct fmgsr_batch_s {
   int32_t batch = 0;
   int op = 0, prec = 0, nu1 = 2, nu2 = 1, buffer = 0, halo = 0;
   int K = 8, T = 256, grid = 0, group = 1;
+  int grid_rb = 0;                // persistent grid of the adjoint that rebuilds u_fwd
   int region = 0;                 // doubles of the LDS stage / coarse region
   size_t lds = 0;
   int n0max = 1;
@@ -966,6 +1125,8 @@ struct fmgsr_batch_s {
   int64_t ws_doubles = 0;
   double algo_bytes = 0.0;          // algorithmic bytes of one solve (profiling)
   double algo_bytes_adjoint = 0.0;  // ... of one adjoint solve
+  double algo_bytes_keep = 0.0;     // ... of a forward solve that only keeps V^{M-1}
+  double algo_bytes_adjoint_rebuild = 0.0;  // ... of an adjoint that rebuilds u_fwd
 };
 
 namespace fmgsr {
@@ -986,12 +1147,18 @@ int64_t pad_of(int buffer) { return (buffer + 2) & ~1; }
 // array it writes once (8 bytes per cell).  `reaction`: coefficient arrays
 // and coarse right-hand sides exist; `adjoint`: the fine coefficient is
 // formed from kappa and u_fwd and grad_kappa is written too.
-double model_bytes(int64_t n, int64_t n0, int M, bool reaction, bool adjoint) {
+// `keep_only`: the SR up pass is skipped (a forward that only keeps
+// V^{M-1}); `rebuild`: an adjoint that rebuilds u_fwd instead of reading it
+// (seven forward SR up passes over rhs, kappa and V^{M-1}: one per segment
+// for A^{M-1}, three per segment in each SR pass).
+double model_bytes(int64_t n, int64_t n0, int M, bool reaction, bool adjoint,
+                   bool keep_only = false, bool rebuild = false) {
   const double r = reaction ? 1.0 : 0.0;
-  const double fine_coef = reaction ? (adjoint ? 2.0 : 1.0) : 0.0;  // kappa (+ u_fwd)
+  const double fine_coef = reaction ? ((adjoint && !rebuild) ? 2.0 : 1.0) : 0.0;  // kappa (+ u_fwd)
   auto nl = [&](int l) { return (double)(n0 << l); };
   double b = 0.0;
-  if (M == 0) return 8.0 * (double)n * (2.0 + fine_coef + (adjoint ? 1.0 : 0.0));
+  if (M == 0)
+    return 8.0 * (double)n * (2.0 + fine_coef + (adjoint ? 1.0 : 0.0) + (rebuild ? 3.0 : 0.0));
   // forcing: level l from level l+1
   for (int l = M - 1; l >= 0; --l) {
     const double nf = nl(l + 1);
@@ -1011,7 +1178,8 @@ double model_bytes(int64_t n, int64_t n0, int M, bool reaction, bool adjoint) {
   b += 8.0 * (0.5 * N + N * (1.0 + fine_coef) + 0.5 * N + 0.5 * N * r);  // SR down
   for (int l = M - 1; l >= 1; --l) b += down(l, l == M - 1 ? 2 : 1);
   for (int l = 1; l <= M - 1; ++l) b += up(l);
-  b += 8.0 * (0.5 * N + N * (1.0 + fine_coef) + N + (adjoint ? N : 0.0));  // SR up
+  if (!keep_only) b += 8.0 * (0.5 * N + N * (1.0 + fine_coef) + N + (adjoint ? N : 0.0));  // SR up
+  if (rebuild) b += 7.0 * 8.0 * (0.5 * N + 2.0 * N);
   return b;
 }
 
@@ -1030,16 +1198,20 @@ int64_t auto_core(int64_t n, int M, int64_t n0, int buffer, int64_t W, int halve
   return best;
 }
 
+// op: kOp*, or kOpRebuild for the adjoint that rebuilds u_fwd.
+constexpr int kOpRebuild = 3;
 template <int K>
 const void* kernel_ptr_k(int op, int prec) {
   if (prec == kF64) {
-    if (op == kOpCubic) return (const void*)k_batched<K, kOpCubic, kF64>;
-    if (op == kOpLinear) return (const void*)k_batched<K, kOpLinear, kF64>;
-    return (const void*)k_batched<K, kOpPoisson, kF64>;
+    if (op == kOpRebuild) return (const void*)k_batched<K, kOpLinear, kF64, true>;
+    if (op == kOpCubic) return (const void*)k_batched<K, kOpCubic, kF64, false>;
+    if (op == kOpLinear) return (const void*)k_batched<K, kOpLinear, kF64, false>;
+    return (const void*)k_batched<K, kOpPoisson, kF64, false>;
   }
-  if (op == kOpCubic) return (const void*)k_batched<K, kOpCubic, kF32>;
-  if (op == kOpLinear) return (const void*)k_batched<K, kOpLinear, kF32>;
-  return (const void*)k_batched<K, kOpPoisson, kF32>;
+  if (op == kOpRebuild) return (const void*)k_batched<K, kOpLinear, kF32, true>;
+  if (op == kOpCubic) return (const void*)k_batched<K, kOpCubic, kF32, false>;
+  if (op == kOpLinear) return (const void*)k_batched<K, kOpLinear, kF32, false>;
+  return (const void*)k_batched<K, kOpPoisson, kF32, false>;
 }
 
 const void* kernel_ptr(int op, int prec, int K) {
@@ -1088,8 +1260,10 @@ fmgsr_status build_plan(fmgsr_batch_s* b, int T, int K, int halve, int group_cap
     } else {
       p.seg = 0;
     }
+    p.coff = p.off / 2;
     p.ws = ws;
-    ws += std::max<int64_t>(slab_doubles(p.n0, p.M), lvl_size(p.n0, 0));
+    // one level: room for the result and a rebuilt forward solution
+    ws += std::max<int64_t>(slab_doubles(p.n0, p.M), 2 * lvl_size(p.n0, 0));
     bytes += model_bytes(p.n, p.n0, p.M, b->op != kOpPoisson, false);
   }
   if (b->auto_segments)
@@ -1099,7 +1273,7 @@ fmgsr_status build_plan(fmgsr_batch_s* b, int T, int K, int halve, int group_cap
   b->T = T;
   b->K = K;
   b->region = std::max(T * (K + 1), 11 * b->n0max);
-  b->lds = sizeof(double) * ((size_t)b->region + 32 + 4 * (size_t)T);
+  b->lds = sizeof(double) * ((size_t)b->region + 32 + 4 * (size_t)T + 2 * kMaxPad);
   if (b->lds > 160 * 1024) return FMGSR_EINVAL;
   size_t lds_limit = 0;  // the device's opt-in limit per workgroup
   if (fmgsr::device_lds_limit(&lds_limit) != hipSuccess) {
@@ -1123,10 +1297,30 @@ fmgsr_status build_plan(fmgsr_batch_s* b, int T, int K, int halve, int group_cap
   const int64_t cap = (int64_t)per_cu * cus;
   b->group = (b->batch < cap) ? (int)std::min<int64_t>(group_cap, cap / b->batch) : 1;
   b->grid = (int)std::min<int64_t>((int64_t)b->batch * b->group, cap);
+  // the adjoint that rebuilds u_fwd runs its own kernel: its persistent grid
+  // is what of this one stays resident (at least a group, for the barriers)
+  b->grid_rb = b->grid;
+  if (b->op == kOpCubic) {
+    const void* kr = kernel_ptr(kOpRebuild, b->prec, K);
+    int per_cu_rb = 0;
+    if (hipFuncSetAttribute(kr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_rb, kr, T, b->lds) != hipSuccess) {
+      (void)hipGetLastError();
+      return FMGSR_EDEVICE;
+    }
+    const int64_t cap_rb = (int64_t)std::max(per_cu_rb, 1) * cus;
+    b->grid_rb = (int)std::max<int64_t>(std::min<int64_t>(b->grid, cap_rb), b->group);
+  }
   b->algo_bytes = bytes;
-  double adj = 0.0;
-  for (const Prob& p : pr) adj += model_bytes(p.n, p.n0, p.M, true, true);
+  double adj = 0.0, adj_rb = 0.0, keep = 0.0;
+  for (const Prob& p : pr) {
+    adj += model_bytes(p.n, p.n0, p.M, true, true);
+    adj_rb += model_bytes(p.n, p.n0, p.M, true, true, false, true);
+    keep += model_bytes(p.n, p.n0, p.M, b->op != kOpPoisson, false, true);
+  }
   b->algo_bytes_adjoint = adj;
+  b->algo_bytes_adjoint_rebuild = adj_rb;
+  b->algo_bytes_keep = keep;
 
   if (!b->d_probs) {
     if (hipMalloc((void**)&b->d_probs, sizeof(Prob) * b->batch) != hipSuccess ||
@@ -1158,9 +1352,30 @@ fmgsr_status build_plan(fmgsr_batch_s* b, int T, int K, int halve, int group_cap
   return FMGSR_OK;
 }
 
+// An adjoint that rebuilds u_fwd takes each window's pad cells from the
+// neighbouring segments' cores: every segment core must be at least the pad.
+bool rebuild_fits(const fmgsr_batch_s* b) {
+  const int64_t pad = pad_of(b->buffer);
+  for (int j = 0; j < b->batch; ++j)
+    if (b->levels_v[j] > 1 && b->n[j] / b->segs[j] < pad) return false;
+  return true;
+}
+
+// Extra inputs and outputs of an execution: the kept level-(M-1) solutions
+// (forward: written; adjoint without u_fwd: the forward rhs and them, read).
+struct Keep {
+  double* vkeep = nullptr;
+  const double* ffwd = nullptr;
+  const double* vfwd = nullptr;
+};
+
 fmgsr_status execute(fmgsr_batch_s* b, int op, bool adjoint, const double* f, const double* kappa,
-                     const double* ufwd, double* u, double* gk, hipStream_t s) {
+                     const double* ufwd, double* u, double* gk, hipStream_t s,
+                     const Keep& kp = Keep()) {
   Args a;
+  a.vkeep = kp.vkeep;
+  a.ffwd = kp.ffwd;
+  a.vfwd = kp.vfwd;
   a.probs = b->d_probs;
   a.order = b->d_order;
   a.batch = b->batch;
@@ -1181,19 +1396,21 @@ fmgsr_status execute(fmgsr_batch_s* b, int op, bool adjoint, const double* f, co
   a.status = b->d_queue + 1;
   a.bars = b->d_queue + 2;
   if (op != b->op) {
-    const void* kp = kernel_ptr(op, b->prec, b->K);
-    if (hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds) != hipSuccess) {
+    const void* kf = kernel_ptr(op, b->prec, b->K);
+    if (hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds) != hipSuccess) {
       (void)hipGetLastError();
       return FMGSR_EDEVICE;
     }
   }
-  ProfScope ps(adjoint ? "k_batched_adjoint" : "k_batched",
-               adjoint ? b->algo_bytes_adjoint : b->algo_bytes, s);
+  const double bytes = !adjoint ? (u ? b->algo_bytes : b->algo_bytes_keep)
+                                 : (kp.vfwd ? b->algo_bytes_adjoint_rebuild : b->algo_bytes_adjoint);
+  ProfScope ps(adjoint ? "k_batched_adjoint" : "k_batched", bytes, s);
   const int64_t nbars = 2 * (int64_t)b->batch;
   hipLaunchKernelGGL(k_queue_reset, dim3((unsigned)((nbars + 255) / 256)), dim3(256), 0, s,
                      b->d_queue, b->d_queue + 2, nbars);
   if (hipGetLastError() != hipSuccess) return FMGSR_EDEVICE;
-  if (launch(a, op, b->prec, b->K, b->grid, b->T, b->lds, s) != hipSuccess) return FMGSR_EDEVICE;
+  const int grid = (op == kOpRebuild) ? b->grid_rb : b->grid;
+  if (launch(a, op, b->prec, b->K, grid, b->T, b->lds, s) != hipSuccess) return FMGSR_EDEVICE;
   return FMGSR_OK;
 }
 
@@ -1312,6 +1529,45 @@ fmgsr_status fmgsr_batch_adjoint(fmgsr_batch b, const double* kappa_packed,
     return FMGSR_EINVAL;
   return bt::execute(b, bt::kOpLinear, true, dJdu_packed, kappa_packed, u_fwd_packed,
                      grad_f_packed, grad_kappa_packed, (hipStream_t)hip_stream);
+}
+
+fmgsr_status fmgsr_batch_solve_keep(fmgsr_batch b, const double* f_packed,
+                                    const double* kappa_packed, double* u_packed,
+                                    double* coarse_packed, void* hip_stream) {
+  if (!b || !is_device_ptr(f_packed) || !is_device_ptr(coarse_packed)) return FMGSR_EINVAL;
+  if (u_packed && !is_device_ptr(u_packed)) return FMGSR_EINVAL;
+  if (b->op == FMGSR_OP_POISSON ? kappa_packed != nullptr : !is_device_ptr(kappa_packed))
+    return FMGSR_EINVAL;
+  if ((const void*)f_packed == (const void*)u_packed ||
+      (const void*)f_packed == (const void*)coarse_packed ||
+      (const void*)u_packed == (const void*)coarse_packed)
+    return FMGSR_EINVAL;
+  bt::Keep kp;
+  kp.vkeep = coarse_packed;
+  return bt::execute(b, b->op, false, f_packed, kappa_packed, nullptr, u_packed, nullptr,
+                     (hipStream_t)hip_stream, kp);
+}
+
+fmgsr_status fmgsr_batch_adjoint_compressed(fmgsr_batch b, const double* kappa_packed,
+                                            const double* f_fwd_packed,
+                                            const double* coarse_fwd_packed,
+                                            const double* dJdu_packed, double* grad_f_packed,
+                                            double* grad_kappa_packed, void* hip_stream) {
+  if (!b) return FMGSR_EINVAL;
+  if (b->op != FMGSR_OP_CUBIC_REACTION) return FMGSR_ENOTSUP;
+  if (!is_device_ptr(kappa_packed) || !is_device_ptr(f_fwd_packed) ||
+      !is_device_ptr(coarse_fwd_packed) || !is_device_ptr(dJdu_packed))
+    return FMGSR_EINVAL;
+  if (!grad_f_packed && !grad_kappa_packed) return FMGSR_EINVAL;
+  if ((grad_f_packed && !is_device_ptr(grad_f_packed)) ||
+      (grad_kappa_packed && !is_device_ptr(grad_kappa_packed)))
+    return FMGSR_EINVAL;
+  if (!bt::rebuild_fits(b)) return FMGSR_ENOTSUP;
+  bt::Keep kp;
+  kp.ffwd = f_fwd_packed;
+  kp.vfwd = coarse_fwd_packed;
+  return bt::execute(b, bt::kOpRebuild, true, dJdu_packed, kappa_packed, nullptr, grad_f_packed,
+                     grad_kappa_packed, (hipStream_t)hip_stream, kp);
 }
 
 fmgsr_status fmgsr_batch_autotune(fmgsr_batch b, const double* f_packed, const double* kappa_packed,
@@ -1435,16 +1691,31 @@ fmgsr_status fmgsr_adjoint(const fmgsr_operator* op, const double* f, double g_l
   if (st != FMGSR_OK) return st;
   hipStream_t s = (hipStream_t)hip_stream;
   double* tmp = nullptr;
-  if (!u_fwd) {
-    if (hipMalloc((void**)&tmp, sizeof(double) * (size_t)n) != hipSuccess) {
+  if (!u_fwd && levels > 1 && bt::rebuild_fits(b)) {
+    // compressed: keep the forward's level-(M-1) solution only (n/2
+    // doubles) and rebuild u_fwd inside the adjoint
+    if (hipMalloc((void**)&tmp, sizeof(double) * (size_t)(n / 2)) != hipSuccess) {
       (void)hipGetLastError();
       fmgsr_batch_destroy(b);
       return FMGSR_ENOMEM;
     }
-    st = fmgsr_batch_solve(b, f, op->kappa, tmp, hip_stream);
-    u_fwd = tmp;
+    st = fmgsr_batch_solve_keep(b, f, op->kappa, nullptr, tmp, hip_stream);
+    if (st == FMGSR_OK)
+      st = fmgsr_batch_adjoint_compressed(b, op->kappa, f, tmp, dJ_du, grad_f, grad_kappa,
+                                          hip_stream);
+  } else {
+    if (!u_fwd) {
+      if (hipMalloc((void**)&tmp, sizeof(double) * (size_t)n) != hipSuccess) {
+        (void)hipGetLastError();
+        fmgsr_batch_destroy(b);
+        return FMGSR_ENOMEM;
+      }
+      st = fmgsr_batch_solve(b, f, op->kappa, tmp, hip_stream);
+      u_fwd = tmp;
+    }
+    if (st == FMGSR_OK)
+      st = fmgsr_batch_adjoint(b, op->kappa, u_fwd, dJ_du, grad_f, grad_kappa, hip_stream);
   }
-  if (st == FMGSR_OK) st = fmgsr_batch_adjoint(b, op->kappa, u_fwd, dJ_du, grad_f, grad_kappa, hip_stream);
   if (hipStreamSynchronize(s) != hipSuccess) {
     (void)hipGetLastError();
     if (st == FMGSR_OK) st = FMGSR_EDEVICE;

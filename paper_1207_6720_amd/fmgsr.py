@@ -100,6 +100,8 @@ def lib():
                                          ctypes.POINTER(Options), ctypes.POINTER(vp)]
         L.fmgsr_batch_solve.argtypes = [vp, vp, vp, vp, vp]
         L.fmgsr_batch_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.fmgsr_batch_solve_keep.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.fmgsr_batch_adjoint_compressed.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.fmgsr_batch_autotune.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
         L.fmgsr_batch_query.argtypes = [vp, ctypes.POINTER(BatchShape), vp]
         L.fmgsr_batch_destroy.argtypes = [vp]
@@ -109,6 +111,7 @@ def lib():
                                     ctypes.c_double, i64, i32, i64, i32, ctypes.POINTER(Options),
                                     vp, vp, vp, vp, vp]
         for name in ("fmgsr_batch_create", "fmgsr_batch_solve", "fmgsr_batch_adjoint",
+                     "fmgsr_batch_solve_keep", "fmgsr_batch_adjoint_compressed",
                      "fmgsr_batch_autotune", "fmgsr_batch_query", "fmgsr_batch_destroy",
                      "fmgsr_solve_batched", "fmgsr_adjoint"):
             getattr(L, name).restype = ctypes.c_int
@@ -306,6 +309,10 @@ class Batch:
         self.offsets = (np.concatenate([[0], np.cumsum(self.sizes)[:-1]]).astype(np.int64)
                         if offsets is None else np.ascontiguousarray(offsets, dtype=np.int64))
         self.total = int((self.offsets + self.sizes).max())
+        # the kept level-(M-1) solutions: problem j at offsets[j] // 2, n_j / 2 values
+        multi = self.levels > 1
+        self.coarse_total = (int((self.offsets[multi] // 2 + self.sizes[multi] // 2).max())
+                             if multi.any() else 0)
         self.op = op
         seg = None if segments is None else np.ascontiguousarray(segments, dtype=np.int64)
         gh = None if g is None else np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
@@ -349,6 +356,57 @@ class Batch:
         if st != FMGSR_OK:
             raise FmgsrError(st, "fmgsr_batch_solve")
         return out
+
+    def solve_keep(self, f, kappa=None, coarse=None, out=None, write_u=True, stream=None):
+        """(u or None, coarse): the iteration keeping every problem's
+        level-(M-1) solution (fmgsr_batch_solve_keep); write_u=False skips
+        the finest level (compression only)."""
+        _check_vec(f, "f", at_least=self.total)
+        kappa = self._coef(kappa, f.device)
+        if coarse is None:
+            coarse = torch.empty(max(self.coarse_total, 1), dtype=torch.float64, device=f.device)
+        else:
+            _check_vec(coarse, "coarse", at_least=max(self.coarse_total, 1), device=f.device)
+        if write_u:
+            if out is None:
+                out = torch.empty_like(f)
+            else:
+                _check_vec(out, "out", at_least=self.total, device=f.device)
+        else:
+            out = None
+        st = lib().fmgsr_batch_solve_keep(self._h, f.data_ptr(),
+                                          kappa.data_ptr() if kappa is not None else None,
+                                          out.data_ptr() if out is not None else None,
+                                          coarse.data_ptr(), self._stream(stream, f.device))
+        if st != FMGSR_OK:
+            raise FmgsrError(st, "fmgsr_batch_solve_keep")
+        return out, coarse
+
+    def adjoint_compressed(self, kappa, f_fwd, coarse_fwd, dJdu, grad_f=None, grad_kappa=None,
+                           stream=None):
+        """(grad_f, grad_kappa) like ``adjoint``, u_fwd rebuilt from the
+        forward's rhs and kept level (fmgsr_batch_adjoint_compressed)."""
+        if self.op != "cubic":
+            raise ValueError("the adjoint needs a plan made for the cubic operator")
+        _check_vec(dJdu, "dJdu", at_least=self.total)
+        dev = dJdu.device
+        _check_vec(kappa, "kappa", at_least=self.total, device=dev)
+        _check_vec(f_fwd, "f_fwd", at_least=self.total, device=dev)
+        _check_vec(coarse_fwd, "coarse_fwd", at_least=max(self.coarse_total, 1), device=dev)
+        if grad_f is None:
+            grad_f = torch.empty_like(dJdu)
+        else:
+            _check_vec(grad_f, "grad_f", at_least=self.total, device=dev)
+        if grad_kappa is None:
+            grad_kappa = torch.empty_like(dJdu)
+        else:
+            _check_vec(grad_kappa, "grad_kappa", at_least=self.total, device=dev)
+        st = lib().fmgsr_batch_adjoint_compressed(
+            self._h, kappa.data_ptr(), f_fwd.data_ptr(), coarse_fwd.data_ptr(), dJdu.data_ptr(),
+            grad_f.data_ptr(), grad_kappa.data_ptr(), self._stream(stream, dev))
+        if st != FMGSR_OK:
+            raise FmgsrError(st, "fmgsr_batch_adjoint_compressed")
+        return grad_f, grad_kappa
 
     def adjoint(self, kappa, u_fwd, dJdu, grad_f=None, grad_kappa=None, stream=None):
         """(grad_f, grad_kappa) of J with dJ/du = dJdu (fmgsr_batch_adjoint)."""
@@ -428,23 +486,42 @@ def adjoint(f, kappa, dJdu, g=(0.0, 0.0), levels=None, segments=0, buffer=8, nu=
 class CubicSolve(torch.autograd.Function):
     """u = FMG-FAS-SR solution of -u'' + kappa u^3 = f for every problem of a
     batch plan, differentiable in f and kappa: the backward pass runs the
-    library's adjoint (fmgsr_batch_adjoint) on the saved u, i.e. the gradient
-    of the discrete solution map, with lambda from one FMG-SR iteration.
+    library's adjoint, i.e. the gradient of the discrete solution map, with
+    lambda from one FMG-SR iteration.
 
-        u = CubicSolve.apply(f, kappa, plan)"""
+        u = CubicSolve.apply(f, kappa, plan)           # keeps the coarse level
+        u = CubicSolve.apply(f, kappa, plan, "u")      # keeps u
+
+    keep="coarse" (default, Sec. 2.4): the forward keeps its level-(M-1)
+    solution (n/2 values) and the backward rebuilds u_fwd from it and f
+    (fmgsr_batch_adjoint_compressed; more arithmetic, less memory).
+    keep="u": u itself is saved (fmgsr_batch_adjoint).  Both give the same
+    gradients bit for bit."""
 
     @staticmethod
-    def forward(ctx, f, kappa, plan):
-        u = plan.solve(f.detach(), kappa.detach())
-        ctx.save_for_backward(kappa, u)
+    def forward(ctx, f, kappa, plan, keep="coarse"):
+        if keep not in ("coarse", "u"):
+            raise ValueError("keep is 'coarse' or 'u'")
         ctx.plan = plan
+        ctx.keep = keep
+        if keep == "coarse":
+            u, coarse = plan.solve_keep(f.detach(), kappa.detach())
+            ctx.save_for_backward(kappa, f, coarse)
+        else:
+            u = plan.solve(f.detach(), kappa.detach())
+            ctx.save_for_backward(kappa, u)
         return u
 
     @staticmethod
     def backward(ctx, grad_u):
-        kappa, u = ctx.saved_tensors
-        gf, gk = ctx.plan.adjoint(kappa, u, grad_u.contiguous())
-        return gf, gk, None
+        if ctx.keep == "coarse":
+            kappa, f, coarse = ctx.saved_tensors
+            gf, gk = ctx.plan.adjoint_compressed(kappa.detach(), f.detach(), coarse,
+                                                 grad_u.contiguous())
+        else:
+            kappa, u = ctx.saved_tensors
+            gf, gk = ctx.plan.adjoint(kappa, u, grad_u.contiguous())
+        return gf, gk, None, None
 
 
 def profile_enable(kernel_filter=None):
