@@ -80,29 +80,36 @@ def disc_rel_modes(n, k, c):
 
 def traffic_for(workload, kernel, kernel_source_hash):
     """Measured HBM bytes per launch of `kernel` in `workload` from the
-    committed counter summary, if it was taken on the current kernel sources
-    (else None)."""
+    committed counter summary, if it was taken on the current sources of
+    that workload's kernels (else None)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha256") != kernel_source_hash:
+    w = t.get("workloads", {}).get(workload, {})
+    if w.get("source_sha256") != kernel_source_hash:
         return None
-    ent = t.get("workloads", {}).get(workload, {}).get("kernels", {}).get(kernel)
+    ent = w.get("kernels", {}).get(kernel)
     return ent.get("hbm_bytes_per_launch") if ent else None
 
 
-def kernel_source_hash():
-    """sha256 over every HIP source and header of the library."""
+# The HIP sources each family of workloads compiles from.
+KERNEL_SOURCES = {
+    "poisson": ("fmgsr.hip", "fmgsr_kernels.hpp", "fmgsr_device.hpp", "fmgsr_host.hpp"),
+    "batched": ("fmgsr_batched.hip", "fmgsr_device.hpp", "fmgsr_host.hpp"),
+}
+
+
+def kernel_source_hash(family):
+    """sha256 over the HIP sources and headers of one family's kernels."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1207_6720_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode())
-                h.update(fh.read())
+    for name in sorted(KERNEL_SOURCES[family]):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -336,7 +343,7 @@ def main():
                + ("" if args.sr_levels == 1 else f"_sr{args.sr_levels}")
                + ("" if args.tau == "split" else "_literal")
                + ("_functionals" if args.functionals_only else ""))
-    traffic = traffic_for(wl.name + variant, dominant, kernel_source_hash())
+    traffic = traffic_for(wl.name + variant, dominant, kernel_source_hash("poisson"))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": dominant,
@@ -487,7 +494,7 @@ def run_batched(args, dev):
     dom_bytes = dom["algo_bytes"] / dom["launches"]
     achieved = dom_bytes / (dom_launch_ms * 1e-3) / 1e9
     traffic = traffic_for(rb.name + ("" if args.precision == "fp64" else "_" + args.precision),
-                          dominant, kernel_source_hash())
+                          dominant, kernel_source_hash("batched"))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dominant, "algo_bytes_per_launch": dom_bytes,

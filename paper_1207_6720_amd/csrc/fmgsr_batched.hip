@@ -87,6 +87,7 @@ struct Args {
   const double* ffwd;    // adjoint without u_fwd: the forward's packed rhs
   const double* vfwd;    // ... and its kept level-(M-1) solution
   int nu1, nu2, buffer, halo;
+  int halo2;             // halo of the two-level (fused) visits
   int region;            // doubles of the LDS stage / coarse-solve region
   int adjoint;           // 1: homogeneous boundary values (adjoint solve)
   int group;             // workgroups cooperating on one problem (G)
@@ -518,6 +519,30 @@ __device__ __forceinline__ void down_visit(const Ctx& c, const Args& ar, int l, 
 }
 
 // Up visit of stored level l: V^l = U^l + P(V^{l-1} - I^ U^l), nu2 sweeps.
+// Coarse-grid correction (Eq. 4) of a run: u += P(cv - I^ u), homogeneous
+// reflections at the level's ends; g0 = the run's first cell, nc = coarse
+// cells of the level.
+template <int K>
+__device__ __forceinline__ void correct_run(double (&u)[K], const double (&cv)[K / 2], int64_t g0,
+                                            int64_t nc, Xch& x) {
+  double e[K / 2];
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) e[p] = cv[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
+  double el, er;
+  x.swap(e[0], e[K / 2 - 1], el, er);
+  const int64_t J0 = g0 >> 1;
+#pragma unroll
+  for (int p = 0; p < K / 2; ++p) {
+    const int64_t J = J0 + p;
+    double em = (p == 0) ? el : e[p - 1];
+    double ep = (p == K / 2 - 1) ? er : e[p + 1];
+    if (J == 0) em = -e[p];
+    if (J == nc - 1) ep = -e[p];
+    u[2 * p] = u[2 * p] + (3.0 * e[p] + em) * 0.25;
+    u[2 * p + 1] = u[2 * p + 1] + (3.0 * e[p] + ep) * 0.25;
+  }
+}
+
 // Vout: where V^l goes (null: the workspace).
 template <int K, int OP, int PREC>
 __device__ __forceinline__ void up_visit(const Ctx& c, const Args& ar, int l, const double* F, double* st,
@@ -549,23 +574,187 @@ __device__ __forceinline__ void up_visit(const Ctx& c, const Args& ar, int l, co
 #pragma unroll
       for (int j = 0; j < K; ++j) a[j] = 0.0;
     }
-    // coarse-grid correction (Eq. 4) with homogeneous reflections
-    double e[K / 2];
+    correct_run<K>(u, cv, g0, nc, x);
+    const SweepGeom sg = sweep_geom(g0, K, max(wlo, (int64_t)0), min(wlo + tl.wcount, n), n,
+                                    c.gL, c.gR);
+    smooth<K, OP, PREC>(u, Fr, a, sg, ar.nu2, x);
+    store_win<K>(st, u, Vo, wlo, clo, chi);
+  }
+  __syncthreads();
+}
+
+// Full weighting of a run's rhs pairs, I F (the Poisson forcing restriction,
+// same expression and boundary reflections as forcing_level).
+template <int K>
+__device__ __forceinline__ void fw_run(const double (&F)[K], double (&Fc)[K / 2], int64_t g0,
+                                       int64_t nf, Xch& x) {
+  double Fl, Fr;
+  x.swap(F[0], F[K - 1], Fl, Fr);
+  const RunBounds rb = run_bounds(g0, K, 0, nf, nf);
 #pragma unroll
-    for (int p = 0; p < K / 2; ++p) e[p] = cv[p] - (u[2 * p] + u[2 * p + 1]) * 0.5;
-    double el, er;
-    x.swap(e[0], e[K / 2 - 1], el, er);
-    const int64_t J0 = g0 >> 1;
+  for (int p = 0; p < K / 2; ++p) {
+    double fm = (p == 0) ? Fl : F[2 * p - 1];
+    double fp = (p == K / 2 - 1) ? Fr : F[2 * p + 2];
+    if (2 * p == rb.jb0) fm = -F[2 * p];
+    if (2 * p + 1 == rb.jbn) fp = -F[2 * p + 1];
+    Fc[p] = ((fm + fp) + 3.0 * (F[2 * p] + F[2 * p + 1])) * 0.125;
+  }
+}
+
+// Two stored levels per tile visit (vertical fusion): the tiles of level l
+// carry a halo of ar.halo2 cells, enough for both levels' sweeps, so the
+// level-(l-1) half of every window is exact on its core.  Each fused value
+// is formed by the same expression as in the one-level visits, so results
+// are bit-for-bit those of two separate visits.
+//
+// Down: level l as down_visit (src, F, A; nu1 sweeps; U^l and Q^{l-1}
+// stored), then level l-1 from registers: its iterate I^ u, its rhs Q^{l-1}
+// (Poisson: I F), its coefficient I^ a; nu1 sweeps; U^{l-1} and Q^{l-2}
+// stored.  Saves reading level l-1's source, rhs and coefficient.
+template <int K, int OP, int PREC>
+__device__ __forceinline__ void down_visit2(const Ctx& c, const Args& ar, int l, int src_kind,
+                                            const double* src, const double* F, double* st,
+                                            Xch& x) {
+  const int64_t n = c.nl(l), n1 = n >> 1;
+  const double* A = c.A + c.off(l);
+  double* Uo = c.U + c.off(l);
+  double* U1 = c.U + c.off(l - 1);
+  double* Qo = (OP != kOpPoisson) ? c.Q + c.off(l - 1) : nullptr;
+  double* Q1 = (OP != kOpPoisson) ? c.Q + c.off(l - 2) : nullptr;
+  const Tiling tl = tiling(n, K, ar.halo2);
+  const int64_t first = (tl.ntiles == 1) ? 0 : c.member, stride = (tl.ntiles == 1) ? 1 : c.G;
+  for (int64_t ti = first; ti < tl.ntiles; ti += stride) {
+    const int64_t clo = ti * tl.core, chi = min(clo + tl.core, n);
+    const int64_t wlo = clo - tl.halo;
+    const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
+    double u[K], Fr[K], a[K];
+    {
+      double tu[K], tf[K], ta[K];
+      double2 tp[K];
+      double tc[K / 2];
+      const Win wf = make_win(wlo, tl.wcount, n);
+      const Win wc = make_win(wlo >> 1, (tl.wcount + 1) / 2 + 2, n >> 1);
+      if (src_kind == kInterp) ld_win<K / 2>(tc, src, wc);
+      else if (src_kind == kRestrict) ld_win_pairs<K>(tp, src, wf);
+      else ld_win<K>(tu, src, wf);
+      ld_win<K>(tf, F, wf);
+      if constexpr (OP != kOpPoisson) ld_win<K>(ta, A, wf);
+      if (src_kind == kInterp) {
+        double cr[K / 2];
+        stage_win<K / 2>(st, tc, cr, wc);
+        interp_from_run<K>(u, cr, g0, n, src, c.gL, c.gR, x);
+      } else {
+        if (src_kind == kRestrict) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) tu[k] = (tp[k].x + tp[k].y) * 0.5;
+        }
+        stage_win<K>(st, tu, u, wf);
+      }
+      stage_win<K>(st, tf, Fr, wf);
+      if constexpr (OP != kOpPoisson) stage_win<K>(st, ta, a, wf);
+      else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) a[j] = 0.0;
+      }
+    }
+    const SweepGeom sg = sweep_geom(g0, K, max(wlo, (int64_t)0), min(wlo + tl.wcount, n), n,
+                                    c.gL, c.gR);
+    smooth<K, OP, PREC>(u, Fr, a, sg, ar.nu1, x);
+    store_win<K>(st, u, Uo, wlo, clo, chi);
+    // level l-1 from the runs of level l
+    double u1[K / 2], f1[K / 2], a1[K / 2];
+    if constexpr (OP != kOpPoisson) {
+      coarse_rhs<K, OP>(u, Fr, a, f1, g0, n, x);
+      store_win<K / 2>(st, f1, Qo, wlo >> 1, clo >> 1, chi >> 1);
+    } else {
+      fw_run<K>(Fr, f1, g0, n, x);
+    }
 #pragma unroll
     for (int p = 0; p < K / 2; ++p) {
-      const int64_t J = J0 + p;
-      double em = (p == 0) ? el : e[p - 1];
-      double ep = (p == K / 2 - 1) ? er : e[p + 1];
-      if (J == 0) em = -e[p];
-      if (J == nc - 1) ep = -e[p];
-      u[2 * p] = u[2 * p] + (3.0 * e[p] + em) * 0.25;
-      u[2 * p + 1] = u[2 * p + 1] + (3.0 * e[p] + ep) * 0.25;
+      u1[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
+      a1[p] = (a[2 * p] + a[2 * p + 1]) * 0.5;
     }
+    const int64_t wlo1 = wlo >> 1, g1 = g0 >> 1;
+    const int wcount1 = tl.wcount / 2;
+    const SweepGeom sg1 = sweep_geom(g1, K / 2, max(wlo1, (int64_t)0), min(wlo1 + wcount1, n1),
+                                     n1, c.gL, c.gR);
+    smooth<K / 2, OP, PREC>(u1, f1, a1, sg1, ar.nu1, x);
+    store_win<K / 2>(st, u1, U1, wlo1, clo >> 1, chi >> 1);
+    if constexpr (OP != kOpPoisson) {
+      double q1[K / 4];
+      coarse_rhs<K / 2, OP>(u1, f1, a1, q1, g1, n1, x);
+      store_win<K / 4>(st, q1, Q1, wlo1 >> 1, clo >> 2, chi >> 2);
+    }
+  }
+  __syncthreads();
+}
+
+// Up: level l-1 as up_visit (U^{l-1}, V^{l-2}, F^{l-1}, A^{l-1}; correction
+// and nu2 sweeps) into registers, then level l with that V^{l-1} as its
+// coarse iterate; only V^l is stored (to Vout when given).  Saves writing and
+// reading V^{l-1}.
+template <int K, int OP, int PREC>
+__device__ __forceinline__ void up_visit2(const Ctx& c, const Args& ar, int l, const double* F1,
+                                          const double* F, double* st, Xch& x,
+                                          double* Vout = nullptr) {
+  const int64_t n = c.nl(l), n1 = n >> 1, n2 = n1 >> 1;
+  const double* A = c.A + c.off(l);
+  const double* A1 = c.A + c.off(l - 1);
+  const double* Up = c.U + c.off(l);
+  const double* Up1 = c.U + c.off(l - 1);
+  const double* Vc = c.V + c.off(l - 2);
+  double* Vo = Vout ? Vout : c.V + c.off(l);
+  const Tiling tl = tiling(n, K, ar.halo2);
+  const int64_t first = (tl.ntiles == 1) ? 0 : c.member, stride = (tl.ntiles == 1) ? 1 : c.G;
+  for (int64_t ti = first; ti < tl.ntiles; ti += stride) {
+    const int64_t clo = ti * tl.core, chi = min(clo + tl.core, n);
+    const int64_t wlo = clo - tl.halo;
+    const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
+    const int64_t wlo1 = wlo >> 1, g1 = g0 >> 1;
+    const int wcount1 = tl.wcount / 2;
+    // level l-1
+    double v1[K / 2];
+    {
+      double u[K / 2], Fr[K / 2], a[K / 2], cv[K / 4];
+      double tu[K / 2], tf[K / 2], ta[K / 2], tc[K / 4];
+      const Win wf = make_win(wlo1, wcount1, n1);
+      const Win wc = make_win(wlo1 >> 1, (wcount1 + 1) / 2, n2);
+      ld_win<K / 2>(tu, Up1, wf);
+      ld_win<K / 4>(tc, Vc, wc);
+      ld_win<K / 2>(tf, F1, wf);
+      if constexpr (OP != kOpPoisson) ld_win<K / 2>(ta, A1, wf);
+      stage_win<K / 2>(st, tu, u, wf);
+      stage_win<K / 4>(st, tc, cv, wc);
+      stage_win<K / 2>(st, tf, Fr, wf);
+      if constexpr (OP != kOpPoisson) stage_win<K / 2>(st, ta, a, wf);
+      else {
+#pragma unroll
+        for (int j = 0; j < K / 2; ++j) a[j] = 0.0;
+      }
+      correct_run<K / 2>(u, cv, g1, n2, x);
+      const SweepGeom sg = sweep_geom(g1, K / 2, max(wlo1, (int64_t)0),
+                                      min(wlo1 + wcount1, n1), n1, c.gL, c.gR);
+      smooth<K / 2, OP, PREC>(u, Fr, a, sg, ar.nu2, x);
+#pragma unroll
+      for (int j = 0; j < K / 2; ++j) v1[j] = u[j];
+    }
+    // level l
+    double u[K], Fr[K], a[K];
+    {
+      double tu[K], tf[K], ta[K];
+      const Win wf = make_win(wlo, tl.wcount, n);
+      ld_win<K>(tu, Up, wf);
+      ld_win<K>(tf, F, wf);
+      if constexpr (OP != kOpPoisson) ld_win<K>(ta, A, wf);
+      stage_win<K>(st, tu, u, wf);
+      stage_win<K>(st, tf, Fr, wf);
+      if constexpr (OP != kOpPoisson) stage_win<K>(st, ta, a, wf);
+      else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) a[j] = 0.0;
+      }
+    }
+    correct_run<K>(u, v1, g0, n1, x);
     const SweepGeom sg = sweep_geom(g0, K, max(wlo, (int64_t)0), min(wlo + tl.wcount, n), n,
                                     c.gL, c.gR);
     smooth<K, OP, PREC>(u, Fr, a, sg, ar.nu2, x);
@@ -1031,14 +1220,21 @@ __device__ __forceinline__ void solve_problem(const Ctx& c, const Args& ar, doub
     } else {
       top = t;
     }
-    for (int l = top; l >= 1; --l) {
+    // down leg: two levels per visit from the top, a single one at the bottom
+    for (int l = top; l >= 1;) {
       int sk;
       const double* src;
       if (l == top && !sr) { sk = kInterp; src = c.V + c.off(l - 1); }
       else if (l == top) { sk = kDirect; src = c.Uh; }
       else { sk = kRestrict; src = c.U + c.off(l + 1); }
       const double* F = (l == top && !sr) ? c.R + c.off(l) : Fsrc + c.off(l);
-      if (ph.begin(c, c.nl(l) <= W)) down_visit<K, OP, PREC>(c, ar, l, sk, src, F, st, x);
+      if (l >= 2) {
+        if (ph.begin(c, c.nl(l) <= W)) down_visit2<K, OP, PREC>(c, ar, l, sk, src, F, st, x);
+        l -= 2;
+      } else {
+        if (ph.begin(c, c.nl(l) <= W)) down_visit<K, OP, PREC>(c, ar, l, sk, src, F, st, x);
+        l -= 1;
+      }
     }
     {
       int sk;
@@ -1050,10 +1246,22 @@ __device__ __forceinline__ void solve_problem(const Ctx& c, const Args& ar, doub
       double* out = (sr && top == 0 && c.vk) ? c.vk : c.V;
       if (ph.begin(c, true)) coarse_visit<OP>(c, sk, src, F, c.A, false, out, st, red);
     }
-    for (int l = 1; l <= top; ++l) {
-      const double* F = (l == top && !sr) ? c.R + c.off(l) : Fsrc + c.off(l);
-      double* Vout = (sr && l == top) ? c.vk : nullptr;
-      if (ph.begin(c, c.nl(l) <= W)) up_visit<K, OP, PREC>(c, ar, l, F, st, x, Vout);
+    // up leg: two levels per visit from the bottom (only the upper one's V
+    // is stored), a single one at the top
+    for (int l = 1; l <= top;) {
+      if (l + 1 <= top) {
+        const int h = l + 1;
+        const double* F = (h == top && !sr) ? c.R + c.off(h) : Fsrc + c.off(h);
+        double* Vout = (sr && h == top) ? c.vk : nullptr;
+        if (ph.begin(c, c.nl(h) <= W))
+          up_visit2<K, OP, PREC>(c, ar, h, Fsrc + c.off(l), F, st, x, Vout);
+        l += 2;
+      } else {
+        const double* F = (l == top && !sr) ? c.R + c.off(l) : Fsrc + c.off(l);
+        double* Vout = (sr && l == top) ? c.vk : nullptr;
+        if (ph.begin(c, c.nl(l) <= W)) up_visit<K, OP, PREC>(c, ar, l, F, st, x, Vout);
+        l += 1;
+      }
     }
     // compression only (a kept V^{M-1} and no fine output): no SR up pass
     if (sr && (c.uo || c.gk) && ph.begin(c, false)) sr_up<K, OP, PREC, RB>(c, ar, st, x);
@@ -1170,14 +1378,31 @@ double model_bytes(int64_t n, int64_t n0, int M, bool reaction, bool adjoint,
     return 8.0 * (sb + m * (1.0 + r) + m + 0.5 * m * r);
   };
   auto up = [&](int l) { const double m = nl(l); return 8.0 * (m + 0.5 * m + m * (1.0 + r) + m); };
-  for (int t = 1; t < M; ++t) {
-    for (int l = t; l >= 1; --l) b += down(l, l == t ? 0 : 1);
-    for (int l = 1; l <= t; ++l) b += up(l);
-  }
+  // two-level visits: the lower level of a down pair reads nothing and
+  // writes U (and Q); an up pair reads both levels' U, F, A and the coarse
+  // V below, and writes the upper level's V only
+  auto down2 = [&](int l, int src) { const double m = nl(l - 1); return down(l, src) + 8.0 * (m + 0.5 * m * r); };
+  auto up2 = [&](int h) {
+    const double a = nl(h - 1), m = nl(h);
+    return 8.0 * (0.5 * a + a + a * (1.0 + r) + m + m * (1.0 + r) + m);
+  };
+  auto legs = [&](int top, int src_top) {
+    double s = 0.0;
+    for (int l = top; l >= 1;) {
+      const int src = (l == top) ? src_top : 1;
+      if (l >= 2) { s += down2(l, src); l -= 2; }
+      else { s += down(l, src); l -= 1; }
+    }
+    for (int l = 1; l <= top;) {
+      if (l + 1 <= top) { s += up2(l + 1); l += 2; }
+      else { s += up(l); l += 1; }
+    }
+    return s;
+  };
+  for (int t = 1; t < M; ++t) b += legs(t, 0);
   const double N = (double)n;
   b += 8.0 * (0.5 * N + N * (1.0 + fine_coef) + 0.5 * N + 0.5 * N * r);  // SR down
-  for (int l = M - 1; l >= 1; --l) b += down(l, l == M - 1 ? 2 : 1);
-  for (int l = 1; l <= M - 1; ++l) b += up(l);
+  b += legs(M - 1, 2);
   if (!keep_only) b += 8.0 * (0.5 * N + N * (1.0 + fine_coef) + N + (adjoint ? N : 0.0));  // SR up
   if (rebuild) b += 7.0 * 8.0 * (0.5 * N + 2.0 * N);
   return b;
@@ -1390,6 +1615,7 @@ fmgsr_status execute(fmgsr_batch_s* b, int op, bool adjoint, const double* f, co
   a.nu2 = b->nu2;
   a.buffer = b->buffer;
   a.halo = b->halo;
+  a.halo2 = 4 * b->halo;
   a.region = b->region;
   a.adjoint = adjoint ? 1 : 0;
   a.group = b->group;
