@@ -103,6 +103,19 @@ __device__ __forceinline__ double wave_shift(double v, bool from_left) {
 // compiler from moving the workgroup's LDS accesses across the exchange,
 // which the multi-wavefront barrier also orders.
 // ---------------------------------------------------------------------------
+// Workgroups are dispatched to the chip's 8 XCDs in turn, and each XCD has
+// its own L2.  xcd_block() renumbers the launch so that every XCD takes one
+// contiguous range of block indices, in order: neighbouring tiles or
+// segments, which share halo cells, then meet in one L2 instead of reading
+// the shared cells from HBM twice.  A bijection on [0, gridDim.x) for any
+// grid size.
+__device__ __forceinline__ int64_t xcd_block() {
+  constexpr int64_t kXcds = 8;
+  const int64_t n = gridDim.x, b = blockIdx.x;
+  const int64_t per = n / kXcds, rem = n % kXcds, x = b % kXcds, k = b / kXcds;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
 struct Xch {
   double* buf;  // two halves of `half` doubles (unused in wave mode)
   int sel;

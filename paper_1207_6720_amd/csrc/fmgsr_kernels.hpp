@@ -228,7 +228,7 @@ __device__ void down_level(const VertArgs& a, double* st, Xch& x, double (&u)[K]
 constexpr int64_t kInteriorMargin = 4 << kMaxFuse;  // cells kept from the domain ends
 
 __device__ __forceinline__ int64_t tile_index(const VertArgs& a) {
-  const int64_t b = blockIdx.x;
+  const int64_t b = xcd_block();
   return a.tile0 + b + (b >= a.gap_at ? a.gap : 0);
 }
 
@@ -850,7 +850,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_down(SegArgs a) {
   double* st = sm;                   // W (K+1)
   Xch x{sm + W * (K + 1), 0, 2 * W};        // 4 W
   const int64_t n = a.n, nc = n >> 1;
-  const int64_t seg = blockIdx.x;
+  const int64_t seg = xcd_block();
   const int64_t core_lo = seg * a.s, core_hi = core_lo + a.s;
   const int64_t wlo = core_lo - a.pad;
   const int64_t g0 = wlo + (int64_t)threadIdx.x * K;
@@ -967,7 +967,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
   double* st = sm;
   Xch x{sm + W * (K + 1), 0, 2 * W};
   const int64_t n = a.n, nc = n >> 1;
-  const int64_t seg = a.seg0 + blockIdx.x;
+  const int64_t seg = a.seg0 + xcd_block();
   // cells of this segment's core that are written
   const int64_t wr_lo = seg * a.s > a.out_lo ? seg * a.s : a.out_lo;
   const int64_t wr_hi = (seg + 1) * a.s < a.out_hi ? (seg + 1) * a.s : a.out_hi;
@@ -1014,7 +1014,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
     if (a.out) store_run_at<K>(st, u, wlo, wr_lo, wr_hi, a.out, a.out_lo);
     if (a.part) {
       const int e0 = (int)threadIdx.x * K;
-      segment_sums<K>(u, (int)a.pad - e0, (int)(a.pad + a.s) - e0, st, a.part, blockIdx.x);
+      segment_sums<K>(u, (int)a.pad - e0, (int)(a.pad + a.s) - e0, st, a.part, seg - a.seg0);
     }
     return;
   }
@@ -1045,7 +1045,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr_up(SegArgs a) {
   if (a.part) {
     const int64_t c0 = core_lo - g0, c1 = (core_hi < n ? core_hi : n) - g0;
     segment_sums<K>(u, (int)(c0 < 0 ? 0 : (c0 > K ? K : c0)), (int)(c1 < 0 ? 0 : (c1 > K ? K : c1)),
-                    st, a.part, blockIdx.x);
+                    st, a.part, seg - a.seg0);
   }
 }
 
@@ -1126,7 +1126,7 @@ __device__ void sr2_up_interior(const Seg2Args& a, double* st, Xch& x) {
   constexpr int K1 = K / 2;
   const int W = blockDim.x;
   const int64_t n = a.n, n1 = n >> 1;
-  const int64_t seg = blockIdx.x;
+  const int64_t seg = xcd_block();
   const int64_t s1 = a.s >> 1;
   const int64_t w1lo = seg * s1 - a.p1;
   const int64_t g1 = w1lo + (int64_t)threadIdx.x * K1;
@@ -1210,7 +1210,7 @@ __device__ void sr2_up_interior(const Seg2Args& a, double* st, Xch& x) {
     if (a.out) store_run_fast<K>(st, u, a.out + wlo, (int)a.pad, (int)(a.pad + a.s));
     if (a.part) {
       const int e0 = (int)threadIdx.x * K;
-      segment_sums<K>(u, (int)a.pad - e0, (int)(a.pad + a.s) - e0, st, a.part, blockIdx.x);
+      segment_sums<K>(u, (int)a.pad - e0, (int)(a.pad + a.s) - e0, st, a.part, seg);
     }
   }
 }
@@ -1223,7 +1223,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr2(Seg2Args a) {
   double* st = sm;                   // W (K+1)
   Xch x{sm + W * (K + 1), 0, 2 * W};        // 4 W
   const int64_t n = a.n, n1 = n >> 1, n2 = n >> 2;
-  const int64_t seg = blockIdx.x;
+  const int64_t seg = xcd_block();
   const int64_t s1 = a.s >> 1;
   if constexpr (UP) {
     const int64_t wlo_m = seg * a.s - a.pad;
@@ -1296,7 +1296,7 @@ __global__ __launch_bounds__(kSegMaxThreads) void k_sr2(Seg2Args a) {
     if (a.part) {
       const int64_t c0 = core_lo - g0, c1 = (core_hi < n ? core_hi : n) - g0;
       segment_sums<K>(u, (int)(c0 < 0 ? 0 : (c0 > K ? K : c0)),
-                      (int)(c1 < 0 ? 0 : (c1 > K ? K : c1)), st, a.part, blockIdx.x);
+                      (int)(c1 < 0 ? 0 : (c1 > K ? K : c1)), st, a.part, seg);
     }
   }
 }
