@@ -24,7 +24,10 @@
 //               [Kaczmarz, sweep], core to the output)
 // Stored-level visits walk the level in halo-exact register tiles (every
 // core equals a whole-level sweep); each visit reads arrays it does not
-// write, so the tiles of one visit are independent.
+// write, so the tiles of one visit are independent.  The legs visit the
+// stored levels two at a time (down: from the top; up: from the bottom),
+// the lower level of a pair worked from registers (down_visit2,
+// up_visit2).
 //
 // Smoothing (nonlinear red-black Gauss-Seidel, one Newton step per point):
 //   cubic   u_i <- ((F_i h^2 + (l + r)) + 2 q u_i^3) / (D + 3 q u_i^2)
