@@ -121,7 +121,7 @@ struct Xch {
   int sel;
   int half;     // >= 2 W for two-value exchanges, >= 4 W for four-value ones
   bool wave = false;
-  __device__ void swap(double first, double last, double& left_last, double& right_first) {
+  __device__ __forceinline__ void swap(double first, double last, double& left_last, double& right_first) {
     if (wave) {
       __builtin_amdgcn_wave_barrier();
       left_last = wave_shift(last, true);
@@ -138,7 +138,7 @@ struct Xch {
     right_first = (t + 1 < W) ? b[t + 1] : 0.0;
   }
   // one value only: the left neighbour's `mine` (0 for the first thread)
-  __device__ double from_left(double mine) {
+  __device__ __forceinline__ double from_left(double mine) {
     if (wave) {
       __builtin_amdgcn_wave_barrier();
       return wave_shift(mine, true);
@@ -151,7 +151,7 @@ struct Xch {
     return (t > 0) ? b[t - 1] : 0.0;
   }
   // the right neighbour's `mine` (0 for the last thread)
-  __device__ double from_right(double mine) {
+  __device__ __forceinline__ double from_right(double mine) {
     if (wave) {
       __builtin_amdgcn_wave_barrier();
       return wave_shift(mine, false);
@@ -168,7 +168,7 @@ struct Xch {
   // every thread publishes (first, second, last, extra) and reads its left
   // neighbour's last and its right neighbour's first, second and extra (0 at
   // the workgroup edges).
-  __device__ void swap(double first, double second, double last, double extra, double& l_last,
+  __device__ __forceinline__ void swap(double first, double second, double last, double extra, double& l_last,
                        double& r_first, double& r_second, double& r_extra) {
     if (wave) {
       __builtin_amdgcn_wave_barrier();
@@ -194,7 +194,7 @@ struct Xch {
   }
   // two cells on each side: the left neighbour's last two (l1 = its last)
   // and the right neighbour's first two (r0 = its first)
-  __device__ void swap2(double c0, double c1, double cl1, double cl, double& l2, double& l1,
+  __device__ __forceinline__ void swap2(double c0, double c1, double cl1, double cl, double& l2, double& l1,
                         double& r0, double& r1) {
     if (wave) {
       __builtin_amdgcn_wave_barrier();

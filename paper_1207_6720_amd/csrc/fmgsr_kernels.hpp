@@ -210,10 +210,88 @@ __device__ __forceinline__ TileGeom tile_geom(const VertArgs& a, int i, int K) {
   return g;
 }
 
-template <int K, int I, bool F32>
-__device__ void down_level(const VertArgs& a, double* st, Xch& x, double (&u)[K],
+// Runs of the general path on a level whose run starts and size are
+// multiples of K (uniform per launch): the level's first cell can only be
+// a run's cell 0 and its last cell a run's cell K-1.
+struct EdgeRun {
+  bool b0, bn;      // this run holds the level's first / last cell
+  double fb0, fbn;  // F h^2 of those two cells
+  double gL2, gR2;  // the boundary terms of their closures: 2 gL, 2 gR
+};
+
+// fh = F h^2 / 2 of the run and its EdgeRun (g0: first cell of the run).
+template <int K>
+__device__ __forceinline__ EdgeRun edge_run(const double (&f)[K], double (&fh)[K], int64_t g0,
+                                            int64_t n, double gL, double gR) {
+  const double h2 = 1.0 / ((double)n * (double)n);
+  EdgeRun e;
+  e.b0 = (g0 == 0);
+  e.bn = (g0 + K == n);
+  e.fb0 = f[0] * h2;
+  e.fbn = f[K - 1] * h2;
+  e.gL2 = 2.0 * gL;
+  e.gR2 = 2.0 * gR;
+#pragma unroll
+  for (int j = 0; j < K; ++j) fh[j] = (f[j] * h2) * 0.5;
+  return e;
+}
+
+// nu red-black sweeps over such a run: every cell takes the interior
+// update, then the level's first (red) and last (black) cell are recomputed
+// with their boundary closure (ghost value 2 g - u), in the operation order
+// of the per-cell form, so the level's cells come out bitwise as with it.
+// Cells outside the level and at the window's edges take values from
+// undefined neighbours; as on interior tiles only halo cells depend on them,
+// and the boundary closures read none.
+template <int K>
+__device__ __forceinline__ void rb_sweeps_edge(double (&u)[K], const double (&fh)[K], int nu,
+                                               const EdgeRun& e, Xch& x) {
+  for (int s = 0; s < nu; ++s) {
+    const double ll = x.from_left(u[K - 1]);
+#pragma unroll
+    for (int j = 0; j < K; j += 2) u[j] = __builtin_fma((j == 0 ? ll : u[j - 1]) + u[j + 1], 0.5, fh[j]);
+    if (e.b0) u[0] = (e.fb0 + (e.gL2 + u[1])) / 3.0;
+    const double rf = x.from_right(u[0]);
+#pragma unroll
+    for (int j = 1; j < K; j += 2) u[j] = __builtin_fma(u[j - 1] + (j == K - 1 ? rf : u[j + 1]), 0.5, fh[j]);
+    if (e.bn) u[K - 1] = (e.fbn + (u[K - 2] + e.gR2)) / 3.0;
+  }
+}
+
+// Whether the level's runs start at multiples of K and its size is one
+// (uniform per launch): the general path's FP64 sweeps then take the
+// interior update with two boundary fix-ups (rb_sweeps_edge).
+__device__ __forceinline__ bool edge_aligned(const TileGeom& G, int K) {
+  return G.n % K == 0 && G.wlo % K == 0;
+}
+
+template <int K, int I, bool F32, bool E = false>
+__device__ __forceinline__ void down_level(const VertArgs& a, double* st, Xch& x, double (&u)[K],
                            const double (&f)[K]) {
   const TileGeom G = tile_geom(a, I, K);
+  if constexpr (!F32 && !E) {
+    if (edge_aligned(G, K)) {
+      down_level<K, I, F32, true>(a, st, x, u, f);
+      return;
+    }
+  }
+  if constexpr (E) {
+    double f1[K / 2], fh[K];
+    const bool more = (I + 1 < kMaxFuse && K >= 4) && (I + 1 < a.levels);
+    if (more) restrict_rhs_run<K>(f, f1, G.g0, G.n, x);
+    const EdgeRun e = edge_run<K>(f, fh, G.g0, G.n, a.gL, a.gR);
+    rb_sweeps_edge<K>(u, fh, a.nu, e, x);
+    if (a.out[I]) store_run<K>(st, u, G.wlo, G.clo, G.chi, a.out[I]);  // null: SR level
+    if constexpr (I + 1 < kMaxFuse && K >= 4) {
+      if (more) {
+        double u1[K / 2];
+#pragma unroll
+        for (int p = 0; p < K / 2; ++p) u1[p] = (u[2 * p] + u[2 * p + 1]) * 0.5;
+        down_level<K / 2, I + 1, F32>(a, st, x, u1, f1);
+      }
+    }
+    return;
+  }
   smooth_general<K, F32>(u, f, G.g0, a.nu, G.lo, G.hi, G.n, a.gL, a.gR, x);
   if (a.out[I]) store_run<K>(st, u, G.wlo, G.clo, G.chi, a.out[I]);  // null: SR level
   if constexpr (I + 1 < kMaxFuse && K >= 4) {
@@ -248,7 +326,7 @@ __device__ __forceinline__ bool deep_skips(const VertArgs& a, int I, int64_t wlo
 }
 
 template <int K, int I, bool F32>
-__device__ void down_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4, double (&u)[K],
+__device__ __forceinline__ void down_level_fast(const VertArgs& a, double* st, Xch& x, Xch4& x4, double (&u)[K],
                                 double (&f)[K], int64_t wlo0) {
   const int64_t wlo = wlo0 >> I;
   double f1[K / 2];
@@ -415,10 +493,16 @@ __global__ __launch_bounds__(T, OCC) void k_down(VertArgs a) {
 
 // Up leg, level I of the kernel (I = 0 is the top).  On entry f holds this
 // level's right-hand side; on return u holds its post-smoothed iterate.
-template <int K, int I, bool F32>
-__device__ void up_level(const VertArgs& a, double* st, Xch& x, const double (&f)[K],
+template <int K, int I, bool F32, bool E = false>
+__device__ __forceinline__ void up_level(const VertArgs& a, double* st, Xch& x, const double (&f)[K],
                          double (&u)[K]) {
   const TileGeom G = tile_geom(a, I, K);
+  if constexpr (!F32 && !E) {
+    if (edge_aligned(G, K)) {
+      up_level<K, I, F32, true>(a, st, x, f, u);
+      return;
+    }
+  }
   const int wcount = (int)blockDim.x * K;
   const int64_t nc = G.n >> 1;
   double c[K / 2];  // post-smoothed coarse iterate of this run's pairs
@@ -474,6 +558,9 @@ __device__ void up_level(const VertArgs& a, double* st, Xch& x, const double (&f
     return;
   }
   // correction (Eq. 4): u = pre + P(c - I^ pre)
+  double fh[E ? K : 1];
+  EdgeRun eg{};
+  if constexpr (E) eg = edge_run<K>(f, fh, G.g0, G.n, a.gL, a.gR);
   bool rebuilt = false;
   if constexpr (I == 0) {
     if (a.src) {
@@ -481,7 +568,8 @@ __device__ void up_level(const VertArgs& a, double* st, Xch& x, const double (&f
       // it in the same window; its stale edge cells stay outside the core's
       // reach
       load_interp_run<K>(st, u, G.wlo, wcount, G.n, a.src, a.gL, a.gR, x);
-      smooth_general<K, F32>(u, f, G.g0, a.nu_pre, G.lo, G.hi, G.n, a.gL, a.gR, x);
+      if constexpr (E) rb_sweeps_edge<K>(u, fh, a.nu_pre, eg, x);
+      else smooth_general<K, F32>(u, f, G.g0, a.nu_pre, G.lo, G.hi, G.n, a.gL, a.gR, x);
       rebuilt = true;
     }
   }
@@ -503,7 +591,8 @@ __device__ void up_level(const VertArgs& a, double* st, Xch& x, const double (&f
       u[2 * p + 1] = u[2 * p + 1] + (3.0 * eJ + ep) * 0.25;
     }
   }
-  smooth_general<K, F32>(u, f, G.g0, a.nu, G.lo, G.hi, G.n, a.gL, a.gR, x);
+  if constexpr (E) rb_sweeps_edge<K>(u, fh, a.nu, eg, x);
+  else smooth_general<K, F32>(u, f, G.g0, a.nu, G.lo, G.hi, G.n, a.gL, a.gR, x);
 }
 
 // Interior runs, fh = F h^2 / 2 of the level, c = its post-smoothed coarse
