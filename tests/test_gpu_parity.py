@@ -112,6 +112,13 @@ CASES = [
     (1 << 22, 23, 1024, 8, (1, 1), 1, "split", (0.0, 0.0), 44),
     (1 << 22, 23, 1, 0, (3, 2), 0, "split", (0.2, -0.3), 45),
     (5 << 20, 21, 1280, 8, (2, 1), 1, "split", (0.0, 0.0), 46),
+    # coarse core on one wavefront: N0 a power of two, one to five levels
+    # above the level of 64 cells (N0 = 64: the exact solve is one
+    # wavefront's cyclic reduction)
+    (1 << 12, 11, 8, 4, (2, 1), 1, "split", (0.1, -0.3), 60),   # N0 = 4
+    (1 << 13, 8, 4, 4, (2, 1), 1, "split", (0.0, 0.0), 61),     # N0 = 64
+    (1 << 8, 4, 2, 2, (2, 1), 1, "split", (0.0, 0.0), 62),      # N0 = 32, one run level
+    (1 << 11, 11, 4, 4, (3, 2), 0, "split", (0.2, 0.1), 63),    # N0 = 2
 ]
 
 
