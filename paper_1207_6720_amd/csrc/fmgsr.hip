@@ -382,13 +382,13 @@ size_t plan_bytes(const Plan& p) {
 }
 
 // Dynamic LDS (bytes) of one workgroup of each kernel that takes it: the
-// coarse core holds its level stack (iterates, right-hand sides, correction)
-// and the cyclic-reduction buffers; the segment kernels a stage of K + 1 and
-// an exchange of 4 doubles per thread.
+// coarse core holds its level stack (iterates, right-hand sides, correction),
+// the cyclic-reduction buffers and the sweeps' second buffer (level C); the
+// segment kernels a stage of K + 1 and an exchange of 4 doubles per thread.
 size_t core_lds(const Plan& p) {
   const int64_t ntot = p.n0 * (((int64_t)1 << (p.C + 1)) - 1);
   const int64_t esz = (p.C > 0) ? (p.n0 << (p.C - 1)) : 0;
-  return (size_t)(2 * ntot + esz + 8 * p.n0) * sizeof(double);
+  return (size_t)(2 * ntot + esz + 8 * p.n0 + (p.n0 << p.C)) * sizeof(double);
 }
 size_t seg_lds(int threads) { return (size_t)threads * (kSegRun + 1 + 4) * sizeof(double); }
 

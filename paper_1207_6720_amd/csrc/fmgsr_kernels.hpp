@@ -1463,36 +1463,44 @@ struct CoreArgs {
 
 __device__ __forceinline__ int lvl_off(int n0, int l) { return n0 * ((1 << l) - 1); }
 
-// One red-black sweep of a level (n cells) in LDS.  A thread owns the
-// pairs (2J, 2J+1), J = tid + k T, in both colours, so at its black update
-// it holds the pair's final values and can also produce, in the same phase,
+// One red-black sweep of a level of n cells (n even) in LDS, in one phase:
+// the thread that owns the pairs (2J, 2J+1), J = tid + k T, reads the old
+// iterate from src and writes the new one to dst, a separate buffer, so no
+// barrier separates the colours.  Its black cell's right neighbour, the
+// next pair's red cell, is recomputed here from the same operands its owner
+// uses, so dst is bitwise the result of the red then black half-sweeps.
+// With the pair's final values the same phase can also produce
 //   rc:  I^ of the level (the next coarser level's start, n/2 cells), and
 //   e:   the correction e = u - I^ ufine of this level (ufine: the finer
 //        level's pre-smoothed iterate), read by the next finer level.
-__device__ __forceinline__ void core_rb(double* u, const double* q, int n, double gL2, double gR2,
-                                        double* rc = nullptr, double* e = nullptr,
-                                        const double* ufine = nullptr) {
+__device__ __forceinline__ void core_sweep(const double* src, double* dst, const double* q, int n,
+                                           double gL2, double gR2, double* rc = nullptr,
+                                           double* e = nullptr, const double* ufine = nullptr) {
   const double h2 = 1.0 / ((double)n * (double)n);
   const double bdiv = (n == 1) ? 4.0 : 3.0;
 #pragma unroll 1
-  for (int colour = 0; colour < 2; ++colour) {
-#pragma unroll 1
-    for (int i = 2 * (int)threadIdx.x + colour; i < n; i += 2 * (int)blockDim.x) {
-      double l = (i > 0) ? u[i - 1] : gL2;
-      double r = (i < n - 1) ? u[i + 1] : gR2;
-      const double num = q[i] * h2 + (l + r);
-      const double v = (i > 0 && i < n - 1) ? num * 0.5 : num / bdiv;
-      u[i] = v;
-      if (colour == 1) {  // i = 2J + 1; l is the pair's red cell u[2J]
-        if (rc) rc[i >> 1] = (l + v) * 0.5;
-        if (e) {
-          e[i - 1] = l - (ufine[2 * (i - 1)] + ufine[2 * (i - 1) + 1]) * 0.5;
-          e[i] = v - (ufine[2 * i] + ufine[2 * i + 1]) * 0.5;
-        }
-      }
+  for (int J = threadIdx.x; 2 * J < n; J += blockDim.x) {
+    const int i0 = 2 * J, i1 = i0 + 1;
+    const double lft = (i0 > 0) ? src[i0 - 1] : gL2;
+    const double b_old = src[i1];
+    const double num0 = q[i0] * h2 + (lft + b_old);
+    const double r0 = (i0 > 0) ? num0 * 0.5 : num0 / bdiv;
+    double rgt = gR2;
+    if (i1 < n - 1) {  // the next pair's red cell, an interior cell
+      const double num2 = q[i0 + 2] * h2 + (b_old + src[i0 + 3]);
+      rgt = num2 * 0.5;
     }
-    __syncthreads();
+    const double num1 = q[i1] * h2 + (r0 + rgt);
+    const double b1 = (i1 < n - 1) ? num1 * 0.5 : num1 / bdiv;
+    dst[i0] = r0;
+    dst[i1] = b1;
+    if (rc) rc[J] = (r0 + b1) * 0.5;
+    if (e) {
+      e[i0] = r0 - (ufine[2 * i0] + ufine[2 * i0 + 1]) * 0.5;
+      e[i1] = b1 - (ufine[2 * i1] + ufine[2 * i1 + 1]) * 0.5;
+    }
   }
+  __syncthreads();
 }
 
 // Levels of at most 64 cells run on the first wavefront alone, one cell per
@@ -1602,6 +1610,7 @@ __global__ __launch_bounds__(kCoreThreads) void k_coarse_core(CoreArgs a) {
   double* E = Q + ntot;           // coarse error of the correction
   const int esz = (C > 0) ? (n0 << (C - 1)) : 0;
   double* PA = E + esz;           // parallel cyclic reduction, two buffers
+  double* TMP = PA + 8 * n0;      // the sweeps' second buffer (level C's size)
   const double gL = a.gL, gR = a.gR, gL2 = 2.0 * gL, gR2 = 2.0 * gR;
   const int nC = n0 << C;
   int lw = -1;  // last level of at most 64 cells (first-wavefront levels)
@@ -1674,11 +1683,20 @@ __global__ __launch_bounds__(kCoreThreads) void k_coarse_core(CoreArgs a) {
       double* qf = Q + lvl_off(n0, m);
       double* uc = U + lvl_off(n0, m - 1);
       double* qc = Q + lvl_off(n0, m - 1);
-      // split tau: the last sweep also restricts (one phase less)
+      // nu1 sweeps alternating between the level and TMP (an odd count
+      // ends with a copy back); split tau: the last sweep also restricts
       const bool fused = !a.literal && a.nu1 > 0;
 #pragma unroll 1
-      for (int s = 0; s < a.nu1; ++s)
-        core_rb(uf, qf, nm, gL2, gR2, (fused && s == a.nu1 - 1) ? uc : nullptr);
+      for (int s = 0; s < a.nu1; ++s) {
+        const bool even = (s % 2 == 0);
+        core_sweep(even ? uf : TMP, even ? TMP : uf, qf, nm, gL2, gR2,
+                   (fused && s == a.nu1 - 1) ? uc : nullptr);
+      }
+      if (a.nu1 % 2 == 1) {
+#pragma unroll 1
+        for (int i = tid; i < nm; i += T) uf[i] = TMP[i];
+        __syncthreads();
+      }
       if (fused) continue;
       const double w = (double)nm * (double)nm, wc = (double)nc * (double)nc;
 #pragma unroll 1
@@ -1804,21 +1822,27 @@ __global__ __launch_bounds__(kCoreThreads) void k_coarse_core(CoreArgs a) {
         for (int J = tid; J < nc; J += T) E[J] = uc[J] - (uf[2 * J] + uf[2 * J + 1]) * 0.5;
         __syncthreads();
       }
+      // the corrected iterate goes to the buffer from which the nu2 sweeps,
+      // alternating, end in the level
+      double* cd = (a.nu2 % 2 == 1) ? TMP : uf;
+      double* co = (a.nu2 % 2 == 1) ? uf : TMP;
 #pragma unroll 1
       for (int J = tid; J < nc; J += T) {
         const double eJ = E[J];
         const double em = (J > 0) ? E[J - 1] : -eJ;
         const double ep = (J < nc - 1) ? E[J + 1] : -eJ;
-        uf[2 * J] = uf[2 * J] + (3.0 * eJ + em) * 0.25;
-        uf[2 * J + 1] = uf[2 * J + 1] + (3.0 * eJ + ep) * 0.25;
+        cd[2 * J] = uf[2 * J] + (3.0 * eJ + em) * 0.25;
+        cd[2 * J + 1] = uf[2 * J + 1] + (3.0 * eJ + ep) * 0.25;
       }
       __syncthreads();
       // the last sweep also forms the next level's e (level m+1 against m+2)
       const bool next_e = (m + 1 < t) && a.nu2 > 0;
 #pragma unroll 1
-      for (int s = 0; s < a.nu2; ++s)
-        core_rb(uf, Q + lvl_off(n0, m + 1), nf, gL2, gR2, nullptr,
-                (next_e && s == a.nu2 - 1) ? E : nullptr, U + lvl_off(n0, m + 2));
+      for (int s = 0; s < a.nu2; ++s) {
+        const bool even = (s % 2 == 0);
+        core_sweep(even ? cd : co, even ? co : cd, Q + lvl_off(n0, m + 1), nf, gL2, gR2, nullptr,
+                   (next_e && s == a.nu2 - 1) ? E : nullptr, U + lvl_off(n0, m + 2));
+      }
       have_e = next_e;
     }
   }

@@ -182,17 +182,17 @@ def test_launch_lds_fits_the_grant_for_every_geometry():
     LDS (MI355X: 160 KiB) less its own static LDS (a few hundred bytes at
     most); a solve checks each request against its kernel's grant before
     enqueuing.  The coarse core's request is its level stack: iterates and
-    right-hand sides of levels 0..C, the correction buffer of level C-1 and
-    8 N0 doubles of cyclic reduction; the segment kernels take 13 doubles
-    per thread."""
+    right-hand sides of levels 0..C, the correction buffer of level C-1, 8
+    N0 doubles of cyclic reduction and the sweeps' second buffer (level C);
+    the segment kernels take 13 doubles per thread."""
     grant = 160 * 1024 - 1024
     # N0 = 1: core levels up to 2048 cells (C = 11)
     ntot, esz = 4095, 1024
-    assert F.launch_lds_bytes(1 << 28, 29, 1 << 16, 8) == (2 * ntot + esz + 8) * 8
+    assert F.launch_lds_bytes(1 << 28, 29, 1 << 16, 8) == (2 * ntot + esz + 8 + 2048) * 8
     # the largest coarsest grid (N0 = 1024): the core takes levels 0 and 1
     # when a level lies above them (the finest level is never in the core)
-    assert F.launch_lds_bytes(4096, 3, 1, 0, sr_levels=0) == (2 * 3072 + 1024 + 8 * 1024) * 8
-    assert F.launch_lds_bytes(2048, 2, 1, 0, sr_levels=0) == (2 * 1024 + 8 * 1024) * 8
+    assert F.launch_lds_bytes(4096, 3, 1, 0, sr_levels=0) == (2 * 3072 + 1024 + 8 * 1024 + 2048) * 8
+    assert F.launch_lds_bytes(2048, 2, 1, 0, sr_levels=0) == (2 * 1024 + 8 * 1024 + 1024) * 8
     # widest segment window: 1024 threads of 8 cells
     s = 8160  # + 2 x 10 pad cells: 1023 runs of 8
     assert F.launch_lds_bytes(8 * s, 9, 8, 8) == max(1024 * 13 * 8,
